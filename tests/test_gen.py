@@ -1,0 +1,52 @@
+"""Synthetic input generators: reproducible, simple, sized as requested."""
+import numpy as np
+
+import graphgen
+
+
+def _simple(n, s, d):
+    assert s.dtype == np.int32 and d.dtype == np.int32
+    assert (s < d).all() and (s >= 0).all() and (d < n).all()
+    k = graphgen.keys_of(s, d)
+    assert np.unique(k).size == k.size
+
+
+def test_er_exact_and_reproducible():
+    s1, d1 = graphgen.er_graph(10_000, 50_000, graphgen.rng_for("er"))
+    s2, d2 = graphgen.er_graph(10_000, 50_000, graphgen.rng_for("er"))
+    assert s1.size == 50_000
+    assert np.array_equal(s1, s2) and np.array_equal(d1, d2)
+    _simple(10_000, s1, d1)
+
+
+def test_chung_lu_shape():
+    n, m = 20_000, 100_000
+    s, d = graphgen.chung_lu_graph(n, m, 2.1, 1000.0, graphgen.rng_for("cl"))
+    assert s.size == m
+    _simple(n, s, d)
+    deg = np.bincount(np.concatenate([s, d]), minlength=n)
+    assert deg.max() > 20 * (2 * m / n)  # heavy tail
+    assert deg.max() <= 1000 * 1.5
+
+
+def test_rmat_shape():
+    n, s, d = graphgen.rmat_graph(12, 16, graphgen.rng_for("rmat"))
+    assert n == 4096
+    _simple(n, s, d)
+    assert 0.5 * 16 * n < s.size <= 16 * n
+
+
+def test_update_streams():
+    rng = graphgen.rng_for("upd")
+    s, d = graphgen.er_graph(1000, 4000, rng)
+    es = graphgen.EdgeSet(s, d)
+    a, b = graphgen.uniform_non_edges(1000, 500, es, rng)
+    k = graphgen.keys_of(a, b)
+    assert np.unique(k).size == 500 and not es.contains(k).any() and (a != b).all()
+    a, b = graphgen.weighted_non_edges(300, es, rng)
+    assert not es.contains(graphgen.keys_of(a, b)).any()
+    a, b = graphgen.existing_edges(700, es, rng)
+    assert es.contains(graphgen.keys_of(a, b)).all()
+    assert np.unique(graphgen.keys_of(a, b)).size == 700
+    sz = graphgen.log_uniform_sizes(1000, 1000, 1_000_000, rng)
+    assert sz.min() >= 1000 and sz.max() <= 1_000_000

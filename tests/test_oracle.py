@@ -1,0 +1,226 @@
+"""Pins of the CPU oracle against facts fixed outside it: the definition
+(brute force), an independent library (networkx), closed forms, and
+hand-derived fixtures.  CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen
+from tests.golden import cases as golden
+
+
+def _nx_cores(n, s, d):
+    nx = pytest.importorskip("networkx")
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from(zip(s.tolist(), d.tolist()))
+    c = nx.core_number(G)
+    return np.asarray([c[v] for v in range(n)], dtype=np.int32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_all_labelled_graphs_small(oracle_mod, n):
+    for s, d in oracle_mod.all_graphs(n):
+        b = oracle_mod.brute_cores(n, s, d)
+        z = oracle_mod.bz_cores(n, s, d)
+        p = oracle_mod.peel_cores(n, s, d)
+        assert np.array_equal(b, z), (s, d, b, z)
+        assert np.array_equal(b, p), (s, d, b, p)
+
+
+def test_random_tiny_graphs_brute(oracle_mod):
+    rng = np.random.default_rng(1)
+    for _ in range(40):
+        n = int(rng.integers(6, 13))
+        pairs = list(itertools.combinations(range(n), 2))
+        keep = rng.random(len(pairs)) < rng.uniform(0.1, 0.7)
+        s = np.asarray([p[0] for p, k in zip(pairs, keep) if k], dtype=np.int32)
+        d = np.asarray([p[1] for p, k in zip(pairs, keep) if k], dtype=np.int32)
+        assert np.array_equal(oracle_mod.brute_cores(n, s, d), oracle_mod.bz_cores(n, s, d))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bz_vs_networkx(oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    n = 2000
+    for gen in ("er", "cl"):
+        if gen == "er":
+            s, d = graphgen.er_graph(n, 8000, rng)
+        else:
+            s, d = graphgen.chung_lu_graph(n, 10000, 2.1, 300.0, rng)
+        assert np.array_equal(_nx_cores(n, s, d), oracle_mod.bz_cores(n, s, d))
+        assert np.array_equal(oracle_mod.peel_cores(n, s, d), oracle_mod.bz_cores(n, s, d))
+
+
+def _edges(pairs):
+    return (np.asarray([a for a, _ in pairs], dtype=np.int32),
+            np.asarray([b for _, b in pairs], dtype=np.int32))
+
+
+def test_closed_forms(oracle_mod):
+    bz = oracle_mod.bz_cores
+    # complete graph K_n -> n-1
+    for n in (2, 3, 7, 20):
+        s, d = _edges(list(itertools.combinations(range(n), 2)))
+        assert (bz(n, s, d) == n - 1).all()
+    # cycle C_n -> 2
+    for n in (3, 10, 101):
+        s, d = _edges([(i, (i + 1) % n) for i in range(n)])
+        assert (bz(n, s, d) == 2).all()
+    # random tree (plus isolated vertices) -> 1 (isolated -> 0)
+    rng = np.random.default_rng(3)
+    n = 500
+    s, d = _edges([(int(rng.integers(0, i)), i) for i in range(1, 400)])
+    c = bz(n, s, d)
+    assert (c[:400] == 1).all() and (c[400:] == 0).all()
+    # complete bipartite K_{a,b} -> min(a, b)
+    for a, b in ((1, 5), (3, 4), (6, 6), (2, 9)):
+        s, d = _edges([(i, a + j) for i in range(a) for j in range(b)])
+        assert (bz(a + b, s, d) == min(a, b)).all()
+    # Petersen graph (3-regular) -> 3
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    s, d = _edges(outer + spokes + inner)
+    assert (bz(10, s, d) == 3).all()
+    # wheel with r >= 4 rim vertices -> 3
+    for r in (4, 5, 12):
+        s, d = _edges([(0, i) for i in range(1, r + 1)] +
+                      [(i, i % r + 1) for i in range(1, r + 1)])
+        assert (bz(r + 1, s, d) == 3).all()
+    # grid P_a x P_b -> 2
+    a, b = 7, 9
+    pairs = []
+    for i in range(a):
+        for j in range(b):
+            v = i * b + j
+            if j + 1 < b:
+                pairs.append((v, v + 1))
+            if i + 1 < a:
+                pairs.append((v, v + b))
+    s, d = _edges(pairs)
+    assert (bz(a * b, s, d) == 2).all()
+    # empty graph -> 0 ; dead ids -> -1
+    e = np.empty(0, dtype=np.int32)
+    assert (bz(9, e, e) == 0).all()
+    alive = np.ones(9, dtype=np.uint8)
+    alive[[2, 5]] = 0
+    c = bz(9, e, e, alive)
+    assert c[2] == -1 and c[5] == -1 and c[0] == 0
+
+
+@pytest.mark.parametrize("name", golden.all_cases())
+def test_golden_fixtures_oracle(oracle_mod, name):
+    case = golden.load(name)
+    g = oracle_mod.DynamicGraph(case["n"], *case["edges"])
+    assert np.array_equal(g.cores(), case["cores"])
+    for kind, s, d, want in case["steps"]:
+        st = (g.insert_edges if kind == "insert" else g.delete_edges)(s, d)[0]
+        assert st == oracle_mod.OK
+        assert np.array_equal(g.cores(), want), (name, kind)
+
+
+def test_theta_threshold_reading(oracle_mod):
+    """The paper's algorithms (method model) with the cd < k test reproduce the
+    hand-derived theta fixture; the lemma's "SD <= k" reading does not."""
+    from oracle import method
+    case = golden.load("theta_delete.txt")
+    kind, s, d, want = case["steps"][0]
+    for le, ok in ((False, True), (True, False)):
+        G = method.graph_from_edges(case["n"], *case["edges"])
+        core = {v: int(c) for v, c in enumerate(case["cores"])}
+        method.delete_edges(G, core, list(zip(s.tolist(), d.tolist())), threshold_le=le)
+        got = np.asarray([core[v] for v in range(case["n"])], dtype=np.int32)
+        assert np.array_equal(got, want) == ok
+
+
+def _random_graph(rng, n, p):
+    pairs = [pq for pq in itertools.combinations(range(n), 2) if rng.random() < p]
+    return pairs
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_method_model_matches_definition(oracle_mod, seed):
+    """The paper's iterative method (Algorithms 1-7, with the readings in
+    oracle.method) ends at the from-scratch core numbers after every batch;
+    after every iteration each core moved by at most one (Section IV-A lemmas
+    on superior edge sets) and equals the decomposition of the graph so far."""
+    from oracle import method
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(25):
+        n = int(rng.integers(5, 16))
+        pairs = _random_graph(rng, n, rng.uniform(0.1, 0.5))
+        all_pairs = list(itertools.combinations(range(n), 2))
+        absent = [p for p in all_pairs if p not in set(pairs)]
+        rng.shuffle(absent)
+        ins = absent[: int(rng.integers(0, len(absent) + 1))]
+        s, d = _edges(pairs) if pairs else (np.empty(0, np.int32), np.empty(0, np.int32))
+        G = method.graph_from_edges(n, s, d)
+        core = {v: int(c) for v, c in enumerate(oracle_mod.bz_cores(n, s, d))}
+        trace = []
+        prev = dict(core)
+        method.insert_edges(G, core, ins, trace=trace)
+        cur_pairs = set(pairs)
+        for chosen, snap in trace:
+            cur_pairs |= set(chosen)
+            cs, cd_ = _edges(sorted(cur_pairs))
+            ref = oracle_mod.bz_cores(n, cs, cd_)
+            assert all(snap[v] == ref[v] for v in range(n))
+            assert all(0 <= snap[v] - prev[v] <= 1 for v in range(n))
+            prev = snap
+        # delete a random subset of the current edges
+        cur = sorted(cur_pairs)
+        rng.shuffle(cur)
+        dels = cur[: int(rng.integers(0, len(cur) + 1))]
+        trace = []
+        prev = dict(core)
+        method.delete_edges(G, core, dels, trace=trace)
+        for chosen, snap in trace:
+            cur_pairs -= set(chosen)
+            cs, cd_ = _edges(sorted(cur_pairs)) if cur_pairs else (np.empty(0, np.int32),) * 2
+            ref = oracle_mod.bz_cores(n, cs, cd_)
+            assert all(snap[v] == ref[v] for v in range(n))
+            assert all(0 <= prev[v] - snap[v] <= 1 for v in range(n))
+            prev = snap
+
+
+def test_superior_set_definition_and_literal_alg2(oracle_mod):
+    """Every selected set satisfies the k-superior edge set definition; the
+    literal per-vertex pick of Algorithm 2 can violate it (two edges at one
+    core-k vertex), which is why the selection reading is needed."""
+    from oracle import method
+    core = {0: 2, 1: 2, 2: 2, 3: 5}
+    edges = [(0, 1), (1, 2), (2, 3)]
+    chosen, rest = method.superior_edge_set(edges, core)
+    for (u, v) in chosen:
+        k = min(core[u], core[v])
+        for (a, b) in chosen:
+            if (a, b) == (u, v):
+                continue
+            shared = {u, v} & {a, b}
+            assert all(core[x] > k for x in shared)
+    # literal Algorithm 2: vertex 0 picks <0,1>, vertex 1 picks <1,2>:
+    # vertex 1 (core 2) then holds two edges of core number 2.
+    literal = [(0, 1), (1, 2)]
+    shared = {0, 1} & {1, 2}
+    assert any(core[x] == 2 for x in shared) and len(literal) == 2
+
+
+def test_dynamic_graph_validation(oracle_mod):
+    g = oracle_mod.DynamicGraph(5, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    E = oracle_mod
+    err = g.validate(np.array([0, 9, 3, 2, 3, 1, 4]), np.array([1, 0, 3, 3, 2, 0, 0]), True)
+    assert err.tolist() == [E.E_EXISTS, E.E_RANGE, E.E_SELF_LOOP, 0, E.E_DUP, E.E_DUP, 0]
+    err = g.validate(np.array([0, 2, 3]), np.array([1, 1, 4]), False)
+    assert err.tolist() == [0, 0, E.E_MISSING]
+    st, fb, applied = g.insert_edges(np.array([3, 3]), np.array([4, 3]), strict=True)
+    assert (st, fb, applied) == (E.E_SELF_LOOP, 1, 0) and g.num_edges() == 2
+    st, fb, applied = g.insert_edges(np.array([3, 3]), np.array([4, 3]), strict=False)
+    assert (st, applied) == (E.OK, 1) and g.num_edges() == 3
+    st, fb = g.delete_vertices(np.array([1, 1]))
+    assert st == E.E_DUP and fb == 1
+    st, fb = g.delete_vertices(np.array([1]))
+    assert st == E.OK and g.cores()[1] == -1 and g.num_edges() == 1
+    st, fb, first = g.insert_vertices(np.array([0, 2]), np.array([3, 4]))
+    assert st == E.OK and first == 5 and g.cores()[5] == 2
