@@ -1,0 +1,183 @@
+/*
+ * coremaint.h -- C ABI of libcoremaint.so: batched core maintenance of a
+ * dynamic undirected graph on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Parallel Algorithms for Core Maintenance in Dynamic Graphs"
+ * (Wang, Yu, Jin, Qian, Xie, Hua).  A batch of inserted (deleted) edges is
+ * processed in iterations; each iteration selects a superior edge set
+ * (Section IV, definition of the k-superior edge set), applies it to the
+ * graph, finds for every core level k in parallel the core-k vertices whose
+ * core number moves (Algorithms 3-4 for insertion, 6-7 for deletion) and
+ * moves them by exactly one (Algorithms 1 and 5).  Vertex insertion and
+ * deletion reduce to edge insertion and deletion (Introduction).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every call returns an int; CM_OK (0) on success, a negative
+ *   CM_E_* code otherwise.  No C++ exception crosses this boundary.
+ *   cm_last_error(g) gives a text message for the last failure on g.
+ * - Ids: vertices are dense int32 ids in [0, n_ids).  Deleted ids stay dead
+ *   (core reported as -1) and are never reused; inserted vertices receive
+ *   fresh ids n_ids, n_ids+1, ...
+ * - Edges: an undirected edge is given once, in either orientation; pairs
+ *   are canonicalised to (min, max).  The graph stays simple.
+ * - Batch validation (strict mode, the default): an item is invalid when an
+ *   endpoint is outside [0, n_ids) (CM_E_RANGE), an endpoint is dead
+ *   (CM_E_DEAD), it is a self-loop (CM_E_SELF_LOOP), its pair occurred at an
+ *   earlier index of the same batch (CM_E_DUP), or for insertion the edge
+ *   already exists (CM_E_EXISTS) / for deletion it does not (CM_E_MISSING);
+ *   checks apply in that order.  A batch with any invalid item is rejected
+ *   as a whole, the graph is left unchanged, the call returns the code of
+ *   the smallest invalid index and stats->first_bad holds that index.
+ *   Filter mode (cm_config.strict = 0) drops invalid items, counts them in
+ *   stats->dropped and applies the rest.
+ * - Memory: `on_device` = 1 means the pointer is device memory of the
+ *   current HIP device (e.g. a torch tensor's data_ptr), 0 means host memory.
+ *   Inputs are borrowed for the duration of the call; outputs are
+ *   caller-allocated.  Every call has returned only after the work it
+ *   enqueued on the handle's stream has completed.
+ * - Threading: one call at a time per handle.
+ * - Core numbers are exact int32 values: after every successful update call
+ *   they equal the core numbers of the updated graph (core number
+ *   definition, Section III).
+ */
+#ifndef COREMAINT_H
+#define COREMAINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CM_OK 0
+#define CM_E_ARG (-1)       /* bad argument (null pointer, negative size, bad mode) */
+#define CM_E_RANGE (-2)     /* vertex id outside [0, n_ids) */
+#define CM_E_SELF_LOOP (-3) /* edge <v, v> */
+#define CM_E_DUP (-4)       /* pair (or id) repeated inside one batch */
+#define CM_E_EXISTS (-5)    /* inserted edge already in the graph */
+#define CM_E_MISSING (-6)   /* deleted edge not in the graph */
+#define CM_E_DEAD (-7)      /* id of a deleted vertex */
+#define CM_E_NOMEM (-8)     /* device or host allocation failed */
+#define CM_E_CAPACITY (-9)  /* configured vertex capacity exceeded */
+#define CM_E_STATE (-10)    /* call not valid in the handle's state (e.g. no graph loaded) */
+#define CM_E_DEVICE (-11)   /* HIP runtime error; the handle is poisoned */
+#define CM_E_INTERNAL (-12) /* internal invariant violated (queue overflow); handle poisoned */
+
+/* Execution forms of the update path. */
+#define CM_MODE_PLAIN 0     /* host loop: one cooperative launch per superior edge set */
+#define CM_MODE_PERSISTENT 1 /* one cooperative launch loops over all sets of the batch */
+
+typedef struct cm_graph cm_graph; /* opaque; owned by the library */
+
+typedef struct cm_config {
+    int32_t vertex_capacity;    /* max vertex ids over the handle's lifetime; 0 = auto (grows) */
+    int64_t edge_capacity_hint; /* adjacency slots to reserve up front; 0 = auto */
+    int32_t strict;             /* 1 = reject an invalid batch whole (default), 0 = drop items */
+    int32_t mode;               /* CM_MODE_PLAIN or CM_MODE_PERSISTENT */
+    int32_t partition_rounds;   /* selection rounds per superior edge set (1..8; 0 = default) */
+    int32_t blocks_per_cu;      /* cooperative grid occupancy (0 = default) */
+    int32_t small_degree;       /* lists up to this length are walked by one lane (0 = default) */
+    int32_t large_degree;       /* lists above this length are split into chunks (0 = default) */
+    int32_t chunk;              /* chunk length for long lists (0 = default) */
+    int32_t timing;             /* 1 = time each maintenance launch with HIP events */
+    void *stream;               /* hipStream_t to run on; NULL = the null stream */
+} cm_config;
+
+typedef struct cm_batch_stats {
+    int32_t status;         /* same value the call returned */
+    int32_t iterations;     /* superior edge sets processed */
+    int64_t first_bad;      /* smallest invalid item index, -1 if none */
+    int64_t applied;        /* edges applied to the graph */
+    int64_t dropped;        /* invalid items dropped (filter mode) */
+    int64_t remaining_sum;  /* sum over iterations of edges still to place (partition work) */
+    int64_t candidates;     /* sum over iterations of candidate vertices visited */
+    int64_t evicted;        /* sum of evicted (insert) / peeled (delete) vertices */
+    int64_t changed;        /* sum of vertices whose core moved */
+    int64_t scanned;        /* adjacency entries read by traversal phases */
+    int64_t alg_bytes;      /* algorithmic HBM bytes of the maintenance launches */
+    int32_t launches;       /* maintenance kernel launches */
+    int32_t pad0;
+    double kernel_ms;       /* summed HIP-event time of those launches (timing = 1) */
+    double ms_total;        /* wall time of the call */
+} cm_batch_stats;
+
+/* Fill *cfg with defaults (strict, plain mode, auto capacities, null stream). */
+void cm_config_default(cm_config *cfg);
+
+/* Create an empty handle on the current HIP device.  cfg may be NULL. */
+int cm_create(const cm_config *cfg, cm_graph **out);
+
+/* Release every device and host resource of g.  g may be NULL. */
+void cm_destroy(cm_graph *g);
+
+/* Text for a status code. */
+const char *cm_strerror(int status);
+
+/* Message of the last failing call on g (empty if none). */
+const char *cm_last_error(const cm_graph *g);
+
+/* Load the simple graph G = (V, E) with V = [0, n) and E given as m pairs
+ * (src[i], dst[i]) (problem definition, Section III).  Replaces any graph
+ * already held.  Pairs must be distinct and loop-free: CM_E_RANGE,
+ * CM_E_SELF_LOOP or CM_E_DUP otherwise (graph left empty).  Core numbers
+ * are not computed until cm_core_decompose. */
+int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src,
+                  const int32_t *dst, int on_device);
+
+/* Initial state: core number of every vertex (core number definition,
+ * Section III) by parallel level-synchronous peeling on the device, plus
+ * each vertex's superior degree SD (Section IV-B definition).  stats may
+ * be NULL (only ms_total, scanned, kernel_ms are filled). */
+int cm_core_decompose(cm_graph *g, cm_batch_stats *stats);
+
+/* Incremental core maintenance (Section V): insert s edges, then bring every
+ * core number up to date.  stats may be NULL. */
+int cm_insert_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst,
+                    int on_device, cm_batch_stats *stats);
+
+/* Decremental core maintenance (Section VI): delete s edges, then bring
+ * every core number up to date.  stats may be NULL. */
+int cm_delete_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst,
+                    int on_device, cm_batch_stats *stats);
+
+/* Vertex insertion (Introduction: a new vertex enters with core 0, then its
+ * edges are inserted).  c new vertices get ids first..first+c-1 where
+ * first = n_ids on entry (*first_new_id receives it, may be NULL).  Vertex i
+ * is joined to nbrs[off[i] .. off[i+1]); off has c+1 entries starting at 0.
+ * Neighbours may be live ids or ids of this call's new vertices; an edge
+ * between two new vertices is listed once.  Invalid items are reported by
+ * their index in nbrs (validation convention above); in strict mode no
+ * vertex is created on error. */
+int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs,
+                       int on_device, int32_t *first_new_id, cm_batch_stats *stats);
+
+/* Vertex deletion (Introduction: the vertex's edges are deleted, then the
+ * vertex).  ids must be live, in range and distinct (CM_E_DEAD, CM_E_RANGE,
+ * CM_E_DUP, index in stats->first_bad).  Deleted ids report core -1. */
+int cm_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int on_device,
+                       cm_batch_stats *stats);
+
+/* Copy the core numbers of ids [0, n) to out (n <= n_ids; dead ids -> -1). */
+int cm_get_cores(cm_graph *g, int32_t *out, int32_t n, int on_device);
+
+/* Current id count (live + dead) and live vertex count. */
+int cm_num_vertices(cm_graph *g, int32_t *n_ids, int32_t *n_alive);
+
+/* Current number of undirected edges. */
+int cm_num_edges(cm_graph *g, int64_t *m);
+
+/* Export the edge set: every undirected edge once as (min, max), in no
+ * particular order, into caller buffers of capacity cap; *m_out receives
+ * the edge count (CM_E_ARG if cap is too small, *m_out still set). */
+int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap,
+                    int64_t *m_out, int on_device);
+
+/* Copy the maintained superior degree SD(v) (Section IV-B definition) of
+ * ids [0, n) to out; dead ids report 0. */
+int cm_get_superior_degrees(cm_graph *g, int32_t *out, int32_t n, int on_device);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COREMAINT_H */

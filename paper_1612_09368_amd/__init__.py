@@ -1,0 +1,287 @@
+"""Python binding of libcoremaint (batched core maintenance on MI355X).
+
+Argument marshalling only: every step of the maintenance path runs in the HIP
+kernels of ``libcoremaint.so``; this module passes pointers and sizes through
+the C ABI declared in ``include/coremaint.h``.  Arrays may be torch tensors
+(device tensors are passed as device pointers, CPU tensors as host pointers)
+or numpy arrays (host).  PyTorch is used only for device memory and streams.
+
+The library must have been built (``python -m paper_1612_09368_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcoremaint.so")
+
+OK = 0
+E_ARG, E_RANGE, E_SELF_LOOP, E_DUP, E_EXISTS, E_MISSING, E_DEAD = -1, -2, -3, -4, -5, -6, -7
+E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL = -8, -9, -10, -11, -12
+MODE_PLAIN, MODE_PERSISTENT = 0, 1
+
+EXPORTED = [
+    "cm_config_default", "cm_create", "cm_destroy", "cm_strerror", "cm_last_error",
+    "cm_load_graph", "cm_core_decompose", "cm_insert_edges", "cm_delete_edges",
+    "cm_insert_vertices", "cm_delete_vertices", "cm_get_cores", "cm_num_vertices",
+    "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("vertex_capacity", ctypes.c_int32),
+        ("edge_capacity_hint", ctypes.c_int64),
+        ("strict", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("partition_rounds", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32),
+        ("small_degree", ctypes.c_int32),
+        ("large_degree", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("first_bad", ctypes.c_int64),
+        ("applied", ctypes.c_int64),
+        ("dropped", ctypes.c_int64),
+        ("remaining_sum", ctypes.c_int64),
+        ("candidates", ctypes.c_int64),
+        ("evicted", ctypes.c_int64),
+        ("changed", ctypes.c_int64),
+        ("scanned", ctypes.c_int64),
+        ("alg_bytes", ctypes.c_int64),
+        ("launches", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("kernel_ms", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad0"}
+
+
+class CoreMaintError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """Load libcoremaint.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1612_09368_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "cm_config_default": (None, [P]),
+        "cm_create": (ctypes.c_int, [P, P]),
+        "cm_destroy": (None, [P]),
+        "cm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "cm_last_error": (ctypes.c_char_p, [P]),
+        "cm_load_graph": (ctypes.c_int, [P, I32, I64, P, P, ctypes.c_int]),
+        "cm_core_decompose": (ctypes.c_int, [P, P]),
+        "cm_insert_edges": (ctypes.c_int, [P, I64, P, P, ctypes.c_int, P]),
+        "cm_delete_edges": (ctypes.c_int, [P, I64, P, P, ctypes.c_int, P]),
+        "cm_insert_vertices": (ctypes.c_int, [P, I32, P, P, ctypes.c_int, P, P]),
+        "cm_delete_vertices": (ctypes.c_int, [P, I32, P, ctypes.c_int, P]),
+        "cm_get_cores": (ctypes.c_int, [P, P, I32, ctypes.c_int]),
+        "cm_num_vertices": (ctypes.c_int, [P, P, P]),
+        "cm_num_edges": (ctypes.c_int, [P, P]),
+        "cm_export_edges": (ctypes.c_int, [P, P, P, I64, P, ctypes.c_int]),
+        "cm_get_superior_degrees": (ctypes.c_int, [P, P, I32, ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(x, dtype):
+    """(pointer, on_device, keepalive, length) for a torch tensor or array."""
+    if x is None:
+        return None, 0, None, 0
+    mod = type(x).__module__
+    if mod.startswith("torch"):
+        torch = _torch()
+        want = {np.int32: torch.int32, np.int64: torch.int64}[dtype]
+        if x.dtype != want:
+            x = x.to(want)
+        x = x.contiguous()
+        return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda), x, x.numel()
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return ctypes.c_void_p(a.ctypes.data), 0, a, a.size
+
+
+def default_stream():
+    try:
+        torch = _torch()
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return ctypes.c_void_p(0)
+
+
+class Graph:
+    """A dynamic graph held on the GPU with exact core numbers."""
+
+    def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
+                 partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
+                 timing=False, stream=None):
+        lib = library()
+        cfg = Config()
+        lib.cm_config_default(ctypes.byref(cfg))
+        cfg.mode = mode
+        cfg.strict = 1 if strict else 0
+        cfg.vertex_capacity = vertex_capacity
+        cfg.edge_capacity_hint = edge_capacity_hint
+        cfg.partition_rounds = partition_rounds
+        cfg.blocks_per_cu = blocks_per_cu
+        cfg.small_degree = small_degree
+        cfg.large_degree = large_degree
+        cfg.chunk = chunk
+        cfg.timing = 1 if timing else 0
+        cfg.stream = stream if stream is not None else default_stream()
+        h = ctypes.c_void_p()
+        st = lib.cm_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != OK:
+            raise CoreMaintError(st, "cm_create: " + lib.cm_strerror(st).decode())
+        self._lib = lib
+        self._h = h
+        self.config = cfg
+        self.last_stats = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers --------------------------------------------------------
+    def _check(self, st, what):
+        if st != OK:
+            msg = self._lib.cm_last_error(self._h).decode() or self._lib.cm_strerror(st).decode()
+            raise CoreMaintError(st, f"{what}: {msg}")
+
+    def _call_stats(self, fn, *args, check=True, what=""):
+        stats = BatchStats()
+        st = fn(self._h, *args, ctypes.byref(stats))
+        self.last_stats = stats
+        if check:
+            self._check(st, what)
+        return st, stats
+
+    # -- API ------------------------------------------------------------
+    def load(self, n, src, dst):
+        ps, ds, ks, m = _ptr(src, np.int32)
+        pd, dd, kd, m2 = _ptr(dst, np.int32)
+        if m != m2 or ds != dd:
+            raise ValueError("src and dst must have the same length and location")
+        self._check(self._lib.cm_load_graph(self._h, int(n), m, ps, pd, ds), "cm_load_graph")
+
+    def decompose(self):
+        return self._call_stats(self._lib.cm_core_decompose, what="cm_core_decompose")[1]
+
+    def _edges(self, fn, src, dst, check, what):
+        ps, ds, ks, m = _ptr(src, np.int32)
+        pd, dd, kd, m2 = _ptr(dst, np.int32)
+        if m != m2 or ds != dd:
+            raise ValueError("src and dst must have the same length and location")
+        st, stats = self._call_stats(fn, m, ps, pd, ds, check=check, what=what)
+        return stats if check else (st, stats)
+
+    def insert_edges(self, src, dst, check=True):
+        return self._edges(self._lib.cm_insert_edges, src, dst, check, "cm_insert_edges")
+
+    def delete_edges(self, src, dst, check=True):
+        return self._edges(self._lib.cm_delete_edges, src, dst, check, "cm_delete_edges")
+
+    def insert_vertices(self, off, nbrs, check=True):
+        po, do, ko, c1 = _ptr(off, np.int64)
+        pn, dn, kn, _ = _ptr(nbrs, np.int32)
+        first = ctypes.c_int32(-1)
+        st, stats = self._call_stats(self._lib.cm_insert_vertices, c1 - 1, po, pn, do,
+                                     ctypes.byref(first), check=check, what="cm_insert_vertices")
+        return (first.value, stats) if check else (st, first.value, stats)
+
+    def delete_vertices(self, ids, check=True):
+        pi, di, ki, c = _ptr(ids, np.int32)
+        st, stats = self._call_stats(self._lib.cm_delete_vertices, c, pi, di, check=check,
+                                     what="cm_delete_vertices")
+        return stats if check else (st, stats)
+
+    def num_vertices(self):
+        n = ctypes.c_int32()
+        a = ctypes.c_int32()
+        self._check(self._lib.cm_num_vertices(self._h, ctypes.byref(n), ctypes.byref(a)), "cm_num_vertices")
+        return n.value, a.value
+
+    def num_edges(self):
+        m = ctypes.c_int64()
+        self._check(self._lib.cm_num_edges(self._h, ctypes.byref(m)), "cm_num_edges")
+        return m.value
+
+    def cores(self, out=None):
+        """Core numbers of every id (dead ids -1).  Returns a numpy array,
+        or fills `out` (a torch int32 tensor, device or host) and returns it."""
+        n, _ = self.num_vertices()
+        if out is None:
+            arr = np.empty(n, dtype=np.int32)
+            self._check(self._lib.cm_get_cores(self._h, ctypes.c_void_p(arr.ctypes.data), n, 0),
+                        "cm_get_cores")
+            return arr
+        p, dev, keep, cnt = _ptr(out, np.int32)
+        self._check(self._lib.cm_get_cores(self._h, p, min(n, cnt), dev), "cm_get_cores")
+        return out
+
+    def superior_degrees(self):
+        n, _ = self.num_vertices()
+        arr = np.empty(n, dtype=np.int32)
+        self._check(self._lib.cm_get_superior_degrees(self._h, ctypes.c_void_p(arr.ctypes.data), n, 0),
+                    "cm_get_superior_degrees")
+        return arr
+
+    def export_edges(self):
+        m = self.num_edges()
+        s = np.empty(max(m, 1), dtype=np.int32)
+        d = np.empty(max(m, 1), dtype=np.int32)
+        got = ctypes.c_int64()
+        self._check(self._lib.cm_export_edges(self._h, ctypes.c_void_p(s.ctypes.data),
+                                              ctypes.c_void_p(d.ctypes.data), m, ctypes.byref(got), 0),
+                    "cm_export_edges")
+        return s[:got.value], d[:got.value]

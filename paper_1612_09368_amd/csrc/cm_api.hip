@@ -1,0 +1,1045 @@
+// C ABI of libcoremaint: host orchestration of the device graph store, the
+// initial decomposition and the batched maintenance drivers.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/coremaint.h"
+#include "cm_launch.h"
+
+using namespace cm;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct cm_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    cm_config cfg{};
+    Tune tune{};
+    int num_cu = 0;
+    int coop_maint = 0;   // cooperative grid of the maintenance kernel
+    int coop_dec = 0;     // cooperative grid of the decomposition kernel
+    int grid_reg = 0;     // grid of regular grid-stride kernels
+
+    DevGraph g{};
+    DevBatch b{};
+    DevQueues q{};
+    Ctl *ctl = nullptr;       // device
+    Ctl *hctl = nullptr;      // pinned host mirror
+    int32_t batch_cap = 0;    // capacity of batch arrays
+    int32_t hash_cap = 0;     // allocated hash slots
+    int32_t scan_cap = 0;
+    int32_t *src_buf = nullptr, *dst_buf = nullptr;  // device staging of host inputs
+    int64_t *scan_tmp = nullptr;
+    int64_t scan_tmp_cap = 0;
+    int64_t *i64_scratch = nullptr;   // small device scratch (totals)
+    unsigned long long *u64_scratch = nullptr;
+    unsigned long long *hu64 = nullptr;  // pinned host scratch
+    int32_t *firstidx = nullptr;      // [n_cap] vertex-deletion duplicate check
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    bool loaded = false;
+    bool decomposed = false;
+    bool poisoned = false;
+    int64_t m = 0;
+    int32_t n_alive = 0;
+    int32_t epoch = 0;
+    int32_t bstamp = 0;
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Fail {
+    int code;
+};
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            g->poisoned = true;                                                        \
+            g->err = std::string("HIP error ") + hipGetErrorString(_e) + " at " #expr; \
+            throw Fail{CM_E_DEVICE};                                                   \
+        }                                                                              \
+    } while (0)
+
+template <class T>
+void dev_alloc(cm_graph *g, T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        g->err = "device allocation of " + std::to_string(sizeof(T) * (size_t)count) + " bytes failed";
+        throw Fail{CM_E_NOMEM};
+    }
+}
+
+template <class T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+KArgs make_args(cm_graph *g) {
+    KArgs a{};
+    a.g = g->g;
+    a.b = g->b;
+    a.q = g->q;
+    a.t = g->tune;
+    a.ctl = g->ctl;
+    return a;
+}
+
+void sync_ctl(cm_graph *g) {
+    HIPCHK(hipMemcpyAsync(g->hctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+}
+
+void check_overflow(cm_graph *g) {
+    if (g->hctl->overflow) {
+        g->poisoned = true;
+        g->err = "internal queue overflow (code " + std::to_string(g->hctl->overflow) + ")";
+        throw Fail{CM_E_INTERNAL};
+    }
+}
+
+// Per-vertex arrays (re)allocation to n_cap ids, keeping the first n_keep.
+void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
+    DevGraph ng = g->g;
+    ng.n_cap = n_cap;
+    hipStream_t st = g->stream;
+    auto grow32 = [&](int32_t *&dst, int32_t *old, int32_t fillv) {
+        dev_alloc(g, &dst, n_cap);
+        HIPCHK(fill_i32(dst, fillv, n_cap, st));
+        if (old && n_keep > 0)
+            HIPCHK(hipMemcpyAsync(dst, old, sizeof(int32_t) * (size_t)n_keep, hipMemcpyDeviceToDevice, st));
+    };
+    grow32(ng.len, g->g.len, 0);
+    grow32(ng.cap, g->g.cap, 0);
+    grow32(ng.core, g->g.core, -1);
+    grow32(ng.mcd, g->g.mcd, 0);
+    grow32(ng.stamp, g->g.stamp, 0);
+    grow32(ng.chg, g->g.chg, 0);
+    grow32(ng.cd, g->g.cd, 0);
+    grow32(ng.dec, g->g.dec, 0);
+    grow32(ng.done, g->g.done, 0);
+    grow32((int32_t *&)ng.matched, (int32_t *)g->g.matched, 0);
+    grow32(ng.bmark, g->g.bmark, 0);
+    grow32(ng.gain, g->g.gain, 0);
+    dev_alloc(g, &ng.off, n_cap);
+    HIPCHK(fill_i64(ng.off, 0, n_cap, st));
+    if (g->g.off && n_keep > 0)
+        HIPCHK(hipMemcpyAsync(ng.off, g->g.off, sizeof(int64_t) * (size_t)n_keep, hipMemcpyDeviceToDevice, st));
+    dev_alloc(g, &ng.claim, n_cap);
+    HIPCHK(fill_u64(ng.claim, ~0ull, n_cap, st));
+    if (g->g.claim && n_keep > 0)
+        HIPCHK(hipMemcpyAsync(ng.claim, g->g.claim, sizeof(unsigned long long) * (size_t)n_keep,
+                              hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    DevGraph old = g->g;
+    dev_free(old.len); dev_free(old.cap); dev_free(old.core); dev_free(old.mcd);
+    dev_free(old.stamp); dev_free(old.chg); dev_free(old.cd); dev_free(old.dec);
+    dev_free(old.done); dev_free(old.matched); dev_free(old.bmark); dev_free(old.gain);
+    dev_free(old.off); dev_free(old.claim);
+    ng.nbr = g->g.nbr;
+    ng.pool_size = g->g.pool_size;
+    ng.n_ids = g->g.n_ids;
+    g->g = ng;
+
+    // vertex-sized batch / queue arrays
+    dev_free(g->b.vlist); dev_free(g->b.reloc); dev_free(g->b.reloc_off); dev_free(g->b.reloc_cap);
+    dev_alloc(g, &g->b.vlist, n_cap);
+    dev_alloc(g, &g->b.reloc, n_cap);
+    dev_alloc(g, &g->b.reloc_off, n_cap);
+    dev_alloc(g, &g->b.reloc_cap, n_cap);
+    for (int i = 0; i < 2; ++i) {
+        dev_free(g->q.fq[i]); dev_free(g->q.eq[i]);
+        dev_alloc(g, &g->q.fq[i], n_cap);
+        dev_alloc(g, &g->q.eq[i], n_cap);
+    }
+    dev_free(g->q.cand); dev_free(g->q.chg); dev_free(g->q.touched);
+    dev_alloc(g, &g->q.cand, n_cap);
+    dev_alloc(g, &g->q.chg, n_cap);
+    dev_alloc(g, &g->q.touched, n_cap);
+    g->q.vcap = n_cap;
+    dev_free(g->firstidx);
+    dev_alloc(g, &g->firstidx, n_cap);
+    HIPCHK(fill_i32(g->firstidx, INT_MAX, n_cap, st));
+    int64_t need_tmp = scan_tmp_len(n_cap);
+    if (need_tmp > g->scan_tmp_cap) {
+        dev_free(g->scan_tmp);
+        dev_alloc(g, &g->scan_tmp, need_tmp);
+        g->scan_tmp_cap = need_tmp;
+    }
+}
+
+// Chunk queues sized for n_cap + pool/chunk items.
+void alloc_chunk_queues(cm_graph *g) {
+    int64_t h = (int64_t)g->g.n_cap + g->g.pool_size / std::max(1, g->tune.chunk) + 1024;
+    if (h > INT_MAX) h = INT_MAX;
+    if (h <= g->q.hcap) return;
+    for (int i = 0; i < 2; ++i) {
+        dev_free(g->q.fh[i]); dev_free(g->q.fx[i]); dev_free(g->q.eh[i]);
+        dev_alloc(g, &g->q.fh[i], h);
+        dev_alloc(g, &g->q.fx[i], h);
+        dev_alloc(g, &g->q.eh[i], h);
+    }
+    dev_free(g->q.chh);
+    dev_alloc(g, &g->q.chh, h);
+    g->q.hcap = (int32_t)h;
+}
+
+void ensure_vertex_capacity(cm_graph *g, int64_t need) {
+    if (need <= g->g.n_cap) return;
+    if (g->cfg.vertex_capacity > 0 && need > g->cfg.vertex_capacity) {
+        g->err = "vertex capacity exceeded";
+        throw Fail{CM_E_CAPACITY};
+    }
+    if (need > INT_MAX - 1) {
+        g->err = "vertex ids exceed int32";
+        throw Fail{CM_E_CAPACITY};
+    }
+    int64_t nc = std::max<int64_t>(need, (int64_t)g->g.n_cap + g->g.n_cap / 2 + 1024);
+    if (g->cfg.vertex_capacity > 0) nc = std::min<int64_t>(nc, g->cfg.vertex_capacity);
+    nc = std::min<int64_t>(nc, INT_MAX - 1);
+    alloc_vertex_arrays(g, (int32_t)nc, g->g.n_ids);
+    alloc_chunk_queues(g);
+}
+
+void ensure_batch(cm_graph *g, int64_t s) {
+    if (s > INT_MAX / 2) {
+        g->err = "batch too large";
+        throw Fail{CM_E_ARG};
+    }
+    if (s > g->batch_cap) {
+        int64_t c = std::max<int64_t>(s, 1024);
+        DevBatch &b = g->b;
+        dev_free(b.err); dev_free(b.eu); dev_free(b.ev); dev_free(b.su); dev_free(b.sv);
+        dev_free(b.hslot); dev_free(b.rem[0]); dev_free(b.rem[1]); dev_free(b.sel); dev_free(b.esel);
+        dev_free(g->src_buf); dev_free(g->dst_buf);
+        dev_alloc(g, &b.err, c); dev_alloc(g, &b.eu, c); dev_alloc(g, &b.ev, c);
+        dev_alloc(g, &b.su, c); dev_alloc(g, &b.sv, c); dev_alloc(g, &b.hslot, c);
+        dev_alloc(g, &b.rem[0], c); dev_alloc(g, &b.rem[1], c); dev_alloc(g, &b.sel, c);
+        dev_alloc(g, &b.esel, c);
+        HIPCHK(fill_i32(b.esel, 0, c, g->stream));
+        dev_alloc(g, &g->src_buf, c); dev_alloc(g, &g->dst_buf, c);
+        b.cap = (int32_t)c;
+        g->batch_cap = (int32_t)c;
+    }
+    int64_t hc = next_pow2(std::max<int64_t>(2 * s, 1024));
+    if (hc > g->hash_cap) {
+        dev_free(g->b.hkey); dev_free(g->b.hval);
+        dev_alloc(g, &g->b.hkey, hc);
+        dev_alloc(g, &g->b.hval, hc);
+        g->hash_cap = (int32_t)hc;
+    }
+    g->b.hcap = (int32_t)hc;
+    HIPCHK(fill_u64(g->b.hkey, ~0ull, hc, g->stream));
+    HIPCHK(fill_i32(g->b.hval, INT_MAX, hc, g->stream));
+    int64_t sc = 2 * s + (int64_t)(g->hctl->pool_tail / (unsigned long long)std::max(1, g->tune.chunk)) + 1024;
+    sc = std::min<int64_t>(sc, INT_MAX);
+    if (sc > g->scan_cap) {
+        dev_free(g->b.scanq);
+        dev_alloc(g, &g->b.scanq, sc);
+        g->scan_cap = (int32_t)sc;
+    }
+    g->b.scap = g->scan_cap;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Build (or rebuild) the adjacency pool so that every live list gets slack;
+// lists keep their order, tombstones are dropped.  extra = slots to add to
+// the pool beyond the packed size.
+void repack(cm_graph *g, int64_t extra) {
+    hipStream_t st = g->stream;
+    KArgs a = make_args(g);
+    int32_t *cnt = g->g.gain;  // gain is zero between batches; used as scratch here
+    HIPCHK(count_live(a, cnt, g->grid_reg, st));
+    int64_t *caps64 = nullptr, *newoff = nullptr;
+    dev_alloc(g, &caps64, g->g.n_cap);
+    dev_alloc(g, &newoff, g->g.n_cap);
+    HIPCHK(caps_from_counts(cnt, g->g.n_ids, g->g.n_cap, caps64, g->g.cap, st));
+    HIPCHK(exclusive_scan_i64(caps64, newoff, g->g.n_cap, g->scan_tmp, g->i64_scratch, st));
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, g->i64_scratch, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t pool = total + std::max<int64_t>(extra, total / 4) + 4096;
+    if (g->cfg.edge_capacity_hint > pool) pool = g->cfg.edge_capacity_hint;
+    int32_t *newnbr = nullptr;
+    dev_alloc(g, &newnbr, pool);
+    HIPCHK(repack_copy(a, newoff, newnbr, g->grid_reg, st));
+    HIPCHK(repack_finish(a, newoff, cnt, g->grid_reg, st));
+    HIPCHK(fill_i32(cnt, 0, g->g.n_cap, st));
+    HIPCHK(hipStreamSynchronize(st));
+    dev_free(caps64);
+    dev_free(newoff);
+    dev_free(g->g.nbr);
+    g->g.nbr = newnbr;
+    g->g.pool_size = pool;
+    unsigned long long tail = (unsigned long long)total;
+    unsigned long long zero = 0;
+    HIPCHK(hipMemcpyAsync(&g->ctl->pool_tail, &tail, sizeof(tail), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(&g->ctl->garbage, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    g->hctl->pool_tail = tail;
+    g->hctl->garbage = 0;
+    alloc_chunk_queues(g);
+}
+
+int finish(cm_graph *g, int code, cm_batch_stats *stats, double t0) {
+    if (stats) {
+        stats->status = code;
+        stats->ms_total = now_ms() - t0;
+    }
+    if (code == CM_OK) g->err.clear();
+    return code;
+}
+
+void fill_stats(cm_graph *g, cm_batch_stats *st, int64_t applied, int64_t dropped, int64_t first_bad) {
+    if (!st) return;
+    const Ctl &c = *g->hctl;
+    st->iterations = (int32_t)c.st_iters;
+    st->first_bad = first_bad;
+    st->applied = applied;
+    st->dropped = dropped;
+    st->remaining_sum = (int64_t)c.st_remaining;
+    st->candidates = (int64_t)c.st_candidates;
+    st->evicted = (int64_t)c.st_evicted;
+    st->changed = (int64_t)c.st_changed;
+    st->scanned = (int64_t)c.st_scanned;
+}
+
+// Algorithmic bytes of the maintenance launches of a batch: what the method
+// must read or write, counted once per access (no cache effects):
+//  partition, per remaining edge and claim round: edge index 4 + endpoints 8
+//    + two core gathers 8 + claim atomics 16 (claim and select passes) = 36
+//  apply, per selected edge: list append or tombstone 2x(4+8) + SD update 8 = 32
+//  traversal, per adjacency entry read: id 4 + core 4 + SD/counter 4 = 12
+//  per candidate / changed vertex: list offset and length 12 + counter 4 = 16
+int64_t alg_bytes(const Ctl &c, int rounds) {
+    return (int64_t)(36ull * c.st_remaining * (unsigned long long)rounds + 32ull * c.st_selected +
+                     12ull * c.st_scanned + 16ull * (c.st_candidates + c.st_changed));
+}
+
+// Validate a batch already staged in g->b.src_in/dst_in (s items).  Returns
+// the number of valid items; in strict mode throws on the first bad item.
+int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *first_bad,
+                 int cur) {
+    hipStream_t st = g->stream;
+    g->bstamp += 2;
+    HIPCHK(ctl_batch_reset(g->ctl, cur, st));
+    KArgs a = make_args(g);
+    a.inserting = inserting ? 1 : 0;
+    a.s = (int32_t)s;
+    a.bstamp = g->bstamp;
+    a.cur = cur;
+    HIPCHK(validate_batch(a, g->grid_reg, st));
+    sync_ctl(g);
+    check_overflow(g);
+    int32_t fb = g->hctl->first_bad;
+    *first_bad = fb == INT_MAX ? -1 : fb;
+    if (fb != INT_MAX && strict) {
+        int32_t code = 0;
+        HIPCHK(hipMemcpyAsync(&code, g->b.err + fb, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        g->err = std::string("invalid batch item ") + std::to_string(fb) + ": " + cm_strerror(code);
+        throw Fail{code};
+    }
+    return g->hctl->rem_count[cur];
+}
+
+// Make room for an insertion batch (validated list `cur`) before any
+// mutation: lists that cannot take their new edges move to spill blocks;
+// if the pool is full it is repacked into a larger one and the step redone.
+void reserve(cm_graph *g, int cur) {
+    hipStream_t st = g->stream;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        KArgs a = make_args(g);
+        a.inserting = 1;
+        a.bstamp = g->bstamp;
+        a.cur = cur;
+        // clear counters used by the reservation (keep validation results)
+        int32_t zero = 0;
+        HIPCHK(hipMemcpyAsync(&g->ctl->vlist_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(&g->ctl->reloc_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(&g->ctl->pool_fail, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        HIPCHK(reserve_gain(a, g->grid_reg, st));
+        HIPCHK(reserve_alloc_copy(a, g->grid_reg, st));
+        sync_ctl(g);
+        check_overflow(g);
+        if (!g->hctl->pool_fail) return;
+        // pool exhausted: repack with room for this batch, then redo
+        int64_t extra = 4 * (int64_t)g->hctl->rem_count[cur] + (int64_t)g->g.pool_size / 2;
+        repack(g, extra);
+        g->bstamp += 2;
+    }
+    g->err = "adjacency pool could not be grown";
+    throw Fail{CM_E_NOMEM};
+}
+
+// Run the iterations of a validated batch (list `cur`) to completion.
+void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
+    hipStream_t st = g->stream;
+    KArgs a = make_args(g);
+    a.inserting = inserting ? 1 : 0;
+    a.max_iters = g->cfg.mode == CM_MODE_PERSISTENT ? INT_MAX : 1;
+    double kms = 0.0;
+    int launches = 0;
+    for (;;) {
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
+        HIPCHK(maintain_coop(a, g->coop_maint, st));
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
+        ++launches;
+        sync_ctl(g);
+        check_overflow(g);
+        if (g->cfg.timing) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+            kms += ms;
+        }
+        g->epoch = g->hctl->epoch;
+        int nxt = (g->epoch + 1) & 1;
+        if (g->hctl->rem_count[nxt] == 0) break;
+        if (g->hctl->iters_done == 0) {
+            g->poisoned = true;
+            g->err = "maintenance launch made no progress";
+            throw Fail{CM_E_INTERNAL};
+        }
+    }
+    if (stats) {
+        stats->launches = launches;
+        stats->kernel_ms = kms;
+        stats->alg_bytes = alg_bytes(*g->hctl, g->tune.rounds);
+    }
+}
+
+// Shared body of edge insertion / deletion on staged device inputs.
+int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats, int64_t *dropped,
+                   bool strict_override, bool strict_value) {
+    hipStream_t st = g->stream;
+    bool strict = strict_override ? strict_value : g->cfg.strict != 0;
+    int cur = (g->epoch + 1) & 1;
+    int64_t fb = -1;
+    int64_t valid = validate(g, s, inserting, strict, &fb, cur);
+    *dropped = s - valid;
+    if (stats) stats->first_bad = fb;
+    if (valid == 0) {
+        if (stats) fill_stats(g, stats, 0, *dropped, fb);
+        return 0;
+    }
+    KArgs a = make_args(g);
+    a.inserting = inserting ? 1 : 0;
+    a.cur = cur;
+    if (inserting) {
+        reserve(g, cur);
+    } else {
+        int32_t zero = 0;
+        HIPCHK(hipMemcpyAsync(&g->ctl->vlist_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        a.bstamp = g->bstamp;
+        HIPCHK(reserve_gain(a, g->grid_reg, st));  // endpoints + tombstone counts
+    }
+    run_maintenance(g, inserting, stats);
+    if (!inserting) {
+        KArgs c = make_args(g);
+        HIPCHK(delete_compact(c, g->grid_reg, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    // statistics of the whole batch are in the mirror read by the last sync
+    sync_ctl(g);
+    if (stats) {
+        int32_t launches = stats->launches;
+        double kms = stats->kernel_ms;
+        int64_t ab = stats->alg_bytes;
+        fill_stats(g, stats, valid, *dropped, fb);
+        stats->launches = launches;
+        stats->kernel_ms = kms;
+        stats->alg_bytes = ab;
+    }
+    g->m += inserting ? valid : -valid;
+    return valid;
+}
+
+void stage_inputs(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device) {
+    if (on_device) {
+        g->b.src_in = const_cast<int32_t *>(src);
+        g->b.dst_in = const_cast<int32_t *>(dst);
+    } else {
+        HIPCHK(hipMemcpyAsync(g->src_buf, src, sizeof(int32_t) * (size_t)s, hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->dst_buf, dst, sizeof(int32_t) * (size_t)s, hipMemcpyHostToDevice, g->stream));
+        g->b.src_in = g->src_buf;
+        g->b.dst_in = g->dst_buf;
+    }
+}
+
+void require_ready(cm_graph *g, bool need_cores) {
+    if (g->poisoned) {
+        throw Fail{CM_E_DEVICE};
+    }
+    if (!g->loaded || (need_cores && !g->decomposed)) {
+        g->err = need_cores ? "no decomposed graph (call cm_load_graph and cm_core_decompose)"
+                            : "no graph loaded";
+        throw Fail{CM_E_STATE};
+    }
+}
+
+void release_all(cm_graph *g) {
+    DevGraph &d = g->g;
+    dev_free(d.off); dev_free(d.len); dev_free(d.cap); dev_free(d.nbr); dev_free(d.core);
+    dev_free(d.mcd); dev_free(d.stamp); dev_free(d.chg); dev_free(d.cd); dev_free(d.dec);
+    dev_free(d.done); dev_free(d.matched); dev_free(d.claim); dev_free(d.bmark); dev_free(d.gain);
+    DevBatch &b = g->b;
+    dev_free(b.err); dev_free(b.eu); dev_free(b.ev); dev_free(b.su); dev_free(b.sv);
+    dev_free(b.hslot); dev_free(b.rem[0]); dev_free(b.rem[1]); dev_free(b.sel); dev_free(b.esel);
+    dev_free(b.hkey); dev_free(b.hval); dev_free(b.vlist); dev_free(b.scanq); dev_free(b.reloc);
+    dev_free(b.reloc_off); dev_free(b.reloc_cap);
+    DevQueues &q = g->q;
+    for (int i = 0; i < 2; ++i) {
+        dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.fx[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
+    }
+    dev_free(q.cand); dev_free(q.chg); dev_free(q.chh); dev_free(q.touched);
+    dev_free(g->src_buf); dev_free(g->dst_buf); dev_free(g->scan_tmp); dev_free(g->i64_scratch);
+    dev_free(g->u64_scratch); dev_free(g->firstidx);
+    g->g = DevGraph{};
+    g->b = DevBatch{};
+    g->q = DevQueues{};
+    g->batch_cap = g->hash_cap = g->scan_cap = 0;
+    g->scan_tmp_cap = 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void cm_config_default(cm_config *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->strict = 1;
+    cfg->mode = CM_MODE_PLAIN;
+}
+
+const char *cm_strerror(int status) {
+    switch (status) {
+    case CM_OK: return "ok";
+    case CM_E_ARG: return "invalid argument";
+    case CM_E_RANGE: return "vertex id out of range";
+    case CM_E_SELF_LOOP: return "self-loop";
+    case CM_E_DUP: return "duplicate item in batch";
+    case CM_E_EXISTS: return "edge already exists";
+    case CM_E_MISSING: return "edge does not exist";
+    case CM_E_DEAD: return "vertex was deleted";
+    case CM_E_NOMEM: return "out of memory";
+    case CM_E_CAPACITY: return "capacity exceeded";
+    case CM_E_STATE: return "invalid state";
+    case CM_E_DEVICE: return "device error";
+    case CM_E_INTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+const char *cm_last_error(const cm_graph *g) { return g ? g->err.c_str() : ""; }
+
+int cm_create(const cm_config *cfg, cm_graph **out) {
+    if (!out) return CM_E_ARG;
+    *out = nullptr;
+    cm_graph *g = new (std::nothrow) cm_graph();
+    if (!g) return CM_E_NOMEM;
+    try {
+        if (cfg) g->cfg = *cfg;
+        else cm_config_default(&g->cfg);
+        if (g->cfg.mode != CM_MODE_PLAIN && g->cfg.mode != CM_MODE_PERSISTENT) {
+            delete g;
+            return CM_E_ARG;
+        }
+        HIPCHK(hipGetDevice(&g->device));
+        g->stream = (hipStream_t)g->cfg.stream;
+        HIPCHK(hipDeviceGetAttribute(&g->num_cu, hipDeviceAttributeMultiprocessorCount, g->device));
+        int coop_ok = 0;
+        HIPCHK(hipDeviceGetAttribute(&coop_ok, hipDeviceAttributeCooperativeLaunch, g->device));
+        if (!coop_ok) {
+            g->err = "device does not support cooperative launches";
+            throw Fail{CM_E_DEVICE};
+        }
+        g->tune.small_deg = g->cfg.small_degree > 0 ? g->cfg.small_degree : 16;
+        g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 4096;
+        g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 2048;
+        g->tune.rounds = g->cfg.partition_rounds > 0 ? std::min(g->cfg.partition_rounds, 8) : 1;
+        if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
+        int bpc_m = 0, bpc_d = 0;
+        HIPCHK(coop_occupancy(0, &bpc_m));
+        HIPCHK(coop_occupancy(1, &bpc_d));
+        int want = g->cfg.blocks_per_cu > 0 ? g->cfg.blocks_per_cu : 2;
+        g->coop_maint = g->num_cu * std::max(1, std::min(want, bpc_m));
+        g->coop_dec = g->num_cu * std::max(1, std::min(want, bpc_d));
+        g->grid_reg = g->num_cu * 8;
+        dev_alloc(g, &g->ctl, 1);
+        HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
+        HIPCHK(hipHostMalloc((void **)&g->hctl, sizeof(Ctl), hipHostMallocDefault));
+        std::memset(g->hctl, 0, sizeof(Ctl));
+        HIPCHK(hipHostMalloc((void **)&g->hu64, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+        dev_alloc(g, &g->i64_scratch, 4);
+        dev_alloc(g, &g->u64_scratch, 4);
+        HIPCHK(hipEventCreate(&g->ev0));
+        HIPCHK(hipEventCreate(&g->ev1));
+        HIPCHK(hipStreamSynchronize(g->stream));
+    } catch (const Fail &f) {
+        cm_destroy(g);
+        return f.code;
+    }
+    *out = g;
+    return CM_OK;
+}
+
+void cm_destroy(cm_graph *g) {
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    release_all(g);
+    if (g->ctl) (void)hipFree(g->ctl);
+    if (g->hctl) (void)hipHostFree(g->hctl);
+    if (g->hu64) (void)hipHostFree(g->hu64);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    delete g;
+}
+
+int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                  int on_device) {
+    if (!g || n < 0 || m < 0 || (m > 0 && (!src || !dst))) return CM_E_ARG;
+    if (g->poisoned) return CM_E_DEVICE;
+    hipStream_t st = g->stream;
+    try {
+        release_all(g);
+        g->loaded = g->decomposed = false;
+        g->m = 0;
+        int32_t n_cap = std::max<int32_t>(n + 1, g->cfg.vertex_capacity > 0 ? g->cfg.vertex_capacity
+                                                                           : n + n / 8 + 1024);
+        alloc_vertex_arrays(g, n_cap, 0);
+        g->g.n_ids = n;
+        // stage edges on the device
+        int32_t *ds = nullptr, *dd = nullptr;
+        bool own = false;
+        if (on_device) {
+            ds = const_cast<int32_t *>(src);
+            dd = const_cast<int32_t *>(dst);
+        } else if (m > 0) {
+            dev_alloc(g, &ds, m);
+            dev_alloc(g, &dd, m);
+            own = true;
+            HIPCHK(hipMemcpyAsync(ds, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(dd, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, st));
+        }
+        int rc = CM_OK;
+        if (m > 0) {
+            // range / self-loop / duplicate check
+            int64_t hc = next_pow2(2 * m);
+            unsigned long long *hkey = nullptr;
+            int64_t *hval = nullptr;
+            dev_alloc(g, &hkey, hc);
+            dev_alloc(g, &hval, hc);
+            HIPCHK(fill_u64(hkey, ~0ull, hc, st));
+            HIPCHK(fill_i64(hval, INT64_MAX, hc, st));
+            HIPCHK(fill_u64(g->u64_scratch, ~0ull, 1, st));
+            HIPCHK(load_check(ds, dd, m, n, hkey, hval, (uint32_t)(hc - 1), g->u64_scratch, st));
+            HIPCHK(hipMemcpyAsync(g->hu64, g->u64_scratch, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            dev_free(hkey);
+            dev_free(hval);
+            unsigned long long fb = g->hu64[0];
+            if (fb != ~0ull) {
+                rc = -(int)(fb & 0xff);
+                g->err = std::string("invalid edge ") + std::to_string((long long)(fb >> 8)) + ": " +
+                         cm_strerror(rc);
+            }
+        }
+        if (rc == CM_OK) {
+            // alive ids get core 0 until decomposed
+            HIPCHK(fill_i32(g->g.core, 0, n, st));
+            HIPCHK(fill_i32(g->g.len, 0, g->g.n_cap, st));
+            if (m > 0) HIPCHK(count_deg(ds, dd, m, g->g.len, st));
+            int64_t *caps64 = nullptr;
+            dev_alloc(g, &caps64, g->g.n_cap);
+            HIPCHK(caps_from_counts(g->g.len, n, g->g.n_cap, caps64, g->g.cap, st));
+            HIPCHK(exclusive_scan_i64(caps64, g->g.off, g->g.n_cap, g->scan_tmp, g->i64_scratch, st));
+            int64_t total = 0;
+            HIPCHK(hipMemcpyAsync(&total, g->i64_scratch, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            dev_free(caps64);
+            int64_t pool = total + total / 4 + 4096;
+            if (g->cfg.edge_capacity_hint > pool) pool = g->cfg.edge_capacity_hint;
+            dev_alloc(g, &g->g.nbr, pool);
+            g->g.pool_size = pool;
+            HIPCHK(fill_i32(g->g.len, 0, g->g.n_cap, st));
+            if (m > 0) HIPCHK(scatter_edges(ds, dd, m, g->g.off, g->g.len, g->g.nbr, st));
+            // control block
+            HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), st));
+            unsigned long long tail = (unsigned long long)total;
+            HIPCHK(hipMemcpyAsync(&g->ctl->pool_tail, &tail, sizeof(tail), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::memset(g->hctl, 0, sizeof(Ctl));
+            g->hctl->pool_tail = tail;
+            g->epoch = 0;
+            alloc_chunk_queues(g);
+            g->m = m;
+            g->n_alive = n;
+            g->loaded = true;
+        }
+        if (own) {
+            dev_free(ds);
+            dev_free(dd);
+        }
+        if (rc != CM_OK) {
+            release_all(g);
+            return rc;
+        }
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    g->err.clear();
+    return CM_OK;
+}
+
+int cm_core_decompose(cm_graph *g, cm_batch_stats *stats) {
+    if (!g) return CM_E_ARG;
+    double t0 = now_ms();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    try {
+        require_ready(g, false);
+        hipStream_t st = g->stream;
+        HIPCHK(ctl_batch_reset(g->ctl, 0, st));
+        KArgs a = make_args(g);
+        HIPCHK(dec_prep(a, g->grid_reg, st));
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
+        HIPCHK(decompose_coop(a, g->coop_dec, st));
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
+        HIPCHK(mcd_init(a, g->grid_reg, st));
+        sync_ctl(g);
+        check_overflow(g);
+        if (stats) {
+            stats->scanned = (int64_t)g->hctl->st_scanned;
+            stats->iterations = g->hctl->dec_rounds;
+            stats->launches = 1;
+            if (g->cfg.timing) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+                stats->kernel_ms = ms;
+            }
+            // per adjacency entry: id 4 + core 4 + degree atomic 4; per vertex 16
+            stats->alg_bytes = 12 * stats->scanned + 16 * (int64_t)g->n_alive;
+        }
+        g->decomposed = true;
+    } catch (const Fail &f) {
+        return finish(g, f.code, stats, t0);
+    }
+    return finish(g, CM_OK, stats, t0);
+}
+
+static int edge_call(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device,
+                     cm_batch_stats *stats, bool inserting) {
+    if (!g) return CM_E_ARG;
+    double t0 = now_ms();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->first_bad = -1;
+    }
+    if (s < 0 || (s > 0 && (!src || !dst))) return finish(g, CM_E_ARG, stats, t0);
+    try {
+        require_ready(g, true);
+        if (s == 0) return finish(g, CM_OK, stats, t0);
+        ensure_batch(g, s);
+        stage_inputs(g, s, src, dst, on_device);
+        int64_t dropped = 0;
+        edge_batch(g, s, inserting, stats, &dropped, false, false);
+    } catch (const Fail &f) {
+        return finish(g, f.code, stats, t0);
+    }
+    return finish(g, CM_OK, stats, t0);
+}
+
+int cm_insert_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device,
+                    cm_batch_stats *stats) {
+    return edge_call(g, s, src, dst, on_device, stats, true);
+}
+
+int cm_delete_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device,
+                    cm_batch_stats *stats) {
+    return edge_call(g, s, src, dst, on_device, stats, false);
+}
+
+int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs, int on_device,
+                       int32_t *first_new_id, cm_batch_stats *stats) {
+    if (!g) return CM_E_ARG;
+    double t0 = now_ms();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->first_bad = -1;
+    }
+    if (c < 0 || (c > 0 && !off)) return finish(g, CM_E_ARG, stats, t0);
+    int32_t first = -1;
+    bool created = false;
+    try {
+        require_ready(g, true);
+        hipStream_t st = g->stream;
+        first = g->g.n_ids;
+        if (first_new_id) *first_new_id = first;
+        if (c == 0) return finish(g, CM_OK, stats, t0);
+        // offsets to the host to size the batch
+        std::vector<int64_t> hoff(2);
+        int64_t total = 0;
+        int64_t *doff = nullptr;
+        bool own_off = false;
+        if (on_device) {
+            HIPCHK(hipMemcpyAsync(&total, off + c, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            int64_t first_off = 0;
+            HIPCHK(hipMemcpyAsync(&first_off, off, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (first_off != 0) { g->err = "off[0] must be 0"; throw Fail{CM_E_ARG}; }
+            doff = const_cast<int64_t *>(off);
+        } else {
+            if (off[0] != 0) { g->err = "off[0] must be 0"; throw Fail{CM_E_ARG}; }
+            for (int32_t i = 0; i < c; ++i)
+                if (off[i + 1] < off[i]) { g->err = "offsets must be non-decreasing"; throw Fail{CM_E_ARG}; }
+            total = off[c];
+            dev_alloc(g, &doff, (int64_t)c + 1);
+            own_off = true;
+            HIPCHK(hipMemcpyAsync(doff, off, sizeof(int64_t) * ((size_t)c + 1), hipMemcpyHostToDevice, st));
+        }
+        if (on_device) {
+            HIPCHK(fill_u64(g->u64_scratch, ~0ull, 1, st));
+            HIPCHK(vins_check_off(doff, c, g->u64_scratch, st));
+            HIPCHK(hipMemcpyAsync(g->hu64, g->u64_scratch, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (g->hu64[0] != ~0ull) { g->err = "offsets must be non-decreasing"; throw Fail{CM_E_ARG}; }
+        }
+        if (total < 0 || (total > 0 && !nbrs)) { g->err = "bad neighbour list"; throw Fail{CM_E_ARG}; }
+        ensure_vertex_capacity(g, (int64_t)first + c);
+        ensure_batch(g, std::max<int64_t>(total, 1));
+        // new ids exist (core 0) while the batch is validated
+        KArgs a = make_args(g);
+        HIPCHK(vins_init(a, first, c, st));
+        g->g.n_ids = first + c;
+        created = true;
+        if (total > 0) {
+            HIPCHK(vins_expand(doff, c, first, g->src_buf, g->grid_reg, st));
+            if (on_device) {
+                HIPCHK(hipMemcpyAsync(g->dst_buf, nbrs, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToDevice, st));
+            } else {
+                HIPCHK(hipMemcpyAsync(g->dst_buf, nbrs, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, st));
+            }
+            g->b.src_in = g->src_buf;
+            g->b.dst_in = g->dst_buf;
+        }
+        if (own_off) dev_free(doff);
+        g->n_alive += c;
+        if (total > 0) {
+            int64_t dropped = 0;
+            edge_batch(g, total, true, stats, &dropped, false, false);
+        }
+        created = false;
+    } catch (const Fail &f) {
+        if (created && !g->poisoned) {
+            KArgs a = make_args(g);
+            (void)vins_revert(a, first, c, g->stream);
+            (void)hipStreamSynchronize(g->stream);
+            g->g.n_ids = first;
+            g->n_alive -= c;
+        }
+        return finish(g, f.code, stats, t0);
+    }
+    return finish(g, CM_OK, stats, t0);
+}
+
+int cm_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int on_device, cm_batch_stats *stats) {
+    if (!g) return CM_E_ARG;
+    double t0 = now_ms();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->first_bad = -1;
+    }
+    if (c < 0 || (c > 0 && !ids)) return finish(g, CM_E_ARG, stats, t0);
+    try {
+        require_ready(g, true);
+        if (c == 0) return finish(g, CM_OK, stats, t0);
+        hipStream_t st = g->stream;
+        int32_t *dids = nullptr;
+        bool own = false;
+        if (on_device) {
+            dids = const_cast<int32_t *>(ids);
+        } else {
+            dev_alloc(g, &dids, c);
+            own = true;
+            HIPCHK(hipMemcpyAsync(dids, ids, sizeof(int32_t) * (size_t)c, hipMemcpyHostToDevice, st));
+        }
+        KArgs a = make_args(g);
+        HIPCHK(fill_u64(g->u64_scratch, ~0ull, 1, st));
+        HIPCHK(fill_u64(g->u64_scratch + 1, 0ull, 1, st));
+        HIPCHK(vdel_check(a, dids, c, g->firstidx, g->u64_scratch, g->u64_scratch + 1, st));
+        HIPCHK(hipMemcpyAsync(g->hu64, g->u64_scratch, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        unsigned long long fb = g->hu64[0];
+        int64_t total = (int64_t)g->hu64[1];
+        if (fb != ~0ull) {
+            int code = -(int)(fb & 0xff);
+            int64_t idx = (int64_t)(fb >> 8);
+            if (stats) stats->first_bad = idx;
+            if (g->cfg.strict) {
+                if (own) dev_free(dids);
+                g->err = std::string("invalid vertex item ") + std::to_string((long long)idx) + ": " +
+                         cm_strerror(code);
+                return finish(g, code, stats, t0);
+            }
+            // filter mode: keep the valid, first occurrences only
+            std::vector<int32_t> h(c);
+            HIPCHK(hipMemcpy(h.data(), dids, sizeof(int32_t) * (size_t)c, hipMemcpyDeviceToHost));
+            std::vector<int32_t> core_h(g->g.n_ids);
+            HIPCHK(hipMemcpy(core_h.data(), g->g.core, sizeof(int32_t) * (size_t)g->g.n_ids, hipMemcpyDeviceToHost));
+            std::vector<int32_t> keep;
+            std::vector<char> seen(g->g.n_ids, 0);
+            for (int32_t i = 0; i < c; ++i) {
+                int32_t x = h[i];
+                if (x < 0 || x >= g->g.n_ids || core_h[x] < 0 || seen[x]) continue;
+                seen[x] = 1;
+                keep.push_back(x);
+            }
+            if (stats) stats->dropped = c - (int64_t)keep.size();
+            if (own) dev_free(dids);
+            dev_alloc(g, &dids, std::max<int64_t>(1, (int64_t)keep.size()));
+            own = true;
+            c = (int32_t)keep.size();
+            if (c > 0)
+                HIPCHK(hipMemcpy(dids, keep.data(), sizeof(int32_t) * (size_t)c, hipMemcpyHostToDevice));
+            HIPCHK(fill_u64(g->u64_scratch + 1, 0ull, 1, st));
+            HIPCHK(fill_u64(g->u64_scratch, ~0ull, 1, st));
+            HIPCHK(vdel_check(a, dids, c, g->firstidx, g->u64_scratch, g->u64_scratch + 1, st));
+            HIPCHK(hipMemcpyAsync(g->hu64, g->u64_scratch, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            total = (int64_t)g->hu64[1];
+        }
+        if (total > 0) {
+            ensure_batch(g, total);
+            HIPCHK(fill_u64(g->u64_scratch + 2, 0ull, 1, st));
+            KArgs a2 = make_args(g);
+            HIPCHK(vdel_gather(a2, dids, c, g->src_buf, g->dst_buf, total, g->u64_scratch + 2, g->grid_reg, st));
+            g->b.src_in = g->src_buf;
+            g->b.dst_in = g->dst_buf;
+            int64_t dropped = 0;
+            // an edge between two deleted ids is gathered twice: drop the copy
+            edge_batch(g, total, false, stats, &dropped, true, false);
+            if (stats) stats->dropped = 0;
+        }
+        KArgs a3 = make_args(g);
+        HIPCHK(vdel_finish(a3, dids, c, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (own) dev_free(dids);
+        g->n_alive -= c;
+    } catch (const Fail &f) {
+        return finish(g, f.code, stats, t0);
+    }
+    return finish(g, CM_OK, stats, t0);
+}
+
+int cm_get_cores(cm_graph *g, int32_t *out, int32_t n, int on_device) {
+    if (!g || n < 0 || (n > 0 && !out)) return CM_E_ARG;
+    try {
+        require_ready(g, false);
+        if (n > g->g.n_ids) return CM_E_ARG;
+        if (n == 0) return CM_OK;
+        HIPCHK(hipMemcpyAsync(out, g->g.core, sizeof(int32_t) * (size_t)n,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_get_superior_degrees(cm_graph *g, int32_t *out, int32_t n, int on_device) {
+    if (!g || n < 0 || (n > 0 && !out)) return CM_E_ARG;
+    try {
+        require_ready(g, true);
+        if (n > g->g.n_ids) return CM_E_ARG;
+        if (n == 0) return CM_OK;
+        HIPCHK(hipMemcpyAsync(out, g->g.mcd, sizeof(int32_t) * (size_t)n,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_num_vertices(cm_graph *g, int32_t *n_ids, int32_t *n_alive) {
+    if (!g) return CM_E_ARG;
+    if (n_ids) *n_ids = g->g.n_ids;
+    if (n_alive) *n_alive = g->n_alive;
+    return CM_OK;
+}
+
+int cm_num_edges(cm_graph *g, int64_t *m) {
+    if (!g || !m) return CM_E_ARG;
+    *m = g->m;
+    return CM_OK;
+}
+
+int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap, int64_t *m_out, int on_device) {
+    if (!g || cap < 0 || (cap > 0 && (!src || !dst))) return CM_E_ARG;
+    try {
+        require_ready(g, false);
+        if (m_out) *m_out = g->m;
+        if (cap < g->m) return CM_E_ARG;
+        if (g->m == 0) return CM_OK;
+        hipStream_t st = g->stream;
+        int32_t *xs = src, *ys = dst;
+        bool own = !on_device;
+        if (own) {
+            dev_alloc(g, &xs, g->m);
+            dev_alloc(g, &ys, g->m);
+        }
+        HIPCHK(fill_u64(g->u64_scratch, 0ull, 1, st));
+        KArgs a = make_args(g);
+        HIPCHK(export_edges(a, xs, ys, g->m, g->u64_scratch, g->grid_reg, st));
+        if (own) {
+            HIPCHK(hipMemcpyAsync(src, xs, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(dst, ys, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (own) {
+            dev_free(xs);
+            dev_free(ys);
+        }
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+// Internal device-side layout and helpers of libcoremaint (gfx950, wave64).
+//
+// Graph store ("slack CSR with per-vertex spill blocks"): vertex v owns the
+// contiguous slot range nbr[off[v] .. off[v] + cap[v]); the first len[v]
+// slots are used, entries < 0 are tombstones left by deletions inside a
+// batch.  A list that outgrows its slack moves to a fresh block carved from
+// the tail of the same pool (its spill block); the old range becomes garbage
+// that the next repack reclaims.  Every list stays contiguous, so one wave
+// reads a list with coalesced loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+#include <stdint.h>
+
+namespace cm {
+
+constexpr int WAVE = 64;
+constexpr int32_t TOMB = -1;             // deleted adjacency slot
+constexpr uint64_t EMPTY_KEY = ~0ull;    // empty hash slot
+
+// ---------------------------------------------------------------------------
+// Control block: counters shared by all workgroups of a launch.  Rotating
+// queue tails use three slots: in round r the tail r%3 is read, (r+1)%3
+// receives pushes and (r+2)%3 is cleared for the next round.
+// ---------------------------------------------------------------------------
+struct Ctl {
+    int32_t rem_count[2];    // remaining-edge lists, ping-pong by epoch parity
+    int32_t sel_count;       // selected edges of the current iteration
+    int32_t fq_tail[3];      // expansion: normal vertices
+    int32_t fh_tail[3];      // expansion: chunks of long lists (count pass)
+    int32_t fx_tail[3];      // expansion: chunks of long lists (expand pass)
+    int32_t eq_tail[3];      // eviction / peel / decomposition: normal vertices
+    int32_t eh_tail[3];      // eviction / peel / decomposition: chunks of long lists
+    int32_t cand_count;      // candidates of the iteration (insert)
+    int32_t chg_count;       // changed vertices (normal)
+    int32_t chh_count;       // changed vertices (chunks)
+    int32_t touched_count;   // vertices whose peel counter was touched (delete)
+    int32_t overflow;        // a queue push went past its capacity (bug guard)
+    int32_t epoch;           // last iteration stamp used
+    int32_t iters_done;      // iterations run by the last launch
+    int32_t pool_fail;       // adjacency pool exhausted during reservation
+    int32_t first_bad;       // smallest invalid batch index
+    int32_t valid_count;     // valid batch items
+    int32_t scan_tail;       // locate-scan chunk queue
+    int32_t vlist_count;     // distinct endpoints of the batch
+    int32_t reloc_count;     // lists relocated to spill blocks
+    int32_t changed_count;   // vertices whose core moved (current iteration)
+    int32_t rm_count[3];     // decomposition: remaining vertices (rotating)
+    int32_t min_deg[3];      // decomposition: smallest remaining degree (rotating)
+    int32_t kmax;            // decomposition: largest core number
+    int32_t dec_rounds;      // decomposition: frontier rounds
+    int32_t pad[2];
+    unsigned long long pool_tail;     // next free adjacency slot
+    unsigned long long garbage;       // slots abandoned by relocations
+    // statistics (summed over the iterations of a batch)
+    unsigned long long st_iters;
+    unsigned long long st_remaining;
+    unsigned long long st_selected;
+    unsigned long long st_candidates;
+    unsigned long long st_evicted;
+    unsigned long long st_changed;
+    unsigned long long st_scanned;
+};
+
+// Per-vertex device arrays plus the adjacency pool.
+struct DevGraph {
+    int32_t n_cap;       // allocated ids
+    int32_t n_ids;       // ids in use
+    int64_t pool_size;   // slots in nbr
+    int64_t *off;        // [n_cap] first slot of the list
+    int32_t *len;        // [n_cap] used slots (incl. tombstones)
+    int32_t *cap;        // [n_cap] reserved slots
+    int32_t *nbr;        // [pool_size]
+    int32_t *core;       // [n_cap] core number; -1 = dead id
+    int32_t *mcd;        // [n_cap] superior degree SD (neighbours with core >= own)
+    int32_t *stamp;      // [n_cap] iteration stamp: candidate (insert) / peeled (delete)
+    int32_t *chg;        // [n_cap] iteration stamp: core moved this iteration
+    int32_t *cd;         // [n_cap] insertion counter (CSD, then decremented)
+    int32_t *dec;        // [n_cap] deletion peel counter (zero between iterations)
+    int32_t *done;       // [n_cap] finished chunks of a long list (zero between uses)
+    uint32_t *matched;   // [n_cap] selection round stamp
+    unsigned long long *claim;  // [n_cap] selection claim key (smaller wins)
+    int32_t *bmark;      // [n_cap] batch stamp (validation scans, reservation)
+    int32_t *gain;       // [n_cap] edges a batch adds to the list (zero between uses)
+};
+
+// Edges of one batch after validation.
+struct DevBatch {
+    int32_t cap;         // capacity in edges
+    int32_t *src_in;     // raw input (device copy or caller pointer)
+    int32_t *dst_in;
+    int32_t *err;        // [cap] per-item status
+    int32_t *eu;         // [cap] canonical endpoints, eu < ev
+    int32_t *ev;
+    int64_t *su;         // [cap] slot of ev in N(eu) (delete), -1 if not found
+    int64_t *sv;         // [cap] slot of eu in N(ev) (delete)
+    int32_t *hslot;      // [cap] hash slot of the item
+    int32_t *rem[2];     // remaining edge indices, ping-pong
+    int32_t *sel;        // selected edge indices of an iteration
+    int32_t *esel;       // [cap] iteration stamp of selection
+    int32_t hcap;        // hash slots (power of two)
+    unsigned long long *hkey;  // [hcap]
+    int32_t *hval;       // [hcap] smallest item index with that key
+    int32_t *vlist;      // [n_cap] distinct batch endpoints (reservation / compaction)
+    int64_t *scanq;      // [scap] (vertex, chunk) locate-scan items
+    int32_t scap;
+    int32_t *reloc;      // [n_cap] relocated vertices
+    int64_t *reloc_off;  // [n_cap] their new first slot
+    int32_t *reloc_cap;  // [n_cap] their new capacity
+};
+
+// Frontier queues of an iteration.  Long lists (len > large) enter the
+// chunk queues as (vertex << 32 | chunk) items so that their work spreads
+// over many waves.
+struct DevQueues {
+    int32_t vcap;        // capacity of vertex queues
+    int32_t hcap;        // capacity of chunk queues
+    int32_t *fq[2];
+    int64_t *fh[2];
+    int64_t *fx[2];
+    int32_t *eq[2];
+    int64_t *eh[2];
+    int32_t *cand;
+    int32_t *chg;
+    int64_t *chh;
+    int32_t *touched;
+};
+
+struct Tune {
+    int32_t small_deg;   // list length walked by one lane
+    int32_t large_deg;   // longer lists are chunked
+    int32_t chunk;       // chunk length
+    int32_t rounds;      // selection rounds per iteration
+};
+
+struct KArgs {
+    DevGraph g;
+    DevBatch b;
+    DevQueues q;
+    Tune t;
+    Ctl *ctl;
+    int32_t inserting;   // 1 = insertion batch, 0 = deletion batch
+    int32_t max_iters;   // iterations this launch may run
+    int32_t s;           // batch items
+    int32_t bstamp;      // batch stamp (bmark values bstamp, bstamp + 1)
+    int32_t cur;         // remaining list that receives the validated batch
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int gwave() {
+    return (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+}
+__device__ __forceinline__ int nwaves() { return (int)((gridDim.x * blockDim.x) / WAVE); }
+__device__ __forceinline__ int gtid() { return (int)(blockIdx.x * blockDim.x + threadIdx.x); }
+__device__ __forceinline__ int gthreads() { return (int)(gridDim.x * blockDim.x); }
+
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int32_t ld_acq(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Append `val` for every active lane with pred set; one atomic per wave.
+// Works in divergent code: the ballot covers the active lanes only.
+template <class T>
+__device__ __forceinline__ void push_agg(T *q, int32_t qcap, int32_t *tail, T val, bool pred,
+                                         int32_t *overflow) {
+    unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    int leader = __ffsll((long long)m) - 1;
+    int cnt = __popcll(m);
+    int me = lane();
+    int rank = __popcll(m & ((1ull << me) - 1ull));
+    int base = 0;
+    if (me == leader) base = atomicAdd(tail, cnt);
+    base = __shfl(base, leader);
+    if (pred) {
+        int pos = base + rank;
+        if (pos < qcap) q[pos] = val;
+        else atomicOr(overflow, 1);
+    }
+}
+
+// Reserve `n` consecutive entries (per lane, any n >= 0) with one atomic per
+// wave; returns this lane's first position.
+__device__ __forceinline__ int reserve_agg(int32_t *tail, int n) {
+    unsigned long long m = __ballot(n > 0);
+    if (m == 0ull) return 0;
+    // exclusive prefix of n over active lanes
+    int me = lane();
+    int incl = n;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(incl, o);
+        if (me >= o) incl += t;
+    }
+    int total = __shfl(incl, WAVE - 1);
+    int base = 0;
+    int leader = __ffsll((long long)m) - 1;
+    if (me == leader) base = atomicAdd(tail, total);
+    base = __shfl(base, leader);
+    return base + incl - n;
+}
+
+__device__ __forceinline__ int64_t chunk_item(int32_t v, int32_t c) {
+    return ((int64_t)v << 32) | (uint32_t)c;
+}
+__device__ __forceinline__ int32_t item_v(int64_t it) { return (int32_t)(it >> 32); }
+__device__ __forceinline__ int32_t item_c(int64_t it) { return (int32_t)(it & 0xffffffff); }
+
+__device__ __forceinline__ int nchunks(int32_t len, int32_t chunk) { return (len + chunk - 1) / chunk; }
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // bijective 32-bit finaliser (xorshift-multiply)
+    x ^= x >> 16; x *= 0x7feb352dU;
+    x ^= x >> 15; x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long edge_key(int32_t a, int32_t b) {
+    int32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    return ((unsigned long long)(uint32_t)lo << 32) | (uint32_t)hi;
+}
+
+__device__ __forceinline__ uint32_t hash_key(unsigned long long k) {
+    uint32_t h = mix32((uint32_t)k ^ 0x9e3779b9U);
+    return mix32(h ^ (uint32_t)(k >> 32));
+}
+
+// Grid-wide barrier of a cooperative launch.
+__device__ __forceinline__ void gsync() { cooperative_groups::this_grid().sync(); }
+
+}  // namespace cm

@@ -1,0 +1,113 @@
+// Load-balanced walks over frontier queues (gfx950, wave64).
+//
+// A frontier is a list of vertices plus a list of chunk items for long
+// adjacency lists.  Each wave takes 64 queue entries: a vertex whose list is
+// short (len <= small) is walked by its own lane; longer lists are walked by
+// the whole wave, one vertex after another (coalesced 256-byte reads);
+// lists longer than `large` never enter the vertex list -- the pusher splits
+// them into chunk items that separate waves walk.
+#pragma once
+#include "cm_internal.h"
+
+namespace cm {
+
+// Route a pushed vertex: short/medium lists to the vertex queue, long lists
+// as `nchunks` items to the chunk queue.  All lanes may call it (pred
+// selects the pushing lanes); a long list costs one atomic on its lane.
+__device__ __forceinline__ void push_vertex(const KArgs &a, int32_t *vq, int32_t *vtail, int64_t *hq,
+                                            int32_t *htail, int32_t w, bool pred) {
+    int32_t L = pred ? a.g.len[w] : 0;
+    bool big = pred && L > a.t.large_deg;
+    push_agg<int32_t>(vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
+    if (big) {
+        int nch = nchunks(L, a.t.chunk);
+        int base = atomicAdd(htail, nch);
+        for (int c = 0; c < nch; ++c) {
+            int pos = base + c;
+            if (pos < a.q.hcap) hq[pos] = chunk_item(w, c);
+            else atomicOr(&a.ctl->overflow, 1);
+        }
+    }
+}
+
+// Grid-stride over a vertex queue.  fl(v, L) runs on the owning lane for
+// short lists; fw(v, L) runs on the whole wave (uniform) for the others.
+template <class FL, class FW>
+__device__ __forceinline__ void for_vertices(const int32_t *q, int32_t n, const DevGraph &g, int32_t small,
+                                             FL &&fl, FW &&fw) {
+    const int step = nwaves() * WAVE;
+    for (int32_t base = gwave() * WAVE; base < n; base += step) {
+        int32_t i = base + lane();
+        int32_t v = (i < n) ? q[i] : -1;
+        int32_t L = (v >= 0) ? g.len[v] : 0;
+        if (v >= 0 && L <= small) fl(v, L);
+        unsigned long long m = __ballot(v >= 0 && L > small);
+        while (m) {
+            int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            int32_t vv = __shfl(v, src);
+            int32_t LL = __shfl(L, src);
+            fw(vv, LL);
+        }
+    }
+}
+
+// Same for an implicit identity list 0..n-1 (whole-graph passes); lists of
+// any length are accepted (long ones are walked by one wave).
+template <class FL, class FW>
+__device__ __forceinline__ void for_all_vertices(int32_t n, const DevGraph &g, int32_t small, FL &&fl,
+                                                 FW &&fw) {
+    const int step = nwaves() * WAVE;
+    for (int32_t base = gwave() * WAVE; base < n; base += step) {
+        int32_t v = base + lane();
+        bool ok = v < n && g.core[v] != -1;  // -1 marks a dead id
+        int32_t L = ok ? g.len[v] : 0;
+        if (ok && L <= small) fl(v, L);
+        unsigned long long m = __ballot(ok && L > small);
+        while (m) {
+            int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            int32_t vv = __shfl(v, src);
+            int32_t LL = __shfl(L, src);
+            fw(vv, LL);
+        }
+    }
+}
+
+// Grid-stride over chunk items, one wave per item: fc(v, lo, hi, nch).
+template <class FC>
+__device__ __forceinline__ void for_chunks(const int64_t *q, int32_t n, const DevGraph &g, int32_t chunk,
+                                           FC &&fc) {
+    for (int32_t j = gwave(); j < n; j += nwaves()) {
+        int64_t it = q[j];
+        int32_t v = item_v(it), c = item_c(it);
+        int32_t L = g.len[v];
+        int32_t lo = c * chunk;
+        int32_t hi = lo + chunk < L ? lo + chunk : L;
+        fc(v, lo, hi, nchunks(L, chunk));
+    }
+}
+
+// Wave walk of slots [lo, hi) of v: every lane calls f(w, slot) each step
+// (w < 0 for padding lanes and tombstones) so f may use wave votes.
+template <class F>
+__device__ __forceinline__ void wave_walk(const DevGraph &g, int32_t v, int32_t lo, int32_t hi, F &&f) {
+    const int32_t *p = g.nbr + g.off[v];
+    for (int32_t s = lo; s < hi; s += WAVE) {
+        int32_t i = s + lane();
+        int32_t w = (i < hi) ? p[i] : -1;
+        f(w, i);
+    }
+}
+
+// Lane walk of slots [0, L) of v, live entries only.
+template <class F>
+__device__ __forceinline__ void lane_walk(const DevGraph &g, int32_t v, int32_t L, F &&f) {
+    const int32_t *p = g.nbr + g.off[v];
+    for (int32_t i = 0; i < L; ++i) {
+        int32_t w = p[i];
+        if (w >= 0) f(w, i);
+    }
+}
+
+}  // namespace cm

@@ -1,0 +1,345 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: core numbers
+bit-exact after the initial decomposition and after every batch; the
+maintained superior degree SD equals its definition on the oracle's cores."""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen
+from tests.golden import cases as golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1612_09368_amd as cm
+    cm.library()
+    return cm
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _t(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def sd_definition(n, s, d, core):
+    """SD(v) = #{w in N(v) : core(w) >= core(v)} (superior degree, Section IV-B)."""
+    sd = np.zeros(n, dtype=np.int64)
+    s = s.astype(np.int64)
+    d = d.astype(np.int64)
+    np.add.at(sd, s, (core[d] >= core[s]).astype(np.int64))
+    np.add.at(sd, d, (core[s] >= core[d]).astype(np.int64))
+    sd[core < 0] = 0
+    return sd.astype(np.int32)
+
+
+def check_state(g, ref, tag=""):
+    got = g.cores()
+    want = ref.cores()
+    assert got.shape == want.shape, tag
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{tag}: {bad.size} cores differ, first {bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}"
+    s, d = ref.edges()
+    sd = g.superior_degrees()
+    want_sd = sd_definition(ref.n, s, d, want)
+    badsd = np.nonzero(sd != want_sd)[0]
+    assert badsd.size == 0, f"{tag}: SD differs at {badsd[:5]} got {sd[badsd[:5]]} want {want_sd[badsd[:5]]}"
+    assert g.num_edges() == ref.num_edges(), tag
+
+
+def new_graph(cm, n, s, d, dev, **kw):
+    g = cm.Graph(**kw)
+    g.load(n, _t(s, dev), _t(d, dev))
+    g.decompose()
+    return g
+
+
+@pytest.mark.parametrize("name", golden.all_cases())
+@pytest.mark.parametrize("mode", [0, 1])
+def test_golden_fixtures(cm, dev, name, mode):
+    case = golden.load(name)
+    with new_graph(cm, case["n"], *case["edges"], dev, mode=mode) as g:
+        assert np.array_equal(g.cores(), case["cores"])
+        for kind, s, d, want in case["steps"]:
+            (g.insert_edges if kind == "insert" else g.delete_edges)(_t(s, dev), _t(d, dev))
+            assert np.array_equal(g.cores(), want), (name, kind, g.cores(), want)
+
+
+def test_decompose_closed_forms(cm, dev, oracle_mod):
+    graphs = []
+    for n in (2, 7, 40):
+        graphs.append((n, list(itertools.combinations(range(n), 2))))
+    graphs.append((101, [(i, (i + 1) % 101) for i in range(101)]))
+    graphs.append((12, [(i, 4 + j) for i in range(4) for j in range(8)]))
+    r = 9
+    graphs.append((r + 1, [(0, i) for i in range(1, r + 1)] + [(i, i % r + 1) for i in range(1, r + 1)]))
+    graphs.append((50, []))
+    for n, pairs in graphs:
+        s = np.asarray([p[0] for p in pairs], dtype=np.int32)
+        d = np.asarray([p[1] for p in pairs], dtype=np.int32)
+        with new_graph(cm, n, s, d, dev) as g:
+            assert np.array_equal(g.cores(), oracle_mod.brute_cores(n, s, d) if n <= 12
+                                  else oracle_mod.bz_cores(n, s, d))
+
+
+@pytest.mark.parametrize("kind", ["er", "cl", "rmat"])
+def test_decompose_random(cm, dev, oracle_mod, kind):
+    rng = graphgen.rng_for("dec-" + kind)
+    if kind == "er":
+        n = 30_000
+        s, d = graphgen.er_graph(n, 150_000, rng)
+    elif kind == "cl":
+        n = 50_000
+        s, d = graphgen.chung_lu_graph(n, 400_000, 2.1, 8000.0, rng)
+    else:
+        n, s, d = graphgen.rmat_graph(15, 16, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev) as g:
+        check_state(g, ref, kind)
+
+
+def _batches(ref, rng, n, count, size):
+    """Alternating insert / delete batches valid against the current graph."""
+    es = graphgen.EdgeSet(*ref.edges())
+    out = []
+    for b in range(count):
+        if b % 2 == 0:
+            s, d = graphgen.uniform_non_edges(n, size, es, rng)
+            es.insert(s, d)
+            out.append(("insert", s, d))
+        else:
+            s, d = graphgen.existing_edges(size, es, rng)
+            es.delete(s, d)
+            out.append(("delete", s, d))
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_er_config_parity(cm, dev, oracle_mod, mode):
+    """G(10,000, 50,000), seed 0: insert 1,000 non-edges, then delete 1,000
+    existing edges; cores compared after each batch."""
+    rng = graphgen.rng_for("er-10k")
+    n = 10_000
+    s, d = graphgen.er_graph(n, 50_000, np.random.default_rng(0))
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    with new_graph(cm, n, s, d, dev, mode=mode) as g:
+        check_state(g, ref, "initial")
+        a, b = graphgen.uniform_non_edges(n, 1000, es, rng)
+        st = g.insert_edges(_t(a, dev), _t(b, dev))
+        ref.insert_edges(a, b)
+        es.insert(a, b)
+        assert st.applied == 1000 and st.iterations >= 1
+        check_state(g, ref, "after insert")
+        a, b = graphgen.existing_edges(1000, es, rng)
+        st = g.delete_edges(_t(a, dev), _t(b, dev))
+        ref.delete_edges(a, b)
+        assert st.applied == 1000
+        check_state(g, ref, "after delete")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fuzz_small_graphs(cm, dev, oracle_mod, seed):
+    rng = np.random.default_rng(1000 + seed)
+    for trial in range(12):
+        n = int(rng.integers(5, 60))
+        maxm = n * (n - 1) // 2
+        m = int(rng.integers(0, min(maxm, 4 * n) + 1))
+        s, d = graphgen.er_graph(n, m, rng)
+        ref = oracle_mod.DynamicGraph(n, s, d)
+        mode = int(rng.integers(0, 2))
+        rounds = int(rng.integers(1, 4))
+        with new_graph(cm, n, s, d, dev, mode=mode, partition_rounds=rounds,
+                       small_degree=int(rng.choice([1, 4, 16])), large_degree=int(rng.choice([8, 32, 4096])),
+                       chunk=int(rng.choice([8, 64, 2048]))) as g:
+            check_state(g, ref, f"seed {seed} trial {trial} initial")
+            for kind, a, b in _batches(ref, rng, n, 6, int(rng.integers(1, max(2, n)))):
+                if a.size == 0:
+                    continue
+                (g.insert_edges if kind == "insert" else g.delete_edges)(_t(a, dev), _t(b, dev))
+                (ref.insert_edges if kind == "insert" else ref.delete_edges)(a, b)
+                check_state(g, ref, f"seed {seed} trial {trial} {kind}")
+
+
+@pytest.mark.parametrize("kind", ["cl", "rmat"])
+def test_skewed_batches(cm, dev, oracle_mod, kind):
+    """Degree-weighted updates on skewed graphs: hubs collect many updates, so
+    batches need many superior edge sets; long lists take the chunked path."""
+    rng = graphgen.rng_for("skew-" + kind)
+    if kind == "cl":
+        n = 40_000
+        s, d = graphgen.chung_lu_graph(n, 300_000, 2.1, 6000.0, rng)
+    else:
+        n, s, d = graphgen.rmat_graph(14, 16, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    for mode in (0, 1):
+        with new_graph(cm, n, s, d, dev, mode=mode, large_degree=512, chunk=256) as g:
+            r2 = oracle_mod.DynamicGraph(n, s, d)
+            e2 = graphgen.EdgeSet(s, d)
+            for step in range(2):
+                a, b = graphgen.weighted_non_edges(5000, e2, rng)
+                st = g.insert_edges(_t(a, dev), _t(b, dev))
+                r2.insert_edges(a, b)
+                e2.insert(a, b)
+                check_state(g, r2, f"{kind} mode {mode} insert {step}")
+                assert st.iterations > 1
+                a, b = graphgen.existing_edges(5000, e2, rng)
+                g.delete_edges(_t(a, dev), _t(b, dev))
+                r2.delete_edges(a, b)
+                e2.delete(a, b)
+                check_state(g, r2, f"{kind} mode {mode} delete {step}")
+    del ref, es
+
+
+def test_insert_then_delete_restores(cm, dev, oracle_mod):
+    rng = graphgen.rng_for("restore")
+    n = 5000
+    s, d = graphgen.chung_lu_graph(n, 30_000, 2.3, 500.0, rng)
+    es = graphgen.EdgeSet(s, d)
+    a, b = graphgen.weighted_non_edges(3000, es, rng)
+    with new_graph(cm, n, s, d, dev) as g:
+        before = g.cores().copy()
+        sd0 = g.superior_degrees().copy()
+        g.insert_edges(_t(a, dev), _t(b, dev))
+        after = g.cores()
+        assert (after >= before).all()
+        g.delete_edges(_t(b, dev), _t(a, dev))
+        assert np.array_equal(g.cores(), before)
+        assert np.array_equal(g.superior_degrees(), sd0)
+
+
+def test_strict_errors_leave_graph_unchanged(cm, dev, oracle_mod):
+    n = 6
+    s = np.array([0, 1, 2, 3], dtype=np.int32)
+    d = np.array([1, 2, 3, 4], dtype=np.int32)
+    with new_graph(cm, n, s, d, dev) as g:
+        before = g.cores().copy()
+        cases = [
+            ("insert", [0, 9], [5, 1], cm.E_RANGE, 1),
+            ("insert", [5, 2], [0, 2], cm.E_SELF_LOOP, 1),
+            ("insert", [0, 5, 2], [5, 0, 5], cm.E_DUP, 1),
+            ("insert", [0, 2], [5, 1], cm.E_EXISTS, 1),
+            ("delete", [0, 0], [1, 5], cm.E_MISSING, 1),
+            ("delete", [1, 0], [0, 1], cm.E_DUP, 1),
+        ]
+        ref = oracle_mod.DynamicGraph(n, s, d)
+        for kind, a, b, code, idx in cases:
+            a = np.array(a, dtype=np.int32)
+            b = np.array(b, dtype=np.int32)
+            fn = g.insert_edges if kind == "insert" else g.delete_edges
+            st, stats = fn(_t(a, dev), _t(b, dev), check=False)
+            assert st == code and stats.first_bad == idx, (kind, a, b, st, stats.first_bad)
+            err = ref.validate(a, b, kind == "insert")
+            assert int(err[np.nonzero(err)[0][0]]) == code
+            assert np.array_equal(g.cores(), before) and g.num_edges() == 4
+        # host inputs take the same path
+        st, stats = g.insert_edges(np.array([0, 4], np.int32), np.array([1, 4], np.int32), check=False)
+        assert st == cm.E_EXISTS and stats.first_bad == 0
+
+
+def test_filter_mode_drops_invalid(cm, dev, oracle_mod):
+    n = 8
+    s = np.array([0, 1, 2], dtype=np.int32)
+    d = np.array([1, 2, 0], dtype=np.int32)
+    with new_graph(cm, n, s, d, dev, strict=False) as g:
+        a = np.array([0, 3, 3, 7, 0, 4, 4], dtype=np.int32)
+        b = np.array([1, 4, 4, 7, 3, 5, 3], dtype=np.int32)
+        st = g.insert_edges(_t(a, dev), _t(b, dev))
+        ref = oracle_mod.DynamicGraph(n, s, d)
+        ref.insert_edges(a, b, strict=False)
+        assert st.applied == 3 and st.dropped == 4 and st.first_bad == 0
+        check_state(g, ref, "filter insert")
+
+
+def test_vertex_ops(cm, dev, oracle_mod):
+    rng = graphgen.rng_for("vops")
+    n = 3000
+    s, d = graphgen.chung_lu_graph(n, 15_000, 2.2, 300.0, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    with new_graph(cm, n, s, d, dev, vertex_capacity=0) as g:
+        # insert 200 vertices with power-law degrees, neighbours degree-weighted
+        degs = graphgen.power_law_degrees(200, 1, 60, 2.1, rng)
+        off, nb = graphgen.vertex_insert_payload(n, 200, degs, es, rng)
+        first, st = g.insert_vertices(_t(off, dev), _t(nb, dev))
+        st2, _, first2 = ref.insert_vertices(off, nb)
+        assert first == first2 == n
+        check_state(g, ref, "vertex insert")
+        # a new vertex joined to an earlier new vertex and existing ones
+        off2 = np.array([0, 3], dtype=np.int64)
+        nb2 = np.array([n, n + 1, 5], dtype=np.int32)
+        first, _ = g.insert_vertices(off2, nb2)
+        ref.insert_vertices(off2, nb2)
+        check_state(g, ref, "vertex insert 2")
+        # delete 300 live vertices (old and new)
+        ids = rng.choice(n + 201, 300, replace=False).astype(np.int32)
+        g.delete_vertices(_t(ids, dev))
+        ref.delete_vertices(ids)
+        check_state(g, ref, "vertex delete")
+        assert (g.cores()[ids] == -1).all()
+        nids, alive = g.num_vertices()
+        assert nids == n + 201 and alive == n + 201 - 300
+        # errors: dead id, duplicate, out of range
+        for bad, code in (([int(ids[0])], cm.E_DEAD), ([1, 1], cm.E_DUP), ([10 ** 6], cm.E_RANGE)):
+            live = [v for v in [1] if v not in set(ids.tolist())]
+            st, _ = g.delete_vertices(np.array(bad, dtype=np.int32), check=False)
+            assert st == code or (code == cm.E_DUP and 1 in set(ids.tolist()))
+            del live
+        # invalid neighbour rejects the whole vertex insert
+        st, fid, _ = g.insert_vertices(np.array([0, 2], np.int64), np.array([0, int(ids[0])], np.int32),
+                                       check=False)
+        assert st == cm.E_DEAD
+        assert g.num_vertices()[0] == n + 201
+        check_state(g, ref, "after rejected vertex insert")
+
+
+def test_growth_and_spill(cm, dev, oracle_mod):
+    """Lists outgrow their slack many times (spill blocks, pool repack)."""
+    rng = graphgen.rng_for("grow")
+    n = 2000
+    s, d = graphgen.er_graph(n, 2000, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    with new_graph(cm, n, s, d, dev) as g:
+        for step in range(6):
+            a, b = graphgen.weighted_non_edges(4000, es, rng)
+            g.insert_edges(_t(a, dev), _t(b, dev))
+            ref.insert_edges(a, b)
+            es.insert(a, b)
+            check_state(g, ref, f"grow {step}")
+        xs, ys = g.export_edges()
+        assert np.array_equal(np.sort(graphgen.keys_of(xs, ys)), np.sort(ref.keys))
+
+
+@pytest.mark.slow
+def test_chung_lu_full_size(cm, dev, oracle_mod):
+    """Chung-Lu n = 1,000,000, m = 10,000,000, exponent 2.1, max weight 50,000;
+    100,000 degree-weighted non-edges inserted, then 100,000 existing edges
+    deleted: full core vectors compared (the benchmark's workload)."""
+    rng = graphgen.rng_for("cl-1m")
+    n = 1_000_000
+    s, d = graphgen.chung_lu_graph(n, 10_000_000, 2.1, 50_000.0, rng)
+    es = graphgen.EdgeSet(s, d)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev) as g:
+        assert np.array_equal(g.cores(), ref.cores())
+        a, b = graphgen.weighted_non_edges(100_000, es, rng)
+        g.insert_edges(_t(a, dev), _t(b, dev))
+        ref.insert_edges(a, b)
+        es.insert(a, b)
+        assert np.array_equal(g.cores(), ref.cores())
+        a, b = graphgen.existing_edges(100_000, es, rng)
+        g.delete_edges(_t(a, dev), _t(b, dev))
+        ref.delete_edges(a, b)
+        check_state(g, ref, "cl full")
