@@ -2,6 +2,7 @@
 // initial decomposition and the batched maintenance drivers.
 #include <algorithm>
 #include <chrono>
+#include <initializer_list>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -104,7 +105,31 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
+// Refuse to launch with a missing buffer (a null device pointer would make
+// the kernel fault).
+void require_ptrs(cm_graph *g, std::initializer_list<const void *> ps, const char *what) {
+    for (const void *p : ps) {
+        if (!p) {
+            g->poisoned = true;
+            g->err = std::string("internal: missing device buffer for ") + what;
+            throw Fail{CM_E_INTERNAL};
+        }
+    }
+}
+
 KArgs make_args(cm_graph *g) {
+    require_ptrs(g, {g->ctl, g->i64_scratch, g->u64_scratch}, "control block");
+    if (g->loaded) {
+        const DevGraph &d = g->g;
+        require_ptrs(g, {d.off, d.len, d.cap, d.nbr, d.core, d.mcd, d.stamp, d.chg, d.cd, d.dec,
+                         d.done, d.matched, d.claim, d.bmark, d.gain},
+                     "graph arrays");
+        const DevQueues &q = g->q;
+        require_ptrs(g, {q.fq[0], q.fq[1], q.fh[0], q.fh[1], q.fx[0], q.fx[1], q.eq[0], q.eq[1],
+                         q.eh[0], q.eh[1], q.cand, q.chg, q.chh, q.touched, g->b.vlist, g->b.reloc,
+                         g->b.reloc_off, g->b.reloc_cap, g->scan_tmp, g->firstidx},
+                     "queues");
+    }
     KArgs a{};
     a.g = g->g;
     a.b = g->b;
@@ -305,9 +330,7 @@ void repack(cm_graph *g, int64_t extra) {
     g->g.nbr = newnbr;
     g->g.pool_size = pool;
     unsigned long long tail = (unsigned long long)total;
-    unsigned long long zero = 0;
-    HIPCHK(hipMemcpyAsync(&g->ctl->pool_tail, &tail, sizeof(tail), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(&g->ctl->garbage, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    HIPCHK(ctl_set_pool(g->ctl, tail, st));
     HIPCHK(hipStreamSynchronize(st));
     g->hctl->pool_tail = tail;
     g->hctl->garbage = 0;
@@ -387,10 +410,7 @@ void reserve(cm_graph *g, int cur) {
         a.bstamp = g->bstamp;
         a.cur = cur;
         // clear counters used by the reservation (keep validation results)
-        int32_t zero = 0;
-        HIPCHK(hipMemcpyAsync(&g->ctl->vlist_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(&g->ctl->reloc_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(&g->ctl->pool_fail, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        HIPCHK(ctl_reserve_reset(g->ctl, st));
         HIPCHK(reserve_gain(a, g->grid_reg, st));
         HIPCHK(reserve_alloc_copy(a, g->grid_reg, st));
         sync_ctl(g);
@@ -461,8 +481,7 @@ int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats
     if (inserting) {
         reserve(g, cur);
     } else {
-        int32_t zero = 0;
-        HIPCHK(hipMemcpyAsync(&g->ctl->vlist_count, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+        HIPCHK(ctl_reserve_reset(g->ctl, st));
         a.bstamp = g->bstamp;
         HIPCHK(reserve_gain(a, g->grid_reg, st));  // endpoints + tombstone counts
     }
@@ -525,8 +544,8 @@ void release_all(cm_graph *g) {
         dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.fx[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
     }
     dev_free(q.cand); dev_free(q.chg); dev_free(q.chh); dev_free(q.touched);
-    dev_free(g->src_buf); dev_free(g->dst_buf); dev_free(g->scan_tmp); dev_free(g->i64_scratch);
-    dev_free(g->u64_scratch); dev_free(g->firstidx);
+    // (the small scratch buffers allocated by cm_create stay until cm_destroy)
+    dev_free(g->src_buf); dev_free(g->dst_buf); dev_free(g->scan_tmp); dev_free(g->firstidx);
     g->g = DevGraph{};
     g->b = DevBatch{};
     g->q = DevQueues{};
@@ -624,6 +643,8 @@ void cm_destroy(cm_graph *g) {
     if (!g) return;
     (void)hipStreamSynchronize(g->stream);
     release_all(g);
+    dev_free(g->i64_scratch);
+    dev_free(g->u64_scratch);
     if (g->ctl) (void)hipFree(g->ctl);
     if (g->hctl) (void)hipHostFree(g->hctl);
     if (g->hu64) (void)hipHostFree(g->hu64);
@@ -703,7 +724,7 @@ int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const i
             // control block
             HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), st));
             unsigned long long tail = (unsigned long long)total;
-            HIPCHK(hipMemcpyAsync(&g->ctl->pool_tail, &tail, sizeof(tail), hipMemcpyHostToDevice, st));
+            HIPCHK(ctl_set_pool(g->ctl, tail, st));
             HIPCHK(hipStreamSynchronize(st));
             std::memset(g->hctl, 0, sizeof(Ctl));
             g->hctl->pool_tail = tail;

@@ -53,6 +53,21 @@ __global__ void k_ctl_batch_reset(Ctl *c, int cur) {
     }
 }
 
+// Reservation counters (validation results are kept).
+__global__ void k_ctl_reserve_reset(Ctl *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->vlist_count = 0;
+        c->reloc_count = 0;
+        c->pool_fail = 0;
+    }
+}
+__global__ void k_ctl_set_pool(Ctl *c, unsigned long long tail) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->pool_tail = tail;
+        c->garbage = 0;
+    }
+}
+
 // Exclusive scan of int64 values (three passes; SCAN_TILE items per block).
 constexpr int SCAN_TILE = 1024;
 
@@ -446,27 +461,43 @@ static inline int grid_for(int64_t n, int maxb) {
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (!p) return hipErrorInvalidValue;
     k_fill_i32<<<grid_for(n, 4096), 256, 0, st>>>(p, v, n);
     return hipGetLastError();
 }
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (!p) return hipErrorInvalidValue;
     k_fill_u64<<<grid_for(n, 4096), 256, 0, st>>>(p, v, n);
     return hipGetLastError();
 }
 hipError_t fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (!p) return hipErrorInvalidValue;
     k_fill_i64<<<grid_for(n, 4096), 256, 0, st>>>(p, v, n);
     return hipGetLastError();
 }
 hipError_t ctl_batch_reset(Ctl *c, int cur, hipStream_t st) {
+    if (!c) return hipErrorInvalidValue;
     k_ctl_batch_reset<<<1, 64, 0, st>>>(c, cur);
+    return hipGetLastError();
+}
+
+hipError_t ctl_reserve_reset(Ctl *c, hipStream_t st) {
+    if (!c) return hipErrorInvalidValue;
+    k_ctl_reserve_reset<<<1, 64, 0, st>>>(c);
+    return hipGetLastError();
+}
+hipError_t ctl_set_pool(Ctl *c, unsigned long long tail, hipStream_t st) {
+    if (!c) return hipErrorInvalidValue;
+    k_ctl_set_pool<<<1, 64, 0, st>>>(c, tail);
     return hipGetLastError();
 }
 
 // in-place exclusive scan of n int64 values; *total_dev receives the sum.
 hipError_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
                               int64_t *total_dev, hipStream_t st) {
+    if (!in || !out || !tmp || !total_dev) return hipErrorInvalidValue;
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
     k_scan_reduce<<<(unsigned)nb, 256, 0, st>>>(in, n, tmp);
@@ -479,6 +510,7 @@ int64_t scan_tmp_len(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 hipError_t load_check(const int32_t *src, const int32_t *dst, int64_t m, int32_t n,
                       unsigned long long *hkey, int64_t *hval, uint32_t mask,
                       unsigned long long *first_bad, hipStream_t st) {
+    if (!src || !dst || !hkey || !hval || !first_bad) return hipErrorInvalidValue;
     k_load_hash<<<grid_for(m, 8192), 256, 0, st>>>(src, dst, m, n, hkey, hval, mask, first_bad);
     k_load_dup<<<grid_for(m, 8192), 256, 0, st>>>(src, dst, m, n, hkey, hval, mask, first_bad);
     return hipGetLastError();

@@ -8,6 +8,8 @@ hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t st);
 hipError_t fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 hipError_t ctl_batch_reset(Ctl *c, int cur, hipStream_t st);
+hipError_t ctl_reserve_reset(Ctl *c, hipStream_t st);
+hipError_t ctl_set_pool(Ctl *c, unsigned long long tail, hipStream_t st);
 hipError_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
                               int64_t *total_dev, hipStream_t st);
 int64_t scan_tmp_len(int64_t n);
