@@ -214,12 +214,19 @@ class EdgeSet:
 def _fresh_pairs(draw_fn, count, es: EdgeSet, rng):
     """Distinct non-loop pairs not in es, drawn by draw_fn(k) -> (a, b)."""
     got = np.empty(0, dtype=np.int64)
+    stale = 0
     while got.size < count:
         need = count - got.size
         a, b = draw_fn(int(need * 1.2) + 16)
         new = _simple_keys(a, b)
         new = new[~es.contains(new)]
         new = new[~np.isin(new, got, assume_unique=True)]
+        if new.size == 0:
+            stale += 1
+            if stale > 64:
+                raise ValueError(f"could not draw {count} fresh pairs (got {got.size})")
+            continue
+        stale = 0
         if new.size > need:
             new = rng.choice(new, need, replace=False)
         got = np.union1d(got, new)

@@ -109,15 +109,21 @@ def test_decompose_random(cm, dev, oracle_mod, kind):
 
 
 def _batches(ref, rng, n, count, size):
-    """Alternating insert / delete batches valid against the current graph."""
+    """Alternating insert / delete batches valid against the current graph
+    (sizes capped by the non-edges / edges available)."""
     es = graphgen.EdgeSet(*ref.edges())
     out = []
     for b in range(count):
         if b % 2 == 0:
-            s, d = graphgen.uniform_non_edges(n, size, es, rng)
+            free = n * (n - 1) // 2 - len(es)
+            if min(size, free) == 0:
+                continue
+            s, d = graphgen.uniform_non_edges(n, min(size, free), es, rng)
             es.insert(s, d)
             out.append(("insert", s, d))
         else:
+            if len(es) == 0:
+                continue
             s, d = graphgen.existing_edges(size, es, rng)
             es.delete(s, d)
             out.append(("delete", s, d))
@@ -159,6 +165,7 @@ def test_fuzz_small_graphs(cm, dev, oracle_mod, seed):
         ref = oracle_mod.DynamicGraph(n, s, d)
         mode = int(rng.integers(0, 2))
         rounds = int(rng.integers(1, 4))
+        print(f"fuzz seed {seed} trial {trial}: n={n} m={m} mode={mode} rounds={rounds}", flush=True)
         with new_graph(cm, n, s, d, dev, mode=mode, partition_rounds=rounds,
                        small_degree=int(rng.choice([1, 4, 16])), large_degree=int(rng.choice([8, 32, 4096])),
                        chunk=int(rng.choice([8, 64, 2048]))) as g:
