@@ -239,7 +239,13 @@ __device__ __forceinline__ uint32_t hash_key(unsigned long long k) {
     return mix32(h ^ (uint32_t)(k >> 32));
 }
 
-// Grid-wide barrier of a cooperative launch.
-__device__ __forceinline__ void gsync() { cooperative_groups::this_grid().sync(); }
+// Grid-wide barrier of a cooperative launch, with device-scope fences on
+// both sides so that plain stores before it are visible to plain loads after
+// it on every CU.
+__device__ __forceinline__ void gsync() {
+    __threadfence();
+    cooperative_groups::this_grid().sync();
+    __threadfence();
+}
 
 }  // namespace cm

@@ -351,8 +351,12 @@ __device__ void apply_insert(const KArgs &a, const Iter &it) {
             int32_t m = atomicAdd(&a.g.mcd[v], 1) + 1;
             if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; rv = true; }
         }
-        push_vertex(a, a.q.fq[0], &c->fq_tail[0], a.q.fh[0], &c->fh_tail[0], u, ru);
-        push_vertex(a, a.q.fq[0], &c->fq_tail[0], a.q.fh[0], &c->fh_tail[0], v, rv);
+        // Roots enter the vertex queue whatever their length: other threads
+        // may still be appending to the same list in this phase, so a chunk
+        // count taken now could be stale.  The first expansion round splits
+        // long root lists into chunks once lengths are final.
+        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
+        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv, &c->overflow);
     }
 }
 
@@ -443,6 +447,18 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
             }
         },
         [&](int32_t v, int32_t L) {
+            if (L > a.t.large_deg) {
+                // a long root list: count its CSD chunk by chunk next round
+                if (lane() == 0) {
+                    int nch = nchunks(L, a.t.chunk);
+                    int base = atomicAdd(&c->fh_tail[sn], nch);
+                    for (int q = 0; q < nch; ++q) {
+                        if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
+                        else atomicOr(&c->overflow, 1);
+                    }
+                }
+                return;
+            }
             int32_t k = g.core[v];
             int32_t pcd = 0;
             wave_walk(g, v, 0, L, [&](int32_t w, int32_t) {
@@ -478,6 +494,7 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
         if (last) {
             int32_t tot = 0;
             if (lane() == 0) {
+                __threadfence();
                 g.done[v] = 0;
                 tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }

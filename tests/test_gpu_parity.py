@@ -350,3 +350,36 @@ def test_chung_lu_full_size(cm, dev, oracle_mod):
         g.delete_edges(_t(a, dev), _t(b, dev))
         ref.delete_edges(a, b)
         check_state(g, ref, "cl full")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_root_list_grows_during_apply(cm, dev, oracle_mod, mode):
+    """A root whose own list receives many other edges of the same superior
+    edge set (it is their unconstrained endpoint): its length is final only
+    after the apply phase, and the chunked CSD count must cover every entry.
+    Two K6 (core 5) joined by a perfect matching rise to core 6; vertex 0 also
+    gains 300 edges to isolated vertices in the same iteration."""
+    a_, b_ = [], []
+    for blk in (0, 6):
+        for i in range(6):
+            for j in range(i + 1, 6):
+                a_.append(blk + i)
+                b_.append(blk + j)
+    for x in range(12, 312):  # pendants of vertex 0 (core 1)
+        a_.append(0)
+        b_.append(x)
+    n = 612
+    s = np.asarray(a_, dtype=np.int32)
+    d = np.asarray(b_, dtype=np.int32)
+    ins_a = np.asarray(list(range(6)) + [0] * 300, dtype=np.int32)
+    ins_b = np.asarray([6 + i for i in range(6)] + list(range(312, 612)), dtype=np.int32)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev, mode=mode, small_degree=4, large_degree=8, chunk=8) as g:
+        check_state(g, ref, "initial")
+        st = g.insert_edges(_t(ins_a, dev), _t(ins_b, dev))
+        ref.insert_edges(ins_a, ins_b)
+        check_state(g, ref, "after insert")
+        assert (g.cores()[:12] == 6).all()
+        g.delete_edges(_t(ins_b, dev), _t(ins_a, dev))
+        ref.delete_edges(ins_b, ins_a)
+        check_state(g, ref, "after delete")
