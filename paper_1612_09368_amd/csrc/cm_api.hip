@@ -375,7 +375,7 @@ int64_t alg_bytes(const Ctl &c, int rounds) {
 // Validate a batch already staged in g->b.src_in/dst_in (s items).  Returns
 // the number of valid items; in strict mode throws on the first bad item.
 int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *first_bad,
-                 int cur) {
+                 int cur, cm_batch_stats *stats) {
     hipStream_t st = g->stream;
     g->bstamp += 2;
     HIPCHK(ctl_batch_reset(g->ctl, cur, st));
@@ -389,6 +389,7 @@ int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *f
     check_overflow(g);
     int32_t fb = g->hctl->first_bad;
     *first_bad = fb == INT_MAX ? -1 : fb;
+    if (stats) stats->first_bad = *first_bad;
     if (fb != INT_MAX && strict) {
         int32_t code = 0;
         HIPCHK(hipMemcpyAsync(&code, g->b.err + fb, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -468,7 +469,7 @@ int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats
     bool strict = strict_override ? strict_value : g->cfg.strict != 0;
     int cur = (g->epoch + 1) & 1;
     int64_t fb = -1;
-    int64_t valid = validate(g, s, inserting, strict, &fb, cur);
+    int64_t valid = validate(g, s, inserting, strict, &fb, cur, stats);
     *dropped = s - valid;
     if (stats) stats->first_bad = fb;
     if (valid == 0) {
