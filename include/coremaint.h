@@ -80,6 +80,10 @@ typedef struct cm_config {
     int32_t small_degree;       /* lists up to this length are walked by one lane (0 = default) */
     int32_t large_degree;       /* lists above this length are split into chunks (0 = default) */
     int32_t chunk;              /* chunk length for long lists (0 = default) */
+    int32_t local_edges;        /* selection / apply steps up to this many edges run in one
+                                   workgroup instead of the whole grid (0 = default) */
+    int32_t local_items;        /* frontier steps up to this many items run in one workgroup
+                                   (0 = default) */
     int32_t timing;             /* 1 = time each maintenance launch with HIP events */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
@@ -96,6 +100,9 @@ typedef struct cm_batch_stats {
     int64_t changed;        /* sum of vertices whose core moved */
     int64_t scanned;        /* adjacency entries read by traversal phases */
     int64_t alg_bytes;      /* algorithmic HBM bytes of the maintenance launches */
+    int64_t rounds;         /* cascade rounds (expansion, eviction, peel) */
+    int64_t grid_steps;     /* steps run by the whole grid (each ends in a grid barrier) */
+    int64_t local_steps;    /* steps run inside one workgroup */
     int32_t launches;       /* maintenance kernel launches */
     int32_t pad0;
     double kernel_ms;       /* summed HIP-event time of those launches (timing = 1) */

@@ -43,6 +43,8 @@ class Config(ctypes.Structure):
         ("small_degree", ctypes.c_int32),
         ("large_degree", ctypes.c_int32),
         ("chunk", ctypes.c_int32),
+        ("local_edges", ctypes.c_int32),
+        ("local_items", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
@@ -61,6 +63,9 @@ class BatchStats(ctypes.Structure):
         ("changed", ctypes.c_int64),
         ("scanned", ctypes.c_int64),
         ("alg_bytes", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("grid_steps", ctypes.c_int64),
+        ("local_steps", ctypes.c_int64),
         ("launches", ctypes.c_int32),
         ("pad0", ctypes.c_int32),
         ("kernel_ms", ctypes.c_double),
@@ -151,7 +156,7 @@ class Graph:
 
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
-                 timing=False, stream=None):
+                 local_edges=0, local_items=0, timing=False, stream=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -164,6 +169,8 @@ class Graph:
         cfg.small_degree = small_degree
         cfg.large_degree = large_degree
         cfg.chunk = chunk
+        cfg.local_edges = local_edges
+        cfg.local_items = local_items
         cfg.timing = 1 if timing else 0
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()

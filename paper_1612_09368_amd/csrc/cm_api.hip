@@ -38,6 +38,7 @@ struct cm_graph {
     DevBatch b{};
     DevQueues q{};
     Ctl *ctl = nullptr;       // device
+    Bar *bar = nullptr;       // device grid-barrier state
     Ctl *hctl = nullptr;      // pinned host mirror
     int32_t batch_cap = 0;    // capacity of batch arrays
     int32_t hash_cap = 0;     // allocated hash slots
@@ -118,7 +119,7 @@ void require_ptrs(cm_graph *g, std::initializer_list<const void *> ps, const cha
 }
 
 KArgs make_args(cm_graph *g) {
-    require_ptrs(g, {g->ctl, g->i64_scratch, g->u64_scratch}, "control block");
+    require_ptrs(g, {g->ctl, g->bar, g->i64_scratch, g->u64_scratch}, "control block");
     if (g->loaded) {
         const DevGraph &d = g->g;
         require_ptrs(g, {d.off, d.len, d.cap, d.nbr, d.core, d.mcd, d.stamp, d.chg, d.cd, d.dec,
@@ -136,12 +137,26 @@ KArgs make_args(cm_graph *g) {
     a.q = g->q;
     a.t = g->tune;
     a.ctl = g->ctl;
+    a.bar = g->bar;
     return a;
 }
 
 void sync_ctl(cm_graph *g) {
     HIPCHK(hipMemcpyAsync(g->hctl, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
+}
+
+// After a cooperative launch: a grid barrier that gave up waiting (a
+// workgroup never arrived) poisons the handle.
+void check_abort(cm_graph *g) {
+    unsigned int ab = 0;
+    HIPCHK(hipMemcpyAsync(&ab, &g->bar->abort[0], sizeof(ab), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (ab) {
+        g->poisoned = true;
+        g->err = "internal: grid barrier wait gave up";
+        throw Fail{CM_E_INTERNAL};
+    }
 }
 
 void check_overflow(cm_graph *g) {
@@ -358,6 +373,9 @@ void fill_stats(cm_graph *g, cm_batch_stats *st, int64_t applied, int64_t droppe
     st->evicted = (int64_t)c.st_evicted;
     st->changed = (int64_t)c.st_changed;
     st->scanned = (int64_t)c.st_scanned;
+    st->rounds = (int64_t)c.st_rounds;
+    st->grid_steps = (int64_t)c.st_grid_steps;
+    st->local_steps = (int64_t)c.st_local_steps;
 }
 
 // Algorithmic bytes of the maintenance launches of a batch: what the method
@@ -440,6 +458,7 @@ void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
         if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
         ++launches;
         sync_ctl(g);
+        check_abort(g);
         check_overflow(g);
         if (g->cfg.timing) {
             float ms = 0.f;
@@ -614,16 +633,20 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 4096;
         g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 2048;
         g->tune.rounds = g->cfg.partition_rounds > 0 ? std::min(g->cfg.partition_rounds, 8) : 1;
+        g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 8192;
+        g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 1024;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
         HIPCHK(coop_occupancy(0, &bpc_m));
         HIPCHK(coop_occupancy(1, &bpc_d));
-        int want = g->cfg.blocks_per_cu > 0 ? g->cfg.blocks_per_cu : 2;
+        int want = g->cfg.blocks_per_cu > 0 ? g->cfg.blocks_per_cu : 1;
         g->coop_maint = g->num_cu * std::max(1, std::min(want, bpc_m));
         g->coop_dec = g->num_cu * std::max(1, std::min(want, bpc_d));
         g->grid_reg = g->num_cu * 8;
         dev_alloc(g, &g->ctl, 1);
         HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
+        dev_alloc(g, &g->bar, 1);
+        HIPCHK(hipMemsetAsync(g->bar, 0, sizeof(Bar), g->stream));
         HIPCHK(hipHostMalloc((void **)&g->hctl, sizeof(Ctl), hipHostMallocDefault));
         std::memset(g->hctl, 0, sizeof(Ctl));
         HIPCHK(hipHostMalloc((void **)&g->hu64, 4 * sizeof(unsigned long long), hipHostMallocDefault));
@@ -647,6 +670,7 @@ void cm_destroy(cm_graph *g) {
     dev_free(g->i64_scratch);
     dev_free(g->u64_scratch);
     if (g->ctl) (void)hipFree(g->ctl);
+    if (g->bar) (void)hipFree(g->bar);
     if (g->hctl) (void)hipHostFree(g->hctl);
     if (g->hu64) (void)hipHostFree(g->hu64);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -765,10 +789,14 @@ int cm_core_decompose(cm_graph *g, cm_batch_stats *stats) {
         if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
         HIPCHK(mcd_init(a, g->grid_reg, st));
         sync_ctl(g);
+        check_abort(g);
         check_overflow(g);
         if (stats) {
             stats->scanned = (int64_t)g->hctl->st_scanned;
             stats->iterations = g->hctl->dec_rounds;
+            stats->rounds = g->hctl->dec_rounds;
+            stats->grid_steps = (int64_t)g->hctl->st_grid_steps;
+            stats->local_steps = (int64_t)g->hctl->st_local_steps;
             stats->launches = 1;
             if (g->cfg.timing) {
                 float ms = 0.f;

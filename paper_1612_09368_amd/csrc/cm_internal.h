@@ -10,7 +10,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
 
 namespace cm {
@@ -50,7 +49,8 @@ struct Ctl {
     int32_t min_deg[3];      // decomposition: smallest remaining degree (rotating)
     int32_t kmax;            // decomposition: largest core number
     int32_t dec_rounds;      // decomposition: frontier rounds
-    int32_t pad[2];
+    int32_t ipub[2][2];      // iteration step machine: (step, round) published by workgroup 0
+    int32_t dpub[2][5];      // decomposition step machine: (step, k, j, f, kmax)
     unsigned long long pool_tail;     // next free adjacency slot
     unsigned long long garbage;       // slots abandoned by relocations
     // statistics (summed over the iterations of a batch)
@@ -61,6 +61,21 @@ struct Ctl {
     unsigned long long st_evicted;
     unsigned long long st_changed;
     unsigned long long st_scanned;
+    unsigned long long st_rounds;       // cascade rounds (expansion, eviction, peel)
+    unsigned long long st_grid_steps;   // steps run by the whole grid
+    unsigned long long st_local_steps;  // steps run inside one workgroup
+};
+
+// Grid barrier state: one arrival counter per group of workgroups (a group is
+// the workgroups that share blockIdx % NGRP, i.e. one XCD under round-robin
+// dispatch), one counter for the groups, one generation word; each on its
+// own 128-byte line.
+constexpr int NGRP = 8;
+struct Bar {
+    unsigned int grp[NGRP * 32];
+    unsigned int top[32];
+    unsigned int gen[32];
+    unsigned int abort[32];   // set when a wait gives up; later barriers return at once
 };
 
 // Per-vertex device arrays plus the adjacency pool.
@@ -132,7 +147,11 @@ struct Tune {
     int32_t large_deg;   // longer lists are chunked
     int32_t chunk;       // chunk length
     int32_t rounds;      // selection rounds per iteration
+    int32_t local_edges; // partition / apply steps up to this many edges run in one workgroup
+    int32_t local_items; // frontier steps up to this many items run in one workgroup
 };
+
+constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
 
 struct KArgs {
     DevGraph g;
@@ -140,6 +159,7 @@ struct KArgs {
     DevQueues q;
     Tune t;
     Ctl *ctl;
+    Bar *bar;
     int32_t inserting;   // 1 = insertion batch, 0 = deletion batch
     int32_t max_iters;   // iterations this launch may run
     int32_t s;           // batch items
@@ -239,13 +259,59 @@ __device__ __forceinline__ uint32_t hash_key(unsigned long long k) {
     return mix32(h ^ (uint32_t)(k >> 32));
 }
 
-// Grid-wide barrier of a cooperative launch, with device-scope fences on
-// both sides so that plain stores before it are visible to plain loads after
-// it on every CU.
-__device__ __forceinline__ void gsync() {
-    __threadfence();
-    cooperative_groups::this_grid().sync();
-    __threadfence();
+// A team is the set of threads that shares one step: the whole grid or one
+// workgroup.  Loops stride by the team size; `lead` does the team's
+// bookkeeping.
+struct Team {
+    int rank;
+    int size;
+    __device__ __forceinline__ int wave() const { return rank / WAVE; }
+    __device__ __forceinline__ int nwaves() const { return size / WAVE; }
+    __device__ __forceinline__ bool lead() const { return rank == 0; }
+};
+__device__ __forceinline__ Team grid_team() { return Team{gtid(), gthreads()}; }
+__device__ __forceinline__ Team block_team() { return Team{(int)threadIdx.x, (int)blockDim.x}; }
+
+// Grid-wide barrier of a cooperative launch (all workgroups co-resident).
+// Thread 0 of each workgroup arrives on its group counter; the last arrival
+// of a group arrives on the top counter; the last group bumps the generation
+// word that everyone waits on.  Device-scope release on arrival and acquire
+// on departure make plain stores before the barrier visible after it.
+__device__ __forceinline__ void gbar(Bar *b) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned nb = gridDim.x;
+        const unsigned grp = blockIdx.x % NGRP;
+        const unsigned members = nb / NGRP + (grp < nb % NGRP ? 1u : 0u);
+        const unsigned ngroups = nb < (unsigned)NGRP ? nb : (unsigned)NGRP;
+        const unsigned g0 = __hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned a = __hip_atomic_fetch_add(&b->grp[grp * 32], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == members - 1u) {
+            __hip_atomic_store(&b->grp[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned t = __hip_atomic_fetch_add(&b->top[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1u) {
+                __hip_atomic_store(&b->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&b->gen[0], g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        // Bounded wait (about a second): a workgroup that never arrives is a
+        // bug; the barrier then trips the abort word instead of hanging, and
+        // the drivers stop at their next check.
+        unsigned polls = 0;
+        while (__hip_atomic_load(&b->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+            if (__hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(2);
+            if (++polls > (1u << 25)) {
+                __hip_atomic_store(&b->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool bar_aborted(Bar *b) {
+    return __hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
 }  // namespace cm

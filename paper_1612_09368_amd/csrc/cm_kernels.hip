@@ -49,6 +49,7 @@ __global__ void k_ctl_batch_reset(Ctl *c, int cur) {
         c->dec_rounds = 0;
         c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
         c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
+        c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
         (void)cur;
     }
 }
@@ -224,7 +225,7 @@ __global__ void k_scatter(const int32_t *src, const int32_t *dst, int64_t m, con
 __global__ void k_count_live(KArgs a, int32_t *cnt) {
     const DevGraph &g = a.g;
     for_all_vertices(
-        g.n_ids, g, a.t.small_deg,
+        grid_team(), g.n_ids, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {
             const int32_t *p = g.nbr + g.off[v];
             int32_t c = 0;
@@ -299,7 +300,7 @@ __global__ void k_dec_prep(KArgs a) {
     const DevGraph &g = a.g;
     Ctl *c = a.ctl;
     for_all_vertices(
-        g.n_ids, g, a.t.small_deg,
+        grid_team(), g.n_ids, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {
             const int32_t *p = g.nbr + g.off[v];
             int32_t d = 0;
@@ -320,12 +321,16 @@ __global__ void k_dec_prep(KArgs a) {
     }
 }
 
-__global__ void k_decompose(KArgs a) { decompose(a); }
+__global__ void __launch_bounds__(COOP_THREADS) k_decompose(KArgs a) {
+    long long scanned = 0;
+    decompose(a, scanned);
+    flush_stat(&a.ctl->st_scanned, scanned);
+}
 
 __global__ void k_mcd_init(KArgs a) {
     const DevGraph &g = a.g;
     for_all_vertices(
-        g.n_ids, g, a.t.small_deg,
+        grid_team(), g.n_ids, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {
             int32_t cv = g.core[v];
             const int32_t *p = g.nbr + g.off[v];
@@ -350,15 +355,25 @@ __global__ void k_mcd_init(KArgs a) {
 // ---------------------------------------------------------------------------
 // Batch validation, reservation, compaction, maintenance
 // ---------------------------------------------------------------------------
-__global__ void k_val_canon(KArgs a) { val_canon(a); }
-__global__ void k_val_dup_mark(KArgs a) { val_dup_mark(a); }
-__global__ void k_val_scan(KArgs a) { val_scan(a); }
-__global__ void k_val_final(KArgs a) { val_final(a); }
-__global__ void k_res_gain(KArgs a) { res_gain(a); }
-__global__ void k_res_alloc(KArgs a) { res_alloc(a); }
-__global__ void k_res_copy(KArgs a) { res_copy(a); }
-__global__ void k_del_compact(KArgs a) { del_compact(a); }
-__global__ void k_maintain(KArgs a) { run_iterations(a); }
+__global__ void k_val_canon(KArgs a) { val_canon(a, grid_team()); }
+__global__ void k_val_dup_mark(KArgs a) { val_dup_mark(a, grid_team()); }
+__global__ void k_val_scan(KArgs a) { val_scan(a, grid_team()); }
+__global__ void k_val_final(KArgs a) { val_final(a, grid_team()); }
+__global__ void k_res_gain(KArgs a) { res_gain(a, grid_team()); }
+__global__ void k_res_alloc(KArgs a) { res_alloc(a, grid_team()); }
+__global__ void k_res_copy(KArgs a) { res_copy(a, grid_team()); }
+__global__ void k_del_compact(KArgs a) { del_compact(a, grid_team()); }
+__global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
+    int32_t ep = ld_acq(&a.ctl->epoch);
+    long long scanned = 0;
+    int pubs = 0;
+    int n = run_iterations(a, a.max_iters, ep, scanned, pubs);
+    flush_stat(&a.ctl->st_scanned, scanned);
+    if (gtid() == 0) {
+        a.ctl->epoch = ep;
+        a.ctl->iters_done = n;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Vertex operations
@@ -551,7 +566,7 @@ hipError_t export_edges(const KArgs &a, int32_t *xs, int32_t *ys, int64_t cap,
 static hipError_t coop(const void *fn, const KArgs &a, int blocks, hipStream_t st) {
     KArgs copy = a;
     void *args[] = {&copy};
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st);
+    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(COOP_THREADS), args, 0, st);
 }
 
 hipError_t dec_prep(const KArgs &a, int blocks, hipStream_t st) {
@@ -624,7 +639,7 @@ hipError_t vdel_finish(const KArgs &a, const int32_t *ids, int32_t c, hipStream_
 
 hipError_t coop_occupancy(int which, int *blocks_per_cu) {
     const void *fn = which == 0 ? (const void *)k_maintain : (const void *)k_decompose;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, COOP_THREADS, 0);
 }
 
 }  // namespace cm

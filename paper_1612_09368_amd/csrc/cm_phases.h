@@ -41,10 +41,10 @@ __device__ __forceinline__ void count_agg(int32_t *ctr, bool pred) {
 
 // V1: range / dead / self-loop checks, canonical (min, max), hash insert
 // (the smallest item index of each pair wins the slot).
-__device__ void val_canon(const KArgs &a) {
+__device__ void val_canon(const KArgs &a, const Team &T) {
     const int32_t n = a.g.n_ids;
     const uint32_t mask = (uint32_t)a.b.hcap - 1u;
-    for (int32_t i = gtid(); i < a.s; i += gthreads()) {
+    for (int32_t i = T.rank; i < a.s; i += T.size) {
         int32_t u = a.b.src_in[i], v = a.b.dst_in[i];
         int32_t e = 0;
         if (u < 0 || v < 0 || u >= n || v >= n) e = ST_RANGE;
@@ -88,8 +88,8 @@ __device__ __forceinline__ void mark_scan(const KArgs &a, int32_t x) {
 // V2: duplicates inside the batch; choose the lists the locate scan reads
 // (insertion: the shorter endpoint list is enough to test existence;
 // deletion: both lists, to find both slots).
-__device__ void val_dup_mark(const KArgs &a) {
-    for (int32_t i = gtid(); i < a.s; i += gthreads()) {
+__device__ void val_dup_mark(const KArgs &a, const Team &T) {
+    for (int32_t i = T.rank; i < a.s; i += T.size) {
         int32_t e = a.b.err[i];
         if (e != 0) continue;
         if (a.b.hval[a.b.hslot[i]] != i) {
@@ -109,10 +109,10 @@ __device__ void val_dup_mark(const KArgs &a) {
 // V3: locate scan.  Each (vertex, chunk) item is read by one wave; every
 // live neighbour probes the batch hash.  Insertion: a hit means the edge
 // exists.  Deletion: a hit records the slot of the entry.
-__device__ void val_scan(const KArgs &a) {
+__device__ void val_scan(const KArgs &a, const Team &T) {
     const uint32_t mask = (uint32_t)a.b.hcap - 1u;
     const int32_t n = qlen(&a.ctl->scan_tail, a.b.scap);
-    for_chunks(a.b.scanq, n, a.g, a.t.chunk,
+    for_chunks(T, a.b.scanq, n, a.g, a.t.chunk,
                [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
                    const int64_t base = a.g.off[x];
                    wave_walk(a.g, x, lo, hi, [&](int32_t w, int32_t slot) {
@@ -141,8 +141,8 @@ __device__ void val_scan(const KArgs &a) {
 
 // V4: missing edges, smallest invalid index, emit valid item indices into
 // the remaining list `cur`.
-__device__ void val_final(const KArgs &a) {
-    for (int32_t i = gtid(); i < a.s; i += gthreads()) {
+__device__ void val_final(const KArgs &a, const Team &T) {
+    for (int32_t i = T.rank; i < a.s; i += T.size) {
         int32_t e = a.b.err[i];
         if (!a.inserting && e == 0 && (a.b.su[i] < 0 || a.b.sv[i] < 0)) {
             e = ST_MISSING;
@@ -166,10 +166,10 @@ __device__ __forceinline__ void mark_endpoint(const KArgs &a, int32_t x) {
 }
 
 // R1: per-vertex count of batch edges (gain) and the distinct endpoints.
-__device__ void res_gain(const KArgs &a) {
+__device__ void res_gain(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->rem_count[a.cur], a.b.cap);
     const int32_t *R = a.b.rem[a.cur];
-    for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
+    for (int32_t idx = T.rank; idx < n; idx += T.size) {
         int32_t i = R[idx];
         mark_endpoint(a, a.b.eu[i]);
         mark_endpoint(a, a.b.ev[i]);
@@ -177,9 +177,9 @@ __device__ void res_gain(const KArgs &a) {
 }
 
 // R2: a list that cannot take its gain moves to a spill block at the pool tail.
-__device__ void res_alloc(const KArgs &a) {
+__device__ void res_alloc(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->vlist_count, a.g.n_cap);
-    for (int32_t j = gtid(); j < n; j += gthreads()) {
+    for (int32_t j = T.rank; j < n; j += T.size) {
         int32_t x = a.b.vlist[j];
         int32_t need = a.g.len[x] + a.g.gain[x];
         a.g.gain[x] = 0;
@@ -200,9 +200,9 @@ __device__ void res_alloc(const KArgs &a) {
 }
 
 // R3: copy relocated lists (one wave per list).
-__device__ void res_copy(const KArgs &a) {
+__device__ void res_copy(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->reloc_count, a.g.n_cap);
-    for (int32_t j = gwave(); j < n; j += nwaves()) {
+    for (int32_t j = T.wave(); j < n; j += T.nwaves()) {
         int32_t x = a.b.reloc[j];
         int32_t L = a.g.len[x];
         const int32_t *src = a.g.nbr + a.g.off[x];
@@ -218,9 +218,9 @@ __device__ void res_copy(const KArgs &a) {
 
 // After a deletion batch: squeeze tombstones out of the touched lists whose
 // tombstone share is large (one wave per list, in place, order kept).
-__device__ void del_compact(const KArgs &a) {
+__device__ void del_compact(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->vlist_count, a.g.n_cap);
-    for (int32_t j = gwave(); j < n; j += nwaves()) {
+    for (int32_t j = T.wave(); j < n; j += T.nwaves()) {
         int32_t x = a.b.vlist[j];
         int32_t L = a.g.len[x];
         int32_t T = a.g.gain[x];
@@ -240,14 +240,31 @@ __device__ void del_compact(const KArgs &a) {
     }
 }
 
+
 // ===========================================================================
-// One iteration = one superior edge set (Algorithm 1 / Algorithm 5 loop body)
+// One iteration = one superior edge set (the loop body of Algorithms 1 and 5)
+//
+// An iteration is a sequence of steps: selection claim / select rounds,
+// apply, cascade rounds (expansion and eviction for insertion, peel for
+// deletion), core update, SD maintenance.  Every step is a team-strided
+// loop; the driver runs a step on the whole grid (then a grid barrier) or,
+// when it is small, inside workgroup 0 alone (then a workgroup barrier),
+// continuing locally until a large step comes up.  All decisions read
+// counters that were published before the last barrier, so every workgroup
+// takes the same path.
 // ===========================================================================
 
 struct Iter {
     int32_t ep;    // iteration stamp
     int32_t cur;   // remaining list read by this iteration
     int32_t n_r;   // its length
+};
+
+enum StepKind : int32_t { S_CLAIM = 0, S_SELECT, S_APPLY, S_EXPAND, S_EVICT, S_PEEL, S_CORE, S_MCD, S_DONE };
+
+struct PC {
+    int32_t step;
+    int32_t r;
 };
 
 __device__ __forceinline__ bool matched_before(uint32_t m, int32_t ep, int rounds, int r) {
@@ -257,17 +274,17 @@ __device__ __forceinline__ bool matched_before(uint32_t m, int32_t ep, int round
 }
 
 // Selection of a superior edge set from the remaining edges (Algorithms 1-2
-// and 5, lines selecting E_k for every level; Definition of the k-superior
-// edge set).  An edge <u,v> has core number k = min(core u, core v); the
-// endpoints with core k are its constrained endpoints.  Every constrained
-// endpoint keeps at most one selected edge: each edge claims its constrained
-// endpoints with a pseudo-random priority and is selected when it wins all
-// of them (several claim rounds fill in more edges).  Levels are not
-// separated: a vertex is constrained only at its own level, so one pass
-// builds the union of all k-superior edge sets.
-__device__ void part_claim(const KArgs &a, const Iter &it, int r) {
+// and 5; Definition of the k-superior edge set).  An edge <u,v> has core
+// number k = min(core u, core v); the endpoints with core k are its
+// constrained endpoints.  Every constrained endpoint keeps at most one
+// selected edge: each edge claims its constrained endpoints with a
+// pseudo-random priority and is selected when it wins all of them (further
+// claim rounds fill in edges whose endpoints are still free).  A vertex is
+// constrained only at its own level, so one pass builds the union of all
+// k-superior edge sets.
+__device__ void part_claim(const KArgs &a, const Iter &it, int r, const Team &T) {
     Ctl *c = a.ctl;
-    if (r == 0 && gtid() == 0) {
+    if (r == 0 && T.lead()) {
         c->sel_count = 0;
         c->rem_count[it.cur ^ 1] = 0;
         for (int j = 0; j < 3; ++j) {
@@ -276,11 +293,13 @@ __device__ void part_claim(const KArgs &a, const Iter &it, int r) {
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
         c->touched_count = 0; c->changed_count = 0;
+        c->st_iters += 1;
+        c->st_remaining += (unsigned long long)it.n_r;
     }
     const int32_t *R = a.b.rem[it.cur];
     const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds + (uint32_t)r;
     const unsigned long long hi = (unsigned long long)(0xFFFFFFFFu - sr) << 32;
-    for (int32_t idx = gtid(); idx < it.n_r; idx += gthreads()) {
+    for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
         int32_t i = R[idx];
         if (r > 0 && a.b.esel[i] == it.ep) continue;
         int32_t u = a.b.eu[i], v = a.b.ev[i];
@@ -296,13 +315,14 @@ __device__ void part_claim(const KArgs &a, const Iter &it, int r) {
     }
 }
 
-__device__ void part_select(const KArgs &a, const Iter &it, int r, bool last) {
+__device__ void part_select(const KArgs &a, const Iter &it, int r, const Team &T) {
     Ctl *c = a.ctl;
+    const bool last = r == a.t.rounds - 1;
     const int32_t *R = a.b.rem[it.cur];
     const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds + (uint32_t)r;
     const unsigned long long hi = (unsigned long long)(0xFFFFFFFFu - sr) << 32;
     const uint32_t mstamp = sr + 1u;
-    for (int32_t idx = gtid(); idx < it.n_r; idx += gthreads()) {
+    for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
         int32_t i = R[idx];
         if (r > 0 && a.b.esel[i] == it.ep) continue;  // taken in an earlier round
         int32_t u = a.b.eu[i], v = a.b.ev[i];
@@ -324,14 +344,14 @@ __device__ void part_select(const KArgs &a, const Iter &it, int r, bool last) {
     }
 }
 
-// Insert the selected set into G (Algorithm 1, insertion of the union of
-// E_k) and update SD of the constrained endpoints; roots of the traversal
-// are constrained endpoints whose new SD exceeds their core (a vertex with
-// SD <= k cannot rise, Section IV-B).
-__device__ void apply_insert(const KArgs &a, const Iter &it) {
+// Insert the selected set into G (Algorithm 1) and update SD of the
+// constrained endpoints; a constrained endpoint whose new SD exceeds its core
+// is a root of the traversal (a vertex with SD <= k cannot rise).
+__device__ void apply_insert(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
-    for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
+    if (T.lead()) c->st_selected += (unsigned long long)n;
+    for (int32_t idx = T.rank; idx < n; idx += T.size) {
         int32_t i = a.b.sel[idx];
         int32_t u = a.b.eu[i], v = a.b.ev[i];
         int32_t cu = a.g.core[u], cv = a.g.core[v];
@@ -352,7 +372,7 @@ __device__ void apply_insert(const KArgs &a, const Iter &it) {
             if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; rv = true; }
         }
         // Roots enter the vertex queue whatever their length: other threads
-        // may still be appending to the same list in this phase, so a chunk
+        // may still be appending to the same list in this step, so a chunk
         // count taken now could be stale.  The first expansion round splits
         // long root lists into chunks once lengths are final.
         push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
@@ -363,10 +383,11 @@ __device__ void apply_insert(const KArgs &a, const Iter &it) {
 // Delete the selected set from G (Algorithm 5) and update SD of the
 // constrained endpoints; a root whose SD on G minus the set falls below its
 // core is peeled at once (Algorithm 6, test cd < k).
-__device__ void apply_delete(const KArgs &a, const Iter &it) {
+__device__ void apply_delete(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
-    for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
+    if (T.lead()) c->st_selected += (unsigned long long)n;
+    for (int32_t idx = T.rank; idx < n; idx += T.size) {
         int32_t i = a.b.sel[idx];
         int32_t u = a.b.eu[i], v = a.b.ev[i];
         int32_t cu = a.g.core[u], cv = a.g.core[v];
@@ -390,18 +411,18 @@ __device__ void apply_delete(const KArgs &a, const Iter &it) {
 }
 
 // Positive traversal (Algorithm 3) as level-synchronous rounds over all
-// levels at once.  A visited vertex v computes cd[v] = CSD(v); if CSD(v) > k
-// it visits its core-k neighbours w with SD(w) > k, otherwise it is queued
-// for eviction (Lemma on CSD: CSD <= k keeps v out of the (k+1)-core).
-// Every candidate's counter counts exactly its candidate neighbours at level
-// k plus its higher-core neighbours, so the later peel is exact whatever the
+// levels at once.  A visited vertex v gets cd[v] = CSD(v); if CSD(v) > k it
+// visits its core-k neighbours w with SD(w) > k, otherwise it is queued for
+// eviction (the lemma on CSD: CSD <= k keeps v out of the (k+1)-core).  A
+// candidate's counter then counts exactly its higher-core neighbours plus its
+// candidate neighbours at level k, so the later peel is exact whatever the
 // visiting order.
 __device__ __forceinline__ bool is_support(const DevGraph &g, int32_t w, int32_t k) {
     int32_t cw = g.core[w];
     return cw > k || (cw == k && g.mcd[w] > k);
 }
 
-__device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &scanned) {
+__device__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -409,7 +430,10 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
     const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
     const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
     const int32_t nx = qlen(&c->fx_tail[sc], a.q.hcap);
-    if (gtid() == 0) { c->fq_tail[sx] = 0; c->fh_tail[sx] = 0; c->fx_tail[sx] = 0; }
+    if (T.lead()) {
+        c->fq_tail[sx] = 0; c->fh_tail[sx] = 0; c->fx_tail[sx] = 0;
+        c->st_rounds += 1;
+    }
     const int32_t ep = it.ep;
 
     auto claim = [&](int32_t w, int32_t k) -> bool {
@@ -427,7 +451,7 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
     };
 
     for_vertices(
-        a.q.fq[bc], nq, g, a.t.small_deg,
+        T, a.q.fq[bc], nq, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {
             int32_t k = g.core[v];
             const int32_t *p = g.nbr + g.off[v];
@@ -476,7 +500,7 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
         });
 
     // CSD of long lists, chunk by chunk; the last chunk to finish decides.
-    for_chunks(a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
+    for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
         int32_t k = g.core[v];
         int32_t part = 0;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) {
@@ -515,7 +539,7 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
     });
 
     // Expansion of long lists whose CSD exceeded k (decided last round).
-    for_chunks(a.q.fx[bc], nx, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
+    for_chunks(T, a.q.fx[bc], nx, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[v];
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { push_next(w, claim(w, k)); });
@@ -525,14 +549,17 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, long long &s
 // Negative traversal (Algorithm 4) as rounds: an evicted candidate lowers the
 // counter of each candidate neighbour at its level; a neighbour is evicted
 // exactly once, when its counter crosses from k+1 to k.
-__device__ void evict_round(const KArgs &a, const Iter &it, int r, long long &scanned) {
+__device__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
     const int bc = r & 1, bn = bc ^ 1;
     const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
     const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
-    if (gtid() == 0) { c->eq_tail[sx] = 0; c->eh_tail[sx] = 0; }
+    if (T.lead()) {
+        c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
+        c->st_rounds += 1;
+    }
     const int32_t ep = it.ep;
     auto hit = [&](int32_t w, int32_t k) -> bool {
         if (w < 0 || g.core[w] != k || g.stamp[w] != ep) return false;
@@ -542,7 +569,7 @@ __device__ void evict_round(const KArgs &a, const Iter &it, int r, long long &sc
         push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
     for_vertices(
-        a.q.eq[bc], nq, g, a.t.small_deg,
+        T, a.q.eq[bc], nq, g, a.t.small_deg,
         [&](int32_t x, int32_t L) {
             int32_t k = g.core[x];
             const int32_t *p = g.nbr + g.off[x];
@@ -557,7 +584,7 @@ __device__ void evict_round(const KArgs &a, const Iter &it, int r, long long &sc
             if (lane() == 0) scanned += L;
             wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
         });
-    for_chunks(a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+    for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
@@ -569,14 +596,17 @@ __device__ void evict_round(const KArgs &a, const Iter &it, int r, long long &sc
 // is cd = SD(w) - dec[w] (SD on G minus the set) and w is peeled exactly
 // once, when cd crosses from k to k-1.  dec is cleared after the iteration
 // through the `touched` list.
-__device__ void peel_round(const KArgs &a, const Iter &it, int r, long long &scanned) {
+__device__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
     const int bc = r & 1, bn = bc ^ 1;
     const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
     const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
-    if (gtid() == 0) { c->eq_tail[sx] = 0; c->eh_tail[sx] = 0; }
+    if (T.lead()) {
+        c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
+        c->st_rounds += 1;
+    }
     const int32_t ep = it.ep;
     auto body = [&](int32_t w, int32_t k) {
         bool first = false, fire = false;
@@ -591,7 +621,7 @@ __device__ void peel_round(const KArgs &a, const Iter &it, int r, long long &sca
         push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
     for_vertices(
-        a.q.eq[bc], nq, g, a.t.small_deg,
+        T, a.q.eq[bc], nq, g, a.t.small_deg,
         [&](int32_t x, int32_t L) {
             int32_t k = g.core[x];
             const int32_t *p = g.nbr + g.off[x];
@@ -603,7 +633,7 @@ __device__ void peel_round(const KArgs &a, const Iter &it, int r, long long &sca
             if (lane() == 0) scanned += L;
             wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { body(w, k); });
         });
-    for_chunks(a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+    for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
@@ -611,13 +641,14 @@ __device__ void peel_round(const KArgs &a, const Iter &it, int r, long long &sca
 }
 
 // Core update (Algorithm 1: +1 for every surviving candidate; Algorithm 5:
-// -1 for every peeled vertex).  SD of a moved vertex is rebuilt next phase.
-__device__ void apply_core(const KArgs &a, const Iter &it) {
+// -1 for every peeled vertex).  SD of a moved vertex is rebuilt next step.
+__device__ void apply_core(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     if (a.inserting) {
         const int32_t n = qlen(&c->cand_count, a.q.vcap);
-        for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
+        if (T.lead()) c->st_candidates += (unsigned long long)n;
+        for (int32_t idx = T.rank; idx < n; idx += T.size) {
             int32_t v = a.q.cand[idx];
             int32_t k = g.core[v];
             bool up = g.cd[v] > k;
@@ -631,15 +662,19 @@ __device__ void apply_core(const KArgs &a, const Iter &it) {
         }
     } else {
         const int32_t n = qlen(&c->chg_count, a.q.vcap);
-        for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
+        const int32_t nt = qlen(&c->touched_count, a.q.vcap);
+        if (T.lead()) {
+            atomicAdd(&c->changed_count, n);
+            c->st_candidates += (unsigned long long)nt;
+        }
+        for (int32_t idx = T.rank; idx < n; idx += T.size) {
             int32_t v = a.q.chg[idx];
             g.core[v] -= 1;
             g.chg[v] = it.ep;
             g.mcd[v] = 0;
         }
-        if (gtid() == 0) atomicAdd(&c->changed_count, n);
         const int32_t nh = qlen(&c->chh_count, a.q.hcap);
-        for (int32_t idx = gtid(); idx < nh; idx += gthreads()) {
+        for (int32_t idx = T.rank; idx < nh; idx += T.size) {
             int64_t item = a.q.chh[idx];
             bool first = item_c(item) == 0;
             if (first) {
@@ -650,19 +685,23 @@ __device__ void apply_core(const KArgs &a, const Iter &it) {
             }
             count_agg(&c->changed_count, first);
         }
-        const int32_t nt = qlen(&c->touched_count, a.q.vcap);
-        for (int32_t idx = gtid(); idx < nt; idx += gthreads()) g.dec[a.q.touched[idx]] = 0;
+        for (int32_t idx = T.rank; idx < nt; idx += T.size) g.dec[a.q.touched[idx]] = 0;
     }
 }
 
 // SD maintenance after the core update: a moved vertex recounts SD from its
 // list; an unmoved neighbour w gains (insert) or loses (delete) one when the
 // moved vertex crossed w's core.
-__device__ void mcd_phase(const KArgs &a, const Iter &it, long long &scanned) {
+__device__ void mcd_phase(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
     const bool ins = a.inserting != 0;
+    if (T.lead()) {
+        unsigned long long ch = (unsigned long long)ld_acq(&c->changed_count);
+        c->st_changed += ch;
+        c->st_evicted += ins ? (unsigned long long)ld_acq(&c->cand_count) - ch : ch;
+    }
     auto nb = [&](int32_t w, int32_t cv) -> int32_t {
         if (w < 0) return 0;
         int32_t cw = g.core[w];
@@ -674,7 +713,7 @@ __device__ void mcd_phase(const KArgs &a, const Iter &it, long long &scanned) {
     };
     const int32_t n = qlen(&c->chg_count, a.q.vcap);
     for_vertices(
-        a.q.chg, n, g, a.t.small_deg,
+        T, a.q.chg, n, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {
             int32_t cv = g.core[v];
             const int32_t *p = g.nbr + g.off[v];
@@ -691,7 +730,7 @@ __device__ void mcd_phase(const KArgs &a, const Iter &it, long long &scanned) {
             if (lane() == 0) { g.mcd[v] = cnt; scanned += L; }
         });
     const int32_t nh = qlen(&c->chh_count, a.q.hcap);
-    for_chunks(a.q.chh, nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
+    for_chunks(T, a.q.chh, nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
         int32_t cv = g.core[v];
         int32_t cnt = 0;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { cnt += nb(w, cv); });
@@ -700,77 +739,135 @@ __device__ void mcd_phase(const KArgs &a, const Iter &it, long long &scanned) {
     });
 }
 
-// Runs up to a.max_iters iterations (one superior edge set each) of the
-// current batch.  Returns the iterations run.  Grid-uniform control flow:
-// every decision reads counters published before a grid barrier.
-__device__ int run_iterations(const KArgs &a) {
+// ---------------------------------------------------------------------------
+// Step machine
+// ---------------------------------------------------------------------------
+
+// Work of a frontier step in list entries: vertex items plus chunk items
+// weighted by the chunk length relative to a typical list.
+__device__ __forceinline__ int64_t frontier_work(const KArgs &a, int32_t nv, int32_t nchk) {
+    return (int64_t)nv + (int64_t)nchk * (a.t.chunk / 16 + 1);
+}
+
+__device__ int64_t step_work(const KArgs &a, const Iter &it, const PC &pc) {
     Ctl *c = a.ctl;
-    const int32_t ep0 = ld_acq(&c->epoch);
+    const int s = pc.r % 3;
+    switch (pc.step) {
+    case S_CLAIM:
+    case S_SELECT: return it.n_r;
+    case S_APPLY: return qlen(&c->sel_count, a.b.cap);
+    case S_EXPAND:
+        return frontier_work(a, qlen(&c->fq_tail[s], a.q.vcap),
+                             qlen(&c->fh_tail[s], a.q.hcap) + qlen(&c->fx_tail[s], a.q.hcap));
+    case S_EVICT:
+    case S_PEEL: return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
+    case S_CORE: return a.inserting ? qlen(&c->cand_count, a.q.vcap) : qlen(&c->chg_count, a.q.vcap);
+    case S_MCD: return frontier_work(a, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap));
+    default: return 0;
+    }
+}
+
+__device__ __forceinline__ bool step_is_local(const KArgs &a, const PC &pc, int64_t work) {
+    if (pc.step <= S_APPLY) return work <= a.t.local_edges;
+    return work <= a.t.local_items;
+}
+
+__device__ __forceinline__ bool slot_empty_f(const KArgs &a, int s) {
+    Ctl *c = a.ctl;
+    return ld_acq(&c->fq_tail[s]) + ld_acq(&c->fh_tail[s]) + ld_acq(&c->fx_tail[s]) == 0;
+}
+__device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
+    Ctl *c = a.ctl;
+    return ld_acq(&c->eq_tail[s]) + ld_acq(&c->eh_tail[s]) == 0;
+}
+
+// Step that follows pc (reads the counters pc's step published).
+__device__ PC next_pc(const KArgs &a, const PC &pc) {
+    switch (pc.step) {
+    case S_CLAIM: return PC{S_SELECT, pc.r};
+    case S_SELECT: return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
+    case S_APPLY:
+        if (a.inserting) {
+            if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
+            return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
+        }
+        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
+    case S_EXPAND:
+        if (!slot_empty_f(a, (pc.r + 1) % 3)) return PC{S_EXPAND, pc.r + 1};
+        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
+    case S_EVICT: return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_EVICT, pc.r + 1};
+    case S_PEEL: return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_PEEL, pc.r + 1};
+    case S_CORE: return PC{S_MCD, 0};
+    default: return PC{S_DONE, 0};
+    }
+}
+
+__device__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Team &T, long long &scanned) {
+    switch (pc.step) {
+    case S_CLAIM: part_claim(a, it, pc.r, T); break;
+    case S_SELECT: part_select(a, it, pc.r, T); break;
+    case S_APPLY:
+        if (a.inserting) apply_insert(a, it, T);
+        else apply_delete(a, it, T);
+        break;
+    case S_EXPAND: expand_round(a, it, pc.r, T, scanned); break;
+    case S_EVICT: evict_round(a, it, pc.r, T, scanned); break;
+    case S_PEEL: peel_round(a, it, pc.r, T, scanned); break;
+    case S_CORE: apply_core(a, it, T); break;
+    case S_MCD: mcd_phase(a, it, T, scanned); break;
+    default: break;
+    }
+}
+
+// Runs up to max_iters iterations of the current batch (each one superior
+// edge set).  ep is the last iteration stamp used (in/out).  Returns the
+// iterations run.  Workgroup 0 publishes the step where a local run stopped
+// in one of two slots (alternating), so a slow workgroup still reading the
+// previous publication is never overtaken.
+__device__ int run_iterations(const KArgs &a, int max_iters, int32_t &ep, long long &scanned, int &pubs) {
+    Ctl *c = a.ctl;
     int it_n = 0;
-    long long scanned = 0;
-    for (; it_n < a.max_iters; ++it_n) {
+    for (; it_n < max_iters; ++it_n) {
         Iter it;
-        it.ep = ep0 + it_n + 1;
+        it.ep = ep + 1;
         it.cur = it.ep & 1;
         it.n_r = qlen(&c->rem_count[it.cur], a.b.cap);
-        if (it.n_r == 0 || ld_acq(&c->overflow) != 0) break;
-        for (int r = 0; r < a.t.rounds; ++r) {
-            part_claim(a, it, r);
-            gsync();
-            part_select(a, it, r, r == a.t.rounds - 1);
-            gsync();
-        }
-        if (a.inserting) {
-            apply_insert(a, it);
-            gsync();
-            for (int r = 0;; ++r) {
-                int s = r % 3;
-                if (ld_acq(&c->fq_tail[s]) + ld_acq(&c->fh_tail[s]) + ld_acq(&c->fx_tail[s]) == 0) break;
-                expand_round(a, it, r, scanned);
-                gsync();
-            }
-            for (int r = 0;; ++r) {
-                int s = r % 3;
-                if (ld_acq(&c->eq_tail[s]) + ld_acq(&c->eh_tail[s]) == 0) break;
-                evict_round(a, it, r, scanned);
-                gsync();
-            }
-        } else {
-            apply_delete(a, it);
-            gsync();
-            for (int r = 0;; ++r) {
-                int s = r % 3;
-                if (ld_acq(&c->eq_tail[s]) + ld_acq(&c->eh_tail[s]) == 0) break;
-                peel_round(a, it, r, scanned);
-                gsync();
-            }
-        }
-        apply_core(a, it);
-        gsync();
-        mcd_phase(a, it, scanned);
-        if (gtid() == 0) {
-            int32_t ns = ld_acq(&c->sel_count);
-            int32_t nch = ld_acq(&c->changed_count);
-            int32_t ncand = ld_acq(&c->cand_count);
-            c->st_iters += 1;
-            c->st_remaining += (unsigned long long)it.n_r;
-            c->st_selected += (unsigned long long)ns;
-            if (a.inserting) {
-                c->st_candidates += (unsigned long long)ncand;
-                c->st_changed += (unsigned long long)nch;
-                c->st_evicted += (unsigned long long)(ncand - nch);
+        if (it.n_r == 0 || bar_aborted(a.bar)) break;
+        PC pc{S_CLAIM, 0};
+        while (pc.step != S_DONE) {
+            int64_t work = step_work(a, it, pc);
+            if (!step_is_local(a, pc, work)) {
+                run_step(a, it, pc, grid_team(), scanned);
+                if (gtid() == 0) c->st_grid_steps += 1;
+                gbar(a.bar);
+                pc = next_pc(a, pc);
             } else {
-                c->st_candidates += (unsigned long long)ld_acq(&c->touched_count);
-                c->st_changed += (unsigned long long)nch;
-                c->st_evicted += (unsigned long long)nch;
+                const int slot = pubs & 1;
+                if (blockIdx.x == 0) {
+                    const Team T = block_team();
+                    for (;;) {
+                        run_step(a, it, pc, T, scanned);
+                        if (threadIdx.x == 0) c->st_local_steps += 1;
+                        __syncthreads();
+                        pc = next_pc(a, pc);
+                        if (pc.step == S_DONE) break;
+                        work = step_work(a, it, pc);
+                        if (!step_is_local(a, pc, work)) break;
+                    }
+                    if (threadIdx.x == 0) {
+                        c->ipub[slot][0] = pc.step;
+                        c->ipub[slot][1] = pc.r;
+                    }
+                }
+                gbar(a.bar);
+                pc.step = ld_acq(&c->ipub[slot][0]);
+                pc.r = ld_acq(&c->ipub[slot][1]);
+                ++pubs;
             }
+            if (bar_aborted(a.bar)) break;
         }
-        gsync();
-    }
-    flush_stat(&c->st_scanned, scanned);
-    if (gtid() == 0) {
-        c->epoch = ep0 + it_n;
-        c->iters_done = it_n;
+        ep = it.ep;
+        if (pc.step != S_DONE) { ++it_n; break; }
     }
     return it_n;
 }
@@ -782,100 +879,177 @@ __device__ int run_iterations(const KArgs &a) {
 // degrees, and a neighbour joins the level when its degree crosses from k+1
 // to k (exactly once).  Empty levels are skipped by jumping k to the
 // smallest remaining degree.  cd[] holds the current degree; core = -2 marks
-// "not yet peeled".  Vertex lists: q.fq[0..1] (remaining, ping-pong);
-// frontier: q.eq / q.eh.
+// "not yet peeled".  Remaining lists: q.fq[0..1] (counts rm_count, rotating
+// by sweep j); frontier: q.eq / q.eh (counts rotating by the frontier index
+// f: a step reads slot f%3, pushes slot (f+1)%3, clears slot (f+2)%3).
+// Runs as a step machine like the iterations: small sweeps and rounds run in
+// workgroup 0 alone.
 // ===========================================================================
-__device__ int decompose(const KArgs &a) {
+enum DecStep : int32_t { D_SWEEP = 0, D_ROUND, D_DONE };
+
+struct DState {
+    int32_t step;
+    int32_t k;   // level
+    int32_t j;   // sweep index
+    int32_t f;   // frontier slot index
+};
+
+__device__ void dec_sweep(const KArgs &a, const DState &st, const Team &T) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
-    int32_t k = 0;
-    int j = 0;       // sweep index (rotating rm_count / min_deg slots)
-    int rr = 0;      // frontier round index (rotating eq/eh slots)
-    long long scanned = 0;
-    int32_t kmax = 0;
-    for (;;) {
-        // Sweep: split the remaining vertices into this level's frontier
-        // (degree <= k) and the rest; track the smallest remaining degree.
-        {
-            const int s0 = j % 3, s1 = (j + 1) % 3, s2 = (j + 2) % 3;
-            const int fs = rr % 3, fb = rr & 1;
-            const int32_t n = qlen(&c->rm_count[s0], a.q.vcap);
-            if (gtid() == 0) {
-                c->rm_count[s2] = 0;
-                c->min_deg[s2] = 0x7fffffff;
-                c->eq_tail[(rr + 1) % 3] = 0; c->eh_tail[(rr + 1) % 3] = 0;
-                c->eq_tail[(rr + 2) % 3] = 0; c->eh_tail[(rr + 2) % 3] = 0;
-            }
-            const int32_t *src = a.q.fq[j & 1];
-            int32_t *dst = a.q.fq[(j + 1) & 1];
-            int32_t mymin = 0x7fffffff;
-            for (int32_t idx = gtid(); idx < n; idx += gthreads()) {
-                int32_t v = src[idx];
-                bool keep = false, take = false;
-                if (g.core[v] == -2) {
-                    int32_t d = g.cd[v];
-                    if (d <= k) { g.core[v] = k; take = true; }
-                    else { keep = true; mymin = d < mymin ? d : mymin; }
-                }
-                push_vertex(a, a.q.eq[fb], &c->eq_tail[fs], a.q.eh[fb], &c->eh_tail[fs], v, take);
-                push_agg<int32_t>(dst, a.q.vcap, &c->rm_count[s1], v, keep, &c->overflow);
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                int32_t t = __shfl_xor(mymin, o);
-                mymin = t < mymin ? t : mymin;
-            }
-            if (lane() == 0 && mymin != 0x7fffffff) atomicMin(&c->min_deg[s1], mymin);
-        }
-        gsync();
-        const int s1 = (j + 1) % 3;
-        ++j;
-        if (ld_acq(&c->eq_tail[rr % 3]) + ld_acq(&c->eh_tail[rr % 3]) == 0) {
-            if (ld_acq(&c->rm_count[s1]) == 0) break;
-            int32_t md = ld_acq(&c->min_deg[s1]);
-            k = md > k + 1 ? md : k + 1;
-            continue;
-        }
-        kmax = k;
-        // Frontier rounds of level k.
-        for (;;) {
-            const int sc = rr % 3, sn = (rr + 1) % 3, sx = (rr + 2) % 3;
-            const int bc = rr & 1, bn = bc ^ 1;
-            const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
-            const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
-            if (gtid() == 0) { c->eq_tail[sx] = 0; c->eh_tail[sx] = 0; }
-            auto body = [&](int32_t w) -> bool {
-                if (w < 0 || g.core[w] != -2) return false;
-                if (atomicSub(&g.cd[w], 1) != k + 1) return false;
-                g.core[w] = k;
-                return true;
-            };
-            auto push_next = [&](int32_t w, bool p) {
-                push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
-            };
-            for_vertices(
-                a.q.eq[bc], nq, g, a.t.small_deg,
-                [&](int32_t x, int32_t L) {
-                    const int32_t *p = g.nbr + g.off[x];
-                    scanned += L;
-                    for (int32_t s = 0; s < L; ++s) push_next(p[s], body(p[s]));
-                },
-                [&](int32_t x, int32_t L) {
-                    if (lane() == 0) scanned += L;
-                    wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { push_next(w, body(w)); });
-                });
-            for_chunks(a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
-                if (lane() == 0) scanned += hi - lo;
-                wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, body(w)); });
-            });
-            gsync();
-            ++rr;
-            if (ld_acq(&c->eq_tail[rr % 3]) + ld_acq(&c->eh_tail[rr % 3]) == 0) break;
-        }
-        k += 1;
+    const int s0 = st.j % 3, s1 = (st.j + 1) % 3, s2 = (st.j + 2) % 3;
+    const int fn = (st.f + 1) % 3, fx = (st.f + 2) % 3, fb = (st.f + 1) & 1;
+    const int32_t n = qlen(&c->rm_count[s0], a.q.vcap);
+    if (T.lead()) {
+        c->rm_count[s2] = 0;
+        c->min_deg[s2] = 0x7fffffff;
+        c->eq_tail[fx] = 0; c->eh_tail[fx] = 0;
     }
-    flush_stat(&c->st_scanned, scanned);
-    if (gtid() == 0) { c->kmax = kmax; c->dec_rounds = rr; }
-    return rr;
+    const int32_t *src = a.q.fq[st.j & 1];
+    int32_t *dst = a.q.fq[(st.j + 1) & 1];
+    int32_t mymin = 0x7fffffff;
+    for (int32_t base = T.wave() * WAVE; base < n; base += T.nwaves() * WAVE) {
+        int32_t idx = base + lane();
+        int32_t v = idx < n ? src[idx] : -1;
+        bool keep = false, take = false;
+        if (v >= 0 && g.core[v] == -2) {
+            int32_t d = g.cd[v];
+            if (d <= st.k) { g.core[v] = st.k; take = true; }
+            else { keep = true; mymin = d < mymin ? d : mymin; }
+        }
+        push_vertex(a, a.q.eq[fb], &c->eq_tail[fn], a.q.eh[fb], &c->eh_tail[fn], v, take);
+        push_agg<int32_t>(dst, a.q.vcap, &c->rm_count[s1], v, keep, &c->overflow);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        int32_t t = __shfl_xor(mymin, o);
+        mymin = t < mymin ? t : mymin;
+    }
+    if (lane() == 0 && mymin != 0x7fffffff) atomicMin(&c->min_deg[s1], mymin);
+}
+
+__device__ void dec_round(const KArgs &a, const DState &st, const Team &T, long long &scanned) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    const int sc = st.f % 3, sn = (st.f + 1) % 3, sx = (st.f + 2) % 3;
+    const int bc = st.f & 1, bn = bc ^ 1;
+    const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
+    const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
+    if (T.lead()) {
+        c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
+        c->dec_rounds += 1;
+    }
+    const int32_t k = st.k;
+    auto body = [&](int32_t w) -> bool {
+        if (w < 0 || g.core[w] != -2) return false;
+        if (atomicSub(&g.cd[w], 1) != k + 1) return false;
+        g.core[w] = k;
+        return true;
+    };
+    auto push_next = [&](int32_t w, bool p) {
+        push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
+    };
+    for_vertices(
+        T, a.q.eq[bc], nq, g, a.t.small_deg,
+        [&](int32_t x, int32_t L) {
+            const int32_t *p = g.nbr + g.off[x];
+            scanned += L;
+            for (int32_t s = 0; s < L; ++s) push_next(p[s], body(p[s]));
+        },
+        [&](int32_t x, int32_t L) {
+            if (lane() == 0) scanned += L;
+            wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { push_next(w, body(w)); });
+        });
+    for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+        if (lane() == 0) scanned += hi - lo;
+        wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, body(w)); });
+    });
+}
+
+__device__ int64_t dec_work(const KArgs &a, const DState &st) {
+    Ctl *c = a.ctl;
+    if (st.step == D_SWEEP) return qlen(&c->rm_count[st.j % 3], a.q.vcap);
+    const int s = st.f % 3;
+    return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
+}
+
+__device__ DState dec_next(const KArgs &a, const DState &st) {
+    Ctl *c = a.ctl;
+    DState nx = st;
+    if (st.step == D_SWEEP) {
+        nx.j = st.j + 1;
+        nx.f = st.f + 1;
+        const int fs = nx.f % 3;
+        if (ld_acq(&c->eq_tail[fs]) + ld_acq(&c->eh_tail[fs]) != 0) {
+            nx.step = D_ROUND;
+            return nx;
+        }
+        const int s1 = nx.j % 3;
+        if (ld_acq(&c->rm_count[s1]) == 0) {
+            nx.step = D_DONE;
+            return nx;
+        }
+        int32_t md = ld_acq(&c->min_deg[s1]);
+        nx.k = md > st.k + 1 ? md : st.k + 1;
+        nx.step = D_SWEEP;
+        return nx;
+    }
+    // after a round
+    nx.f = st.f + 1;
+    const int fs = nx.f % 3;
+    if (ld_acq(&c->eq_tail[fs]) + ld_acq(&c->eh_tail[fs]) != 0) {
+        nx.step = D_ROUND;
+        return nx;
+    }
+    nx.k = st.k + 1;
+    nx.step = D_SWEEP;
+    return nx;
+}
+
+__device__ void decompose(const KArgs &a, long long &scanned) {
+    Ctl *c = a.ctl;
+    DState st{D_SWEEP, 0, 0, 0};
+    int pubs = 0;
+    int32_t kmax = 0;
+    while (st.step != D_DONE) {
+        if (bar_aborted(a.bar)) break;
+        int64_t work = dec_work(a, st);
+        if (work > a.t.local_items) {
+            if (st.step == D_SWEEP) dec_sweep(a, st, grid_team());
+            else { dec_round(a, st, grid_team(), scanned); kmax = st.k; }
+            if (gtid() == 0) c->st_grid_steps += 1;
+            gbar(a.bar);
+            st = dec_next(a, st);
+        } else {
+            const int slot = pubs & 1;
+            if (blockIdx.x == 0) {
+                const Team T = block_team();
+                for (;;) {
+                    if (st.step == D_SWEEP) dec_sweep(a, st, T);
+                    else { dec_round(a, st, T, scanned); kmax = st.k; }
+                    if (threadIdx.x == 0) c->st_local_steps += 1;
+                    __syncthreads();
+                    st = dec_next(a, st);
+                    if (st.step == D_DONE) break;
+                    if (dec_work(a, st) > a.t.local_items) break;
+                }
+                if (threadIdx.x == 0) {
+                    c->dpub[slot][0] = st.step;
+                    c->dpub[slot][1] = st.k;
+                    c->dpub[slot][2] = st.j;
+                    c->dpub[slot][3] = st.f;
+                    c->dpub[slot][4] = kmax;
+                }
+            }
+            gbar(a.bar);
+            st.step = ld_acq(&c->dpub[slot][0]);
+            st.k = ld_acq(&c->dpub[slot][1]);
+            st.j = ld_acq(&c->dpub[slot][2]);
+            st.f = ld_acq(&c->dpub[slot][3]);
+            kmax = ld_acq(&c->dpub[slot][4]);
+            ++pubs;
+        }
+    }
+    if (gtid() == 0) c->kmax = kmax;
 }
 
 }  // namespace cm

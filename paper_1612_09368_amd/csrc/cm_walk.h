@@ -30,13 +30,13 @@ __device__ __forceinline__ void push_vertex(const KArgs &a, int32_t *vq, int32_t
     }
 }
 
-// Grid-stride over a vertex queue.  fl(v, L) runs on the owning lane for
+// Team-stride over a vertex queue.  fl(v, L) runs on the owning lane for
 // short lists; fw(v, L) runs on the whole wave (uniform) for the others.
 template <class FL, class FW>
-__device__ __forceinline__ void for_vertices(const int32_t *q, int32_t n, const DevGraph &g, int32_t small,
-                                             FL &&fl, FW &&fw) {
-    const int step = nwaves() * WAVE;
-    for (int32_t base = gwave() * WAVE; base < n; base += step) {
+__device__ __forceinline__ void for_vertices(const Team &T, const int32_t *q, int32_t n, const DevGraph &g,
+                                             int32_t small, FL &&fl, FW &&fw) {
+    const int step = T.nwaves() * WAVE;
+    for (int32_t base = T.wave() * WAVE; base < n; base += step) {
         int32_t i = base + lane();
         int32_t v = (i < n) ? q[i] : -1;
         int32_t L = (v >= 0) ? g.len[v] : 0;
@@ -55,10 +55,10 @@ __device__ __forceinline__ void for_vertices(const int32_t *q, int32_t n, const 
 // Same for an implicit identity list 0..n-1 (whole-graph passes); lists of
 // any length are accepted (long ones are walked by one wave).
 template <class FL, class FW>
-__device__ __forceinline__ void for_all_vertices(int32_t n, const DevGraph &g, int32_t small, FL &&fl,
-                                                 FW &&fw) {
-    const int step = nwaves() * WAVE;
-    for (int32_t base = gwave() * WAVE; base < n; base += step) {
+__device__ __forceinline__ void for_all_vertices(const Team &T, int32_t n, const DevGraph &g, int32_t small,
+                                                 FL &&fl, FW &&fw) {
+    const int step = T.nwaves() * WAVE;
+    for (int32_t base = T.wave() * WAVE; base < n; base += step) {
         int32_t v = base + lane();
         bool ok = v < n && g.core[v] != -1;  // -1 marks a dead id
         int32_t L = ok ? g.len[v] : 0;
@@ -74,11 +74,11 @@ __device__ __forceinline__ void for_all_vertices(int32_t n, const DevGraph &g, i
     }
 }
 
-// Grid-stride over chunk items, one wave per item: fc(v, lo, hi, nch).
+// Team-stride over chunk items, one wave per item: fc(v, lo, hi, nch).
 template <class FC>
-__device__ __forceinline__ void for_chunks(const int64_t *q, int32_t n, const DevGraph &g, int32_t chunk,
-                                           FC &&fc) {
-    for (int32_t j = gwave(); j < n; j += nwaves()) {
+__device__ __forceinline__ void for_chunks(const Team &T, const int64_t *q, int32_t n, const DevGraph &g,
+                                           int32_t chunk, FC &&fc) {
+    for (int32_t j = T.wave(); j < n; j += T.nwaves()) {
         int64_t it = q[j];
         int32_t v = item_v(it), c = item_c(it);
         int32_t L = g.len[v];
