@@ -84,6 +84,7 @@ typedef struct cm_config {
                                    workgroup instead of the whole grid (0 = default) */
     int32_t local_items;        /* frontier steps up to this many items run in one workgroup
                                    (0 = default) */
+    int32_t local_work;         /* ... if their lists hold at most this many entries (0 = default) */
     int32_t timing;             /* 1 = time each maintenance launch with HIP events */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;

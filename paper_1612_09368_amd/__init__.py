@@ -45,6 +45,7 @@ class Config(ctypes.Structure):
         ("chunk", ctypes.c_int32),
         ("local_edges", ctypes.c_int32),
         ("local_items", ctypes.c_int32),
+        ("local_work", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
@@ -156,7 +157,7 @@ class Graph:
 
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
-                 local_edges=0, local_items=0, timing=False, stream=None):
+                 local_edges=0, local_items=0, local_work=0, timing=False, stream=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -171,6 +172,7 @@ class Graph:
         cfg.chunk = chunk
         cfg.local_edges = local_edges
         cfg.local_items = local_items
+        cfg.local_work = local_work
         cfg.timing = 1 if timing else 0
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()

@@ -629,12 +629,13 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
             g->err = "device does not support cooperative launches";
             throw Fail{CM_E_DEVICE};
         }
-        g->tune.small_deg = g->cfg.small_degree > 0 ? g->cfg.small_degree : 16;
-        g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 4096;
-        g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 2048;
+        g->tune.small_deg = g->cfg.small_degree > 0 ? g->cfg.small_degree : 4;
+        g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 256;
+        g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 128;
         g->tune.rounds = g->cfg.partition_rounds > 0 ? std::min(g->cfg.partition_rounds, 8) : 1;
         g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 8192;
-        g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 1024;
+        g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 2048;
+        g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
         HIPCHK(coop_occupancy(0, &bpc_m));

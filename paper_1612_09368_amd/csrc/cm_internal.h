@@ -49,8 +49,8 @@ struct Ctl {
     int32_t min_deg[3];      // decomposition: smallest remaining degree (rotating)
     int32_t kmax;            // decomposition: largest core number
     int32_t dec_rounds;      // decomposition: frontier rounds
-    int32_t ipub[2][2];      // iteration step machine: (step, round) published by workgroup 0
-    int32_t dpub[2][5];      // decomposition step machine: (step, k, j, f, kmax)
+    int32_t ipub[2][4];      // iteration step machine: (step, round, force grid) published by workgroup 0
+    int32_t dpub[2][6];      // decomposition step machine: (step, k, j, f, kmax, force grid)
     unsigned long long pool_tail;     // next free adjacency slot
     unsigned long long garbage;       // slots abandoned by relocations
     // statistics (summed over the iterations of a batch)
@@ -149,6 +149,8 @@ struct Tune {
     int32_t rounds;      // selection rounds per iteration
     int32_t local_edges; // partition / apply steps up to this many edges run in one workgroup
     int32_t local_items; // frontier steps up to this many items run in one workgroup
+    int32_t local_work;  // ... and only if their lists hold at most this many entries
+    int32_t pad;
 };
 
 constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
@@ -167,6 +169,22 @@ struct KArgs {
     int32_t cur;         // remaining list that receives the validated batch
     int32_t pad;
 };
+
+// Per-batch parameters of the validation / reservation steps.
+struct BatchCtx {
+    const int32_t *src;  // raw items
+    const int32_t *dst;
+    int32_t s;           // item count
+    int32_t inserting;   // 1 = insertion batch
+    int32_t cur;         // remaining list that receives the valid items
+    int32_t bstamp;      // per-vertex mark values bstamp (scan) and bstamp + 1 (endpoints)
+    int32_t hcap;        // hash slots used (power of two, <= allocated)
+    int32_t pad;
+};
+
+__device__ __forceinline__ BatchCtx batch_of(const KArgs &a) {
+    return BatchCtx{a.b.src_in, a.b.dst_in, a.s, a.inserting, a.cur, a.bstamp, a.b.hcap, 0};
+}
 
 // ---------------------------------------------------------------------------
 // Wave helpers

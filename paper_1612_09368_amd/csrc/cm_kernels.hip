@@ -355,11 +355,11 @@ __global__ void k_mcd_init(KArgs a) {
 // ---------------------------------------------------------------------------
 // Batch validation, reservation, compaction, maintenance
 // ---------------------------------------------------------------------------
-__global__ void k_val_canon(KArgs a) { val_canon(a, grid_team()); }
-__global__ void k_val_dup_mark(KArgs a) { val_dup_mark(a, grid_team()); }
-__global__ void k_val_scan(KArgs a) { val_scan(a, grid_team()); }
-__global__ void k_val_final(KArgs a) { val_final(a, grid_team()); }
-__global__ void k_res_gain(KArgs a) { res_gain(a, grid_team()); }
+__global__ void k_val_canon(KArgs a) { val_canon(a, batch_of(a), grid_team()); }
+__global__ void k_val_dup_mark(KArgs a) { val_dup_mark(a, batch_of(a), grid_team()); }
+__global__ void k_val_scan(KArgs a) { val_scan(a, batch_of(a), grid_team()); }
+__global__ void k_val_final(KArgs a) { val_final(a, batch_of(a), grid_team()); }
+__global__ void k_res_gain(KArgs a) { res_gain(a, batch_of(a), grid_team()); }
 __global__ void k_res_alloc(KArgs a) { res_alloc(a, grid_team()); }
 __global__ void k_res_copy(KArgs a) { res_copy(a, grid_team()); }
 __global__ void k_del_compact(KArgs a) { del_compact(a, grid_team()); }
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
     int32_t ep = ld_acq(&a.ctl->epoch);
     long long scanned = 0;
     int pubs = 0;
-    int n = run_iterations(a, a.max_iters, ep, scanned, pubs);
+    int n = run_iterations(a, a.inserting, a.max_iters, ep, scanned, pubs);
     flush_stat(&a.ctl->st_scanned, scanned);
     if (gtid() == 0) {
         a.ctl->epoch = ep;

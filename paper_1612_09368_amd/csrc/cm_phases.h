@@ -41,11 +41,11 @@ __device__ __forceinline__ void count_agg(int32_t *ctr, bool pred) {
 
 // V1: range / dead / self-loop checks, canonical (min, max), hash insert
 // (the smallest item index of each pair wins the slot).
-__device__ void val_canon(const KArgs &a, const Team &T) {
+__device__ __forceinline__ void val_canon(const KArgs &a, const BatchCtx &bc, const Team &T) {
     const int32_t n = a.g.n_ids;
-    const uint32_t mask = (uint32_t)a.b.hcap - 1u;
-    for (int32_t i = T.rank; i < a.s; i += T.size) {
-        int32_t u = a.b.src_in[i], v = a.b.dst_in[i];
+    const uint32_t mask = (uint32_t)bc.hcap - 1u;
+    for (int32_t i = T.rank; i < bc.s; i += T.size) {
+        int32_t u = bc.src[i], v = bc.dst[i];
         int32_t e = 0;
         if (u < 0 || v < 0 || u >= n || v >= n) e = ST_RANGE;
         else if (a.g.core[u] < 0 || a.g.core[v] < 0) e = ST_DEAD;
@@ -71,8 +71,8 @@ __device__ void val_canon(const KArgs &a, const Team &T) {
     }
 }
 
-__device__ __forceinline__ void mark_scan(const KArgs &a, int32_t x) {
-    if (atomicExch(&a.g.bmark[x], a.bstamp) != a.bstamp) {
+__device__ __forceinline__ void mark_scan(const KArgs &a, const BatchCtx &bc, int32_t x) {
+    if (atomicExch(&a.g.bmark[x], bc.bstamp) != bc.bstamp) {
         int32_t L = a.g.len[x];
         int nch = nchunks(L, a.t.chunk);
         if (nch > 0) {
@@ -88,8 +88,8 @@ __device__ __forceinline__ void mark_scan(const KArgs &a, int32_t x) {
 // V2: duplicates inside the batch; choose the lists the locate scan reads
 // (insertion: the shorter endpoint list is enough to test existence;
 // deletion: both lists, to find both slots).
-__device__ void val_dup_mark(const KArgs &a, const Team &T) {
-    for (int32_t i = T.rank; i < a.s; i += T.size) {
+__device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc, const Team &T) {
+    for (int32_t i = T.rank; i < bc.s; i += T.size) {
         int32_t e = a.b.err[i];
         if (e != 0) continue;
         if (a.b.hval[a.b.hslot[i]] != i) {
@@ -97,11 +97,11 @@ __device__ void val_dup_mark(const KArgs &a, const Team &T) {
             continue;
         }
         int32_t u = a.b.eu[i], v = a.b.ev[i];
-        if (a.inserting) {
-            mark_scan(a, a.g.len[u] <= a.g.len[v] ? u : v);
+        if (bc.inserting) {
+            mark_scan(a, bc, a.g.len[u] <= a.g.len[v] ? u : v);
         } else {
-            mark_scan(a, u);
-            mark_scan(a, v);
+            mark_scan(a, bc, u);
+            mark_scan(a, bc, v);
         }
     }
 }
@@ -109,8 +109,8 @@ __device__ void val_dup_mark(const KArgs &a, const Team &T) {
 // V3: locate scan.  Each (vertex, chunk) item is read by one wave; every
 // live neighbour probes the batch hash.  Insertion: a hit means the edge
 // exists.  Deletion: a hit records the slot of the entry.
-__device__ void val_scan(const KArgs &a, const Team &T) {
-    const uint32_t mask = (uint32_t)a.b.hcap - 1u;
+__device__ __forceinline__ void val_scan(const KArgs &a, const BatchCtx &bc, const Team &T) {
+    const uint32_t mask = (uint32_t)bc.hcap - 1u;
     const int32_t n = qlen(&a.ctl->scan_tail, a.b.scap);
     for_chunks(T, a.b.scanq, n, a.g, a.t.chunk,
                [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
@@ -124,7 +124,7 @@ __device__ void val_scan(const KArgs &a, const Team &T) {
                            if (k2 == EMPTY_KEY) break;
                            if (k2 == key) {
                                int32_t i = a.b.hval[h];
-                               if (a.inserting) {
+                               if (bc.inserting) {
                                    a.b.err[i] = ST_EXISTS;
                                } else if (x == a.b.eu[i]) {
                                    a.b.su[i] = base + slot;
@@ -141,15 +141,15 @@ __device__ void val_scan(const KArgs &a, const Team &T) {
 
 // V4: missing edges, smallest invalid index, emit valid item indices into
 // the remaining list `cur`.
-__device__ void val_final(const KArgs &a, const Team &T) {
-    for (int32_t i = T.rank; i < a.s; i += T.size) {
+__device__ __forceinline__ void val_final(const KArgs &a, const BatchCtx &bc, const Team &T) {
+    for (int32_t i = T.rank; i < bc.s; i += T.size) {
         int32_t e = a.b.err[i];
-        if (!a.inserting && e == 0 && (a.b.su[i] < 0 || a.b.sv[i] < 0)) {
+        if (!bc.inserting && e == 0 && (a.b.su[i] < 0 || a.b.sv[i] < 0)) {
             e = ST_MISSING;
             a.b.err[i] = e;
         }
         if (e != 0) atomicMin(&a.ctl->first_bad, i);
-        push_agg<int32_t>(a.b.rem[a.cur], a.b.cap, &a.ctl->rem_count[a.cur], i, e == 0,
+        push_agg<int32_t>(a.b.rem[bc.cur], a.b.cap, &a.ctl->rem_count[bc.cur], i, e == 0,
                           &a.ctl->overflow);
     }
 }
@@ -159,25 +159,25 @@ __device__ void val_final(const KArgs &a, const Team &T) {
 // tombstone compaction after a deletion batch.
 // ===========================================================================
 
-__device__ __forceinline__ void mark_endpoint(const KArgs &a, int32_t x) {
+__device__ __forceinline__ void mark_endpoint(const KArgs &a, const BatchCtx &bc, int32_t x) {
     atomicAdd(&a.g.gain[x], 1);
-    bool first = atomicExch(&a.g.bmark[x], a.bstamp + 1) != a.bstamp + 1;
+    bool first = atomicExch(&a.g.bmark[x], bc.bstamp + 1) != bc.bstamp + 1;
     push_agg<int32_t>(a.b.vlist, a.g.n_cap, &a.ctl->vlist_count, x, first, &a.ctl->overflow);
 }
 
 // R1: per-vertex count of batch edges (gain) and the distinct endpoints.
-__device__ void res_gain(const KArgs &a, const Team &T) {
-    const int32_t n = qlen(&a.ctl->rem_count[a.cur], a.b.cap);
-    const int32_t *R = a.b.rem[a.cur];
+__device__ __forceinline__ void res_gain(const KArgs &a, const BatchCtx &bc, const Team &T) {
+    const int32_t n = qlen(&a.ctl->rem_count[bc.cur], a.b.cap);
+    const int32_t *R = a.b.rem[bc.cur];
     for (int32_t idx = T.rank; idx < n; idx += T.size) {
         int32_t i = R[idx];
-        mark_endpoint(a, a.b.eu[i]);
-        mark_endpoint(a, a.b.ev[i]);
+        mark_endpoint(a, bc, a.b.eu[i]);
+        mark_endpoint(a, bc, a.b.ev[i]);
     }
 }
 
 // R2: a list that cannot take its gain moves to a spill block at the pool tail.
-__device__ void res_alloc(const KArgs &a, const Team &T) {
+__device__ __forceinline__ void res_alloc(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->vlist_count, a.g.n_cap);
     for (int32_t j = T.rank; j < n; j += T.size) {
         int32_t x = a.b.vlist[j];
@@ -200,7 +200,7 @@ __device__ void res_alloc(const KArgs &a, const Team &T) {
 }
 
 // R3: copy relocated lists (one wave per list).
-__device__ void res_copy(const KArgs &a, const Team &T) {
+__device__ __forceinline__ void res_copy(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->reloc_count, a.g.n_cap);
     for (int32_t j = T.wave(); j < n; j += T.nwaves()) {
         int32_t x = a.b.reloc[j];
@@ -218,7 +218,7 @@ __device__ void res_copy(const KArgs &a, const Team &T) {
 
 // After a deletion batch: squeeze tombstones out of the touched lists whose
 // tombstone share is large (one wave per list, in place, order kept).
-__device__ void del_compact(const KArgs &a, const Team &T) {
+__device__ __forceinline__ void del_compact(const KArgs &a, const Team &T) {
     const int32_t n = qlen(&a.ctl->vlist_count, a.g.n_cap);
     for (int32_t j = T.wave(); j < n; j += T.nwaves()) {
         int32_t x = a.b.vlist[j];
@@ -258,6 +258,7 @@ struct Iter {
     int32_t ep;    // iteration stamp
     int32_t cur;   // remaining list read by this iteration
     int32_t n_r;   // its length
+    int32_t ins;   // 1 = insertion batch, 0 = deletion batch
 };
 
 enum StepKind : int32_t { S_CLAIM = 0, S_SELECT, S_APPLY, S_EXPAND, S_EVICT, S_PEEL, S_CORE, S_MCD, S_DONE };
@@ -282,7 +283,7 @@ __device__ __forceinline__ bool matched_before(uint32_t m, int32_t ep, int round
 // claim rounds fill in edges whose endpoints are still free).  A vertex is
 // constrained only at its own level, so one pass builds the union of all
 // k-superior edge sets.
-__device__ void part_claim(const KArgs &a, const Iter &it, int r, const Team &T) {
+__device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r, const Team &T) {
     Ctl *c = a.ctl;
     if (r == 0 && T.lead()) {
         c->sel_count = 0;
@@ -315,7 +316,7 @@ __device__ void part_claim(const KArgs &a, const Iter &it, int r, const Team &T)
     }
 }
 
-__device__ void part_select(const KArgs &a, const Iter &it, int r, const Team &T) {
+__device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int r, const Team &T) {
     Ctl *c = a.ctl;
     const bool last = r == a.t.rounds - 1;
     const int32_t *R = a.b.rem[it.cur];
@@ -347,7 +348,7 @@ __device__ void part_select(const KArgs &a, const Iter &it, int r, const Team &T
 // Insert the selected set into G (Algorithm 1) and update SD of the
 // constrained endpoints; a constrained endpoint whose new SD exceeds its core
 // is a root of the traversal (a vertex with SD <= k cannot rise).
-__device__ void apply_insert(const KArgs &a, const Iter &it, const Team &T) {
+__device__ __forceinline__ void apply_insert(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
     if (T.lead()) c->st_selected += (unsigned long long)n;
@@ -383,7 +384,7 @@ __device__ void apply_insert(const KArgs &a, const Iter &it, const Team &T) {
 // Delete the selected set from G (Algorithm 5) and update SD of the
 // constrained endpoints; a root whose SD on G minus the set falls below its
 // core is peeled at once (Algorithm 6, test cd < k).
-__device__ void apply_delete(const KArgs &a, const Iter &it, const Team &T) {
+__device__ __forceinline__ void apply_delete(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
     if (T.lead()) c->st_selected += (unsigned long long)n;
@@ -422,7 +423,7 @@ __device__ __forceinline__ bool is_support(const DevGraph &g, int32_t w, int32_t
     return cw > k || (cw == k && g.mcd[w] > k);
 }
 
-__device__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+__device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -549,7 +550,7 @@ __device__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &
 // Negative traversal (Algorithm 4) as rounds: an evicted candidate lowers the
 // counter of each candidate neighbour at its level; a neighbour is evicted
 // exactly once, when its counter crosses from k+1 to k.
-__device__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+__device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -596,7 +597,7 @@ __device__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T
 // is cd = SD(w) - dec[w] (SD on G minus the set) and w is peeled exactly
 // once, when cd crosses from k to k-1.  dec is cleared after the iteration
 // through the `touched` list.
-__device__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+__device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -642,10 +643,10 @@ __device__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T,
 
 // Core update (Algorithm 1: +1 for every surviving candidate; Algorithm 5:
 // -1 for every peeled vertex).  SD of a moved vertex is rebuilt next step.
-__device__ void apply_core(const KArgs &a, const Iter &it, const Team &T) {
+__device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
-    if (a.inserting) {
+    if (it.ins) {
         const int32_t n = qlen(&c->cand_count, a.q.vcap);
         if (T.lead()) c->st_candidates += (unsigned long long)n;
         for (int32_t idx = T.rank; idx < n; idx += T.size) {
@@ -692,11 +693,11 @@ __device__ void apply_core(const KArgs &a, const Iter &it, const Team &T) {
 // SD maintenance after the core update: a moved vertex recounts SD from its
 // list; an unmoved neighbour w gains (insert) or loses (delete) one when the
 // moved vertex crossed w's core.
-__device__ void mcd_phase(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
+__device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
-    const bool ins = a.inserting != 0;
+    const bool ins = it.ins != 0;
     if (T.lead()) {
         unsigned long long ch = (unsigned long long)ld_acq(&c->changed_count);
         c->st_changed += ch;
@@ -749,7 +750,52 @@ __device__ __forceinline__ int64_t frontier_work(const KArgs &a, int32_t nv, int
     return (int64_t)nv + (int64_t)nchk * (a.t.chunk / 16 + 1);
 }
 
-__device__ int64_t step_work(const KArgs &a, const Iter &it, const PC &pc) {
+// Sum over the threads of one workgroup (every thread of it must call).
+__device__ __forceinline__ long long block_sum64(long long v) {
+    __shared__ long long red[COOP_THREADS / WAVE];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane() == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// List entries a frontier step would walk: the lengths of its vertex items
+// plus a full chunk per chunk item (computed by one workgroup).
+__device__ __forceinline__ long long queue_work(const KArgs &a, const Team &T, const int32_t *q, int32_t n,
+                                                int32_t nchk, int walks) {
+    long long w = 0;
+    for (int32_t i = T.rank; i < n; i += T.size) w += a.g.len[q[i]];
+    w = block_sum64(w) * walks;
+    return w + (long long)nchk * a.t.chunk;
+}
+
+// Whether workgroup 0 may run this step by itself: its item count already
+// passed step_is_local; here the list entries it would walk are checked.
+__device__ __forceinline__ bool block_local_ok(const KArgs &a, const Iter &it, const PC &pc, const Team &T) {
+    Ctl *c = a.ctl;
+    const int s = pc.r % 3;
+    long long w = 0;
+    switch (pc.step) {
+    case S_EXPAND:
+        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap),
+                       qlen(&c->fh_tail[s], a.q.hcap) + qlen(&c->fx_tail[s], a.q.hcap), 2);
+        break;
+    case S_EVICT:
+    case S_PEEL:
+        w = queue_work(a, T, a.q.eq[pc.r & 1], qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap), 1);
+        break;
+    case S_MCD:
+        w = queue_work(a, T, a.q.chg, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap), 1);
+        break;
+    default: return true;
+    }
+    return w <= a.t.local_work;
+}
+
+__device__ __forceinline__ int64_t step_work(const KArgs &a, const Iter &it, const PC &pc) {
     Ctl *c = a.ctl;
     const int s = pc.r % 3;
     switch (pc.step) {
@@ -761,7 +807,7 @@ __device__ int64_t step_work(const KArgs &a, const Iter &it, const PC &pc) {
                              qlen(&c->fh_tail[s], a.q.hcap) + qlen(&c->fx_tail[s], a.q.hcap));
     case S_EVICT:
     case S_PEEL: return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
-    case S_CORE: return a.inserting ? qlen(&c->cand_count, a.q.vcap) : qlen(&c->chg_count, a.q.vcap);
+    case S_CORE: return it.ins ? qlen(&c->cand_count, a.q.vcap) : qlen(&c->chg_count, a.q.vcap);
     case S_MCD: return frontier_work(a, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap));
     default: return 0;
     }
@@ -782,12 +828,12 @@ __device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
 }
 
 // Step that follows pc (reads the counters pc's step published).
-__device__ PC next_pc(const KArgs &a, const PC &pc) {
+__device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &pc) {
     switch (pc.step) {
     case S_CLAIM: return PC{S_SELECT, pc.r};
     case S_SELECT: return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
     case S_APPLY:
-        if (a.inserting) {
+        if (it.ins) {
             if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
             return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
         }
@@ -802,12 +848,13 @@ __device__ PC next_pc(const KArgs &a, const PC &pc) {
     }
 }
 
-__device__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Team &T, long long &scanned) {
+__device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Team &T,
+                                         long long &scanned) {
     switch (pc.step) {
     case S_CLAIM: part_claim(a, it, pc.r, T); break;
     case S_SELECT: part_select(a, it, pc.r, T); break;
     case S_APPLY:
-        if (a.inserting) apply_insert(a, it, T);
+        if (it.ins) apply_insert(a, it, T);
         else apply_delete(a, it, T);
         break;
     case S_EXPAND: expand_round(a, it, pc.r, T, scanned); break;
@@ -824,7 +871,8 @@ __device__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Tea
 // iterations run.  Workgroup 0 publishes the step where a local run stopped
 // in one of two slots (alternating), so a slow workgroup still reading the
 // previous publication is never overtaken.
-__device__ int run_iterations(const KArgs &a, int max_iters, int32_t &ep, long long &scanned, int &pubs) {
+__device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_iters, int32_t &ep, long long &scanned,
+                              int &pubs) {
     Ctl *c = a.ctl;
     int it_n = 0;
     for (; it_n < max_iters; ++it_n) {
@@ -832,24 +880,29 @@ __device__ int run_iterations(const KArgs &a, int max_iters, int32_t &ep, long l
         it.ep = ep + 1;
         it.cur = it.ep & 1;
         it.n_r = qlen(&c->rem_count[it.cur], a.b.cap);
+        it.ins = ins;
         if (it.n_r == 0 || bar_aborted(a.bar)) break;
         PC pc{S_CLAIM, 0};
+        bool force = false;  // published by workgroup 0: run pc on the grid
         while (pc.step != S_DONE) {
             int64_t work = step_work(a, it, pc);
-            if (!step_is_local(a, pc, work)) {
+            if (force || !step_is_local(a, pc, work)) {
+                force = false;
                 run_step(a, it, pc, grid_team(), scanned);
                 if (gtid() == 0) c->st_grid_steps += 1;
                 gbar(a.bar);
-                pc = next_pc(a, pc);
+                pc = next_pc(a, it, pc);
             } else {
                 const int slot = pubs & 1;
                 if (blockIdx.x == 0) {
                     const Team T = block_team();
+                    bool fg = false;
                     for (;;) {
+                        if (!block_local_ok(a, it, pc, T)) { fg = true; break; }
                         run_step(a, it, pc, T, scanned);
                         if (threadIdx.x == 0) c->st_local_steps += 1;
                         __syncthreads();
-                        pc = next_pc(a, pc);
+                        pc = next_pc(a, it, pc);
                         if (pc.step == S_DONE) break;
                         work = step_work(a, it, pc);
                         if (!step_is_local(a, pc, work)) break;
@@ -857,11 +910,13 @@ __device__ int run_iterations(const KArgs &a, int max_iters, int32_t &ep, long l
                     if (threadIdx.x == 0) {
                         c->ipub[slot][0] = pc.step;
                         c->ipub[slot][1] = pc.r;
+                        c->ipub[slot][2] = fg ? 1 : 0;
                     }
                 }
                 gbar(a.bar);
                 pc.step = ld_acq(&c->ipub[slot][0]);
                 pc.r = ld_acq(&c->ipub[slot][1]);
+                force = ld_acq(&c->ipub[slot][2]) != 0;
                 ++pubs;
             }
             if (bar_aborted(a.bar)) break;
@@ -894,7 +949,7 @@ struct DState {
     int32_t f;   // frontier slot index
 };
 
-__device__ void dec_sweep(const KArgs &a, const DState &st, const Team &T) {
+__device__ __forceinline__ void dec_sweep(const KArgs &a, const DState &st, const Team &T) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int s0 = st.j % 3, s1 = (st.j + 1) % 3, s2 = (st.j + 2) % 3;
@@ -927,7 +982,7 @@ __device__ void dec_sweep(const KArgs &a, const DState &st, const Team &T) {
     if (lane() == 0 && mymin != 0x7fffffff) atomicMin(&c->min_deg[s1], mymin);
 }
 
-__device__ void dec_round(const KArgs &a, const DState &st, const Team &T, long long &scanned) {
+__device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, const Team &T, long long &scanned) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = st.f % 3, sn = (st.f + 1) % 3, sx = (st.f + 2) % 3;
@@ -965,14 +1020,23 @@ __device__ void dec_round(const KArgs &a, const DState &st, const Team &T, long 
     });
 }
 
-__device__ int64_t dec_work(const KArgs &a, const DState &st) {
+__device__ __forceinline__ bool dec_block_local_ok(const KArgs &a, const DState &st, const Team &T) {
+    if (st.step != D_ROUND) return true;
+    Ctl *c = a.ctl;
+    const int s = st.f % 3;
+    long long w = queue_work(a, T, a.q.eq[st.f & 1], qlen(&c->eq_tail[s], a.q.vcap),
+                             qlen(&c->eh_tail[s], a.q.hcap), 1);
+    return w <= a.t.local_work;
+}
+
+__device__ __forceinline__ int64_t dec_work(const KArgs &a, const DState &st) {
     Ctl *c = a.ctl;
     if (st.step == D_SWEEP) return qlen(&c->rm_count[st.j % 3], a.q.vcap);
     const int s = st.f % 3;
     return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
 }
 
-__device__ DState dec_next(const KArgs &a, const DState &st) {
+__device__ __forceinline__ DState dec_next(const KArgs &a, const DState &st) {
     Ctl *c = a.ctl;
     DState nx = st;
     if (st.step == D_SWEEP) {
@@ -1005,15 +1069,17 @@ __device__ DState dec_next(const KArgs &a, const DState &st) {
     return nx;
 }
 
-__device__ void decompose(const KArgs &a, long long &scanned) {
+__device__ __forceinline__ void decompose(const KArgs &a, long long &scanned) {
     Ctl *c = a.ctl;
     DState st{D_SWEEP, 0, 0, 0};
     int pubs = 0;
     int32_t kmax = 0;
+    bool force = false;
     while (st.step != D_DONE) {
         if (bar_aborted(a.bar)) break;
         int64_t work = dec_work(a, st);
-        if (work > a.t.local_items) {
+        if (force || work > a.t.local_items) {
+            force = false;
             if (st.step == D_SWEEP) dec_sweep(a, st, grid_team());
             else { dec_round(a, st, grid_team(), scanned); kmax = st.k; }
             if (gtid() == 0) c->st_grid_steps += 1;
@@ -1023,7 +1089,9 @@ __device__ void decompose(const KArgs &a, long long &scanned) {
             const int slot = pubs & 1;
             if (blockIdx.x == 0) {
                 const Team T = block_team();
+                bool fg = false;
                 for (;;) {
+                    if (!dec_block_local_ok(a, st, T)) { fg = true; break; }
                     if (st.step == D_SWEEP) dec_sweep(a, st, T);
                     else { dec_round(a, st, T, scanned); kmax = st.k; }
                     if (threadIdx.x == 0) c->st_local_steps += 1;
@@ -1038,6 +1106,7 @@ __device__ void decompose(const KArgs &a, long long &scanned) {
                     c->dpub[slot][2] = st.j;
                     c->dpub[slot][3] = st.f;
                     c->dpub[slot][4] = kmax;
+                    c->dpub[slot][5] = fg ? 1 : 0;
                 }
             }
             gbar(a.bar);
@@ -1046,6 +1115,7 @@ __device__ void decompose(const KArgs &a, long long &scanned) {
             st.j = ld_acq(&c->dpub[slot][2]);
             st.f = ld_acq(&c->dpub[slot][3]);
             kmax = ld_acq(&c->dpub[slot][4]);
+            force = ld_acq(&c->dpub[slot][5]) != 0;
             ++pubs;
         }
     }
