@@ -203,12 +203,15 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
-__device__ __forceinline__ int32_t ld_acq(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Coherent read of a control word.  Relaxed (no cache invalidation): the
+// ordering with the data it guards comes from the grid / workgroup barrier
+// the readers passed; the load itself reads the device-coherent value.
+__device__ __forceinline__ int32_t ld_rlx(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+
+// Wait until every memory operation this wave issued has completed.
+__device__ __forceinline__ void wave_drain() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Append `val` for every active lane with pred set; one atomic per wave.
 // Works in divergent code: the ballot covers the active lanes only.
@@ -296,6 +299,7 @@ __device__ __forceinline__ Team block_team() { return Team{(int)threadIdx.x, (in
 // word that everyone waits on.  Device-scope release on arrival and acquire
 // on departure make plain stores before the barrier visible after it.
 __device__ __forceinline__ void gbar(Bar *b) {
+    wave_drain();  // this wave's stores and atomics have reached the cache hierarchy
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned nb = gridDim.x;
@@ -316,7 +320,7 @@ __device__ __forceinline__ void gbar(Bar *b) {
         // bug; the barrier then trips the abort word instead of hanging, and
         // the drivers stop at their next check.
         unsigned polls = 0;
-        while (__hip_atomic_load(&b->gen[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        while (__hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
             if (__hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             __builtin_amdgcn_s_sleep(2);
             if (++polls > (1u << 25)) {
@@ -324,6 +328,8 @@ __device__ __forceinline__ void gbar(Bar *b) {
                 break;
             }
         }
+        // one acquire for the whole workgroup after the wait (polls stay relaxed)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }

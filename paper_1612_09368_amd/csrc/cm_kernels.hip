@@ -364,7 +364,7 @@ __global__ void k_res_alloc(KArgs a) { res_alloc(a, grid_team()); }
 __global__ void k_res_copy(KArgs a) { res_copy(a, grid_team()); }
 __global__ void k_del_compact(KArgs a) { del_compact(a, grid_team()); }
 __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
-    int32_t ep = ld_acq(&a.ctl->epoch);
+    int32_t ep = ld_rlx(&a.ctl->epoch);
     long long scanned = 0;
     int pubs = 0;
     int n = run_iterations(a, a.inserting, a.max_iters, ep, scanned, pubs);

@@ -24,7 +24,7 @@ __device__ __forceinline__ void flush_stat(unsigned long long *dst, long long v)
 // Queue length as published by its tail, clamped to the buffer capacity
 // (a tail can pass the capacity only after an overflow, which aborts the batch).
 __device__ __forceinline__ int32_t qlen(const int32_t *tail, int32_t cap) {
-    int32_t n = ld_acq(tail);
+    int32_t n = ld_rlx(tail);
     return n < cap ? n : cap;
 }
 
@@ -512,14 +512,13 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         if (lane() == 0) {
             scanned += hi - lo;
             atomicAdd(&g.cd[v], part);
-            __threadfence();
+            wave_drain();  // the partial sum lands before this chunk counts as done
             last = atomicAdd(&g.done[v], 1) == nch - 1;
         }
         last = __shfl(last, 0);
         if (last) {
             int32_t tot = 0;
             if (lane() == 0) {
-                __threadfence();
                 g.done[v] = 0;
                 tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -699,9 +698,9 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
     const int32_t ep = it.ep;
     const bool ins = it.ins != 0;
     if (T.lead()) {
-        unsigned long long ch = (unsigned long long)ld_acq(&c->changed_count);
+        unsigned long long ch = (unsigned long long)ld_rlx(&c->changed_count);
         c->st_changed += ch;
-        c->st_evicted += ins ? (unsigned long long)ld_acq(&c->cand_count) - ch : ch;
+        c->st_evicted += ins ? (unsigned long long)ld_rlx(&c->cand_count) - ch : ch;
     }
     auto nb = [&](int32_t w, int32_t cv) -> int32_t {
         if (w < 0) return 0;
@@ -820,11 +819,11 @@ __device__ __forceinline__ bool step_is_local(const KArgs &a, const PC &pc, int6
 
 __device__ __forceinline__ bool slot_empty_f(const KArgs &a, int s) {
     Ctl *c = a.ctl;
-    return ld_acq(&c->fq_tail[s]) + ld_acq(&c->fh_tail[s]) + ld_acq(&c->fx_tail[s]) == 0;
+    return ld_rlx(&c->fq_tail[s]) + ld_rlx(&c->fh_tail[s]) + ld_rlx(&c->fx_tail[s]) == 0;
 }
 __device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
     Ctl *c = a.ctl;
-    return ld_acq(&c->eq_tail[s]) + ld_acq(&c->eh_tail[s]) == 0;
+    return ld_rlx(&c->eq_tail[s]) + ld_rlx(&c->eh_tail[s]) == 0;
 }
 
 // Step that follows pc (reads the counters pc's step published).
@@ -914,9 +913,9 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                     }
                 }
                 gbar(a.bar);
-                pc.step = ld_acq(&c->ipub[slot][0]);
-                pc.r = ld_acq(&c->ipub[slot][1]);
-                force = ld_acq(&c->ipub[slot][2]) != 0;
+                pc.step = ld_rlx(&c->ipub[slot][0]);
+                pc.r = ld_rlx(&c->ipub[slot][1]);
+                force = ld_rlx(&c->ipub[slot][2]) != 0;
                 ++pubs;
             }
             if (bar_aborted(a.bar)) break;
@@ -1043,16 +1042,16 @@ __device__ __forceinline__ DState dec_next(const KArgs &a, const DState &st) {
         nx.j = st.j + 1;
         nx.f = st.f + 1;
         const int fs = nx.f % 3;
-        if (ld_acq(&c->eq_tail[fs]) + ld_acq(&c->eh_tail[fs]) != 0) {
+        if (ld_rlx(&c->eq_tail[fs]) + ld_rlx(&c->eh_tail[fs]) != 0) {
             nx.step = D_ROUND;
             return nx;
         }
         const int s1 = nx.j % 3;
-        if (ld_acq(&c->rm_count[s1]) == 0) {
+        if (ld_rlx(&c->rm_count[s1]) == 0) {
             nx.step = D_DONE;
             return nx;
         }
-        int32_t md = ld_acq(&c->min_deg[s1]);
+        int32_t md = ld_rlx(&c->min_deg[s1]);
         nx.k = md > st.k + 1 ? md : st.k + 1;
         nx.step = D_SWEEP;
         return nx;
@@ -1060,7 +1059,7 @@ __device__ __forceinline__ DState dec_next(const KArgs &a, const DState &st) {
     // after a round
     nx.f = st.f + 1;
     const int fs = nx.f % 3;
-    if (ld_acq(&c->eq_tail[fs]) + ld_acq(&c->eh_tail[fs]) != 0) {
+    if (ld_rlx(&c->eq_tail[fs]) + ld_rlx(&c->eh_tail[fs]) != 0) {
         nx.step = D_ROUND;
         return nx;
     }
@@ -1110,12 +1109,12 @@ __device__ __forceinline__ void decompose(const KArgs &a, long long &scanned) {
                 }
             }
             gbar(a.bar);
-            st.step = ld_acq(&c->dpub[slot][0]);
-            st.k = ld_acq(&c->dpub[slot][1]);
-            st.j = ld_acq(&c->dpub[slot][2]);
-            st.f = ld_acq(&c->dpub[slot][3]);
-            kmax = ld_acq(&c->dpub[slot][4]);
-            force = ld_acq(&c->dpub[slot][5]) != 0;
+            st.step = ld_rlx(&c->dpub[slot][0]);
+            st.k = ld_rlx(&c->dpub[slot][1]);
+            st.j = ld_rlx(&c->dpub[slot][2]);
+            st.f = ld_rlx(&c->dpub[slot][3]);
+            kmax = ld_rlx(&c->dpub[slot][4]);
+            force = ld_rlx(&c->dpub[slot][5]) != 0;
             ++pubs;
         }
     }
