@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-persistent", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -126,6 +128,13 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s, d, batches = make_workload(args.warmup + args.steps)
     dev_batches = [tuple(tuple(torch.from_numpy(np.ascontiguousarray(z)).to(dev) for z in pair)
                          for pair in step) for step in batches]
@@ -182,6 +191,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "per": "batch of 100000 edges"},
         "iterations_per_batch": [x["iterations"] for x in st],
+        "rounds_per_batch": [x["rounds"] for x in st],
+        "steps_per_batch": [x["grid_steps"] + x["local_steps"] for x in st],
         "decompose": {"ms": plain["dec_ms"], "kernel_ms": plain["dec_stats"]["kernel_ms"],
                       "edges_per_s": N_EDGE / (plain["dec_ms"] * 1e-3)},
     }
