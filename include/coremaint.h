@@ -86,6 +86,8 @@ typedef struct cm_config {
                                    (0 = default) */
     int32_t local_work;         /* ... if their lists hold at most this many entries (0 = default) */
     int32_t timing;             /* 1 = time each maintenance launch with HIP events */
+    int32_t use_graph;          /* 1 = cm_run_batches replays its persistent launch from an
+                                   instantiated hipGraph (rebuilt when buffers move) */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 
@@ -105,7 +107,7 @@ typedef struct cm_batch_stats {
     int64_t grid_steps;     /* steps run by the whole grid (each ends in a grid barrier) */
     int64_t local_steps;    /* steps run inside one workgroup */
     int32_t launches;       /* maintenance kernel launches */
-    int32_t pad0;
+    int32_t graph_launch;   /* 1 when the launch was replayed from a hipGraph */
     double kernel_ms;       /* summed HIP-event time of those launches (timing = 1) */
     double ms_total;        /* wall time of the call */
 } cm_batch_stats;
@@ -180,6 +182,35 @@ int cm_num_edges(cm_graph *g, int64_t *m);
  * the edge count (CM_E_ARG if cap is too small, *m_out still set). */
 int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap,
                     int64_t *m_out, int on_device);
+
+/* Batch kinds of cm_run_batches. */
+#define CM_BATCH_INSERT 0
+#define CM_BATCH_DELETE 1
+
+/* Run nb edge batches in order (Algorithms 1 and 5 per batch).  Batch j is
+ * items [offsets[j], offsets[j+1]) of src/dst with kind kinds[j]
+ * (CM_BATCH_INSERT / CM_BATCH_DELETE); kinds and offsets are host arrays
+ * (offsets has nb+1 entries, starting at 0), src/dst follow on_device.
+ * Each batch is validated against the graph as left by the batches before
+ * it; in strict mode an invalid batch is skipped whole (results[j].status
+ * holds the code of its smallest invalid item) and later batches still run.
+ *
+ * Packed independent batches: sub (optional, same location as src) gives
+ * every item a sub-batch id in [0, nsub); a sub-batch lies inside one batch.
+ * Strictness then applies per sub-batch: a sub-batch with an invalid item
+ * is dropped whole and sub_status[b] (host, nsub entries, may be NULL)
+ * receives its code; the other sub-batches of the batch proceed.  This is
+ * how many independent graphs, packed as one disjoint union, are updated
+ * by one launch.
+ *
+ * CM_MODE_PLAIN: host loop, one cooperative launch per superior edge set.
+ * CM_MODE_PERSISTENT: one cooperative launch runs every batch (validation,
+ * reservation, all iterations, compaction); with use_graph it is replayed
+ * from a hipGraph.  results (nb entries) may be NULL.  Returns CM_OK unless
+ * the call itself failed (bad arguments, device error). */
+int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t *offsets,
+                   const int32_t *src, const int32_t *dst, const int32_t *sub, int32_t nsub,
+                   int on_device, cm_batch_stats *results, int32_t *sub_status);
 
 /* Copy the maintained superior degree SD(v) (Section IV-B definition) of
  * ids [0, n) to out; dead ids report 0. */

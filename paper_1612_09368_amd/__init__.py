@@ -23,12 +23,13 @@ OK = 0
 E_ARG, E_RANGE, E_SELF_LOOP, E_DUP, E_EXISTS, E_MISSING, E_DEAD = -1, -2, -3, -4, -5, -6, -7
 E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL = -8, -9, -10, -11, -12
 MODE_PLAIN, MODE_PERSISTENT = 0, 1
+BATCH_INSERT, BATCH_DELETE = 0, 1
 
 EXPORTED = [
     "cm_config_default", "cm_create", "cm_destroy", "cm_strerror", "cm_last_error",
     "cm_load_graph", "cm_core_decompose", "cm_insert_edges", "cm_delete_edges",
     "cm_insert_vertices", "cm_delete_vertices", "cm_get_cores", "cm_num_vertices",
-    "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees",
+    "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees", "cm_run_batches",
 ]
 
 
@@ -47,6 +48,7 @@ class Config(ctypes.Structure):
         ("local_items", ctypes.c_int32),
         ("local_work", ctypes.c_int32),
         ("timing", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -68,13 +70,13 @@ class BatchStats(ctypes.Structure):
         ("grid_steps", ctypes.c_int64),
         ("local_steps", ctypes.c_int64),
         ("launches", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("graph_launch", ctypes.c_int32),
         ("kernel_ms", ctypes.c_double),
         ("ms_total", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad0"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class CoreMaintError(RuntimeError):
@@ -112,6 +114,7 @@ def library():
         "cm_num_edges": (ctypes.c_int, [P, P]),
         "cm_export_edges": (ctypes.c_int, [P, P, P, I64, P, ctypes.c_int]),
         "cm_get_superior_degrees": (ctypes.c_int, [P, P, I32, ctypes.c_int]),
+        "cm_run_batches": (ctypes.c_int, [P, I32, P, P, P, P, P, I32, ctypes.c_int, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -157,7 +160,7 @@ class Graph:
 
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
-                 local_edges=0, local_items=0, local_work=0, timing=False, stream=None):
+                 local_edges=0, local_items=0, local_work=0, timing=False, use_graph=False, stream=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -174,6 +177,7 @@ class Graph:
         cfg.local_items = local_items
         cfg.local_work = local_work
         cfg.timing = 1 if timing else 0
+        cfg.use_graph = 1 if use_graph else 0
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()
         st = lib.cm_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -254,6 +258,31 @@ class Graph:
                                      what="cm_delete_vertices")
         return stats if check else (st, stats)
 
+    def run_batches(self, kinds, offsets, src, dst, sub=None, nsub=0):
+        """Run a sequence of edge batches (see cm_run_batches).  kinds / offsets
+        are host sequences; src, dst (and sub) may live on the device.
+        Returns (list of BatchStats, sub-batch statuses or None)."""
+        kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        nb = kinds.size
+        ps, ds, ks, m = _ptr(src, np.int32)
+        pd, dd, kd, m2 = _ptr(dst, np.int32)
+        if m != m2 or ds != dd or offsets.size != nb + 1 or (nb and offsets[-1] != m):
+            raise ValueError("inconsistent batch arrays")
+        psub, dsub, ksub = None, ds, None
+        if sub is not None:
+            psub, dsub, ksub, m3 = _ptr(sub, np.int32)
+            if m3 != m or dsub != ds:
+                raise ValueError("sub must match src")
+        res = (BatchStats * max(nb, 1))()
+        sst = np.zeros(max(nsub, 1), dtype=np.int32)
+        st = self._lib.cm_run_batches(self._h, nb, ctypes.c_void_p(kinds.ctypes.data),
+                                      ctypes.c_void_p(offsets.ctypes.data), ps, pd, psub, int(nsub), ds,
+                                      ctypes.cast(res, ctypes.c_void_p),
+                                      ctypes.c_void_p(sst.ctypes.data) if sub is not None else None)
+        self._check(st, "cm_run_batches")
+        return [res[j] for j in range(nb)], (sst[:nsub] if sub is not None else None)
+
     def num_vertices(self):
         n = ctypes.c_int32()
         a = ctypes.c_int32()
@@ -294,3 +323,77 @@ class Graph:
                                               ctypes.c_void_p(d.ctypes.data), m, ctypes.byref(got), 0),
                     "cm_export_edges")
         return s[:got.value], d[:got.value]
+
+
+class GraphPool:
+    """Many independent graphs updated together.
+
+    The graphs are packed as one disjoint union (graph i's ids are offset by
+    the sizes of the graphs before it); a disjoint union has no edge between
+    two members, so its core numbers are exactly the members' core numbers.
+    Per-graph batches are grouped into stages (the t-th batch of every graph)
+    and each stage becomes one insertion and one deletion batch of the union,
+    packed with a sub-batch id per member batch, so that one
+    ``cm_run_batches`` call (one persistent launch, optionally a hipGraph
+    replay) updates every graph; an invalid member batch is dropped alone.
+    """
+
+    def __init__(self, graphs, **cfg):
+        self.sizes = [int(n) for n, _, _ in graphs]
+        self.base = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        src = np.concatenate([np.asarray(s, np.int64) + b for (_, s, _), b in zip(graphs, self.base)]) \
+            if graphs else np.empty(0, np.int64)
+        dst = np.concatenate([np.asarray(d, np.int64) + b for (_, _, d), b in zip(graphs, self.base)]) \
+            if graphs else np.empty(0, np.int64)
+        self.graph = Graph(**cfg)
+        self.graph.load(int(self.base[-1]), src.astype(np.int32), dst.astype(np.int32))
+        self.graph.decompose()
+
+    def pack(self, batches):
+        """batches: list of (graph_id, kind, src, dst) in submission order.
+        Returns (kinds, offsets, src, dst, sub, nsub, order) where order[k] is
+        the sub-batch id of submission k."""
+        per_graph = {}
+        stage_of = []
+        for k, (gid, kind, s, d) in enumerate(batches):
+            t = per_graph.get(gid, 0)
+            per_graph[gid] = t + 1
+            stage_of.append(t)
+        nstages = max(stage_of) + 1 if batches else 0
+        kinds, offs, srcs, dsts, subs = [], [0], [], [], []
+        order = np.full(len(batches), -1, dtype=np.int64)
+        nsub = 0
+        for t in range(nstages):
+            for kind in (BATCH_INSERT, BATCH_DELETE):
+                members = [k for k in range(len(batches)) if stage_of[k] == t and batches[k][1] == kind]
+                if not members:
+                    continue
+                for k in members:
+                    gid, _, s, d = batches[k]
+                    b = self.base[gid]
+                    srcs.append(np.asarray(s, np.int64) + b)
+                    dsts.append(np.asarray(d, np.int64) + b)
+                    subs.append(np.full(len(s), nsub, np.int32))
+                    order[k] = nsub
+                    nsub += 1
+                kinds.append(kind)
+                offs.append(offs[-1] + sum(len(batches[k][2]) for k in members))
+        cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.empty(0, dt))
+        return (np.asarray(kinds, np.int32), np.asarray(offs, np.int64), cat(srcs, np.int32),
+                cat(dsts, np.int32), cat(subs, np.int32), nsub, order)
+
+    def run(self, batches, device=None):
+        """Apply the per-graph batches; returns one status per submission."""
+        kinds, offs, s, d, sub, nsub, order = self.pack(batches)
+        if device is not None:
+            torch = _torch()
+            s, d, sub = (torch.from_numpy(x).to(device) for x in (s, d, sub))
+        stats, sst = self.graph.run_batches(kinds, offs, s, d, sub=sub, nsub=nsub)
+        return [int(sst[order[k]]) for k in range(len(batches))], stats
+
+    def cores(self, gid):
+        c = self.graph.cores()
+        return c[self.base[gid]:self.base[gid + 1]]
+
+    def close(self):
+        self.graph.close()

@@ -51,6 +51,20 @@ struct cm_graph {
     unsigned long long *hu64 = nullptr;  // pinned host scratch
     int32_t *firstidx = nullptr;      // [n_cap] vertex-deletion duplicate check
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int coop_prog = 0;        // cooperative grid of the batch program kernel
+    // batch programs (cm_run_batches)
+    ProgDesc *d_prog = nullptr;
+    ProgDesc *h_prog = nullptr;       // pinned
+    ProgBatch *d_pbatch = nullptr;
+    ProgOut *d_pout = nullptr;
+    int32_t prog_cap = 0;
+    int32_t *d_isrc = nullptr, *d_idst = nullptr, *d_isub = nullptr;  // staged host items
+    int64_t items_cap = 0;
+    unsigned long long *d_sub_bad = nullptr;
+    int32_t sub_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<char> graph_key;
 
     bool loaded = false;
     bool decomposed = false;
@@ -300,7 +314,7 @@ void ensure_batch(cm_graph *g, int64_t s) {
     g->b.hcap = (int32_t)hc;
     HIPCHK(fill_u64(g->b.hkey, ~0ull, hc, g->stream));
     HIPCHK(fill_i32(g->b.hval, INT_MAX, hc, g->stream));
-    int64_t sc = 2 * s + (int64_t)(g->hctl->pool_tail / (unsigned long long)std::max(1, g->tune.chunk)) + 1024;
+    int64_t sc = 2 * s + g->g.pool_size / std::max(1, g->tune.chunk) + 1024;
     sc = std::min<int64_t>(sc, INT_MAX);
     if (sc > g->scan_cap) {
         dev_free(g->b.scanq);
@@ -393,7 +407,7 @@ int64_t alg_bytes(const Ctl &c, int rounds) {
 // Validate a batch already staged in g->b.src_in/dst_in (s items).  Returns
 // the number of valid items; in strict mode throws on the first bad item.
 int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *first_bad,
-                 int cur, cm_batch_stats *stats) {
+                 int cur, cm_batch_stats *stats, bool packed) {
     hipStream_t st = g->stream;
     g->bstamp += 2;
     HIPCHK(ctl_batch_reset(g->ctl, cur, st));
@@ -402,13 +416,15 @@ int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *f
     a.s = (int32_t)s;
     a.bstamp = g->bstamp;
     a.cur = cur;
+    a.strict = strict ? 1 : 0;
+    if (!packed) a.b.sub_in = nullptr;
     HIPCHK(validate_batch(a, g->grid_reg, st));
     sync_ctl(g);
     check_overflow(g);
     int32_t fb = g->hctl->first_bad;
     *first_bad = fb == INT_MAX ? -1 : fb;
     if (stats) stats->first_bad = *first_bad;
-    if (fb != INT_MAX && strict) {
+    if (fb != INT_MAX && strict && !packed) {
         int32_t code = 0;
         HIPCHK(hipMemcpyAsync(&code, g->b.err + fb, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -483,12 +499,12 @@ void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
 
 // Shared body of edge insertion / deletion on staged device inputs.
 int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats, int64_t *dropped,
-                   bool strict_override, bool strict_value) {
+                   bool strict_override, bool strict_value, bool packed = false) {
     hipStream_t st = g->stream;
     bool strict = strict_override ? strict_value : g->cfg.strict != 0;
     int cur = (g->epoch + 1) & 1;
     int64_t fb = -1;
-    int64_t valid = validate(g, s, inserting, strict, &fb, cur, stats);
+    int64_t valid = validate(g, s, inserting, strict, &fb, cur, stats, packed);
     *dropped = s - valid;
     if (stats) stats->first_bad = fb;
     if (valid == 0) {
@@ -524,6 +540,56 @@ int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats
     }
     g->m += inserting ? valid : -valid;
     return valid;
+}
+
+// Launch the batch program (device descriptor already written): directly as
+// a cooperative kernel, or by replaying an instantiated hipGraph whose single
+// cooperative kernel node carries the current KArgs (rebuilt when any buffer
+// address or size in KArgs changed).  Returns 1 when the graph was used.
+int launch_program(cm_graph *g, const KArgs &a) {
+    hipStream_t st = g->stream;
+    if (!g->cfg.use_graph) {
+        HIPCHK(program_coop(a, g->coop_prog, st));
+        return 0;
+    }
+    std::vector<char> key(sizeof(KArgs) + sizeof(int));
+    std::memcpy(key.data(), &a, sizeof(KArgs));
+    std::memcpy(key.data() + sizeof(KArgs), &g->coop_prog, sizeof(int));
+    if (!g->gexec || key != g->graph_key) {
+        if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        g->gexec = nullptr;
+        g->graph = nullptr;
+        KArgs copy = a;
+        void *args[] = {&copy};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(program_kernel());
+        p.gridDim = dim3(g->coop_prog);
+        p.blockDim = dim3(COOP_THREADS);
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphCreate(&g->graph, 0));
+        HIPCHK(hipGraphAddKernelNode(&node, g->graph, nullptr, 0, &p));
+        hipKernelNodeAttrValue v;
+        std::memset(&v, 0, sizeof(v));
+        v.cooperative = 1;
+        HIPCHK(hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v));
+        HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
+        g->graph_key = key;
+    }
+    HIPCHK(hipGraphLaunch(g->gexec, st));
+    return 1;
+}
+
+template <class T>
+void grow_dev(cm_graph *g, T *&p, int64_t &cap_io, int64_t need) {
+    if (need <= cap_io && p) return;
+    dev_free(p);
+    int64_t c = std::max<int64_t>(need, 1024);
+    dev_alloc(g, &p, c);
+    cap_io = c;
 }
 
 void stage_inputs(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device) {
@@ -564,6 +630,12 @@ void release_all(cm_graph *g) {
         dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.fx[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
     }
     dev_free(q.cand); dev_free(q.chg); dev_free(q.chh); dev_free(q.touched);
+    dev_free(g->d_pbatch); dev_free(g->d_pout); dev_free(g->d_isrc); dev_free(g->d_idst);
+    dev_free(g->d_isub); dev_free(g->d_sub_bad);
+    g->prog_cap = 0; g->items_cap = 0; g->sub_cap = 0;
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->gexec = nullptr; g->graph = nullptr; g->graph_key.clear();
     // (the small scratch buffers allocated by cm_create stay until cm_destroy)
     dev_free(g->src_buf); dev_free(g->dst_buf); dev_free(g->scan_tmp); dev_free(g->firstidx);
     g->g = DevGraph{};
@@ -644,6 +716,12 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->coop_maint = g->num_cu * std::max(1, std::min(want, bpc_m));
         g->coop_dec = g->num_cu * std::max(1, std::min(want, bpc_d));
         g->grid_reg = g->num_cu * 8;
+        int bpc_p = 0;
+        HIPCHK(coop_occupancy(2, &bpc_p));
+        g->coop_prog = g->num_cu * std::max(1, std::min(want, bpc_p));
+        dev_alloc(g, &g->d_prog, 1);
+        HIPCHK(hipHostMalloc((void **)&g->h_prog, sizeof(ProgDesc), hipHostMallocDefault));
+        std::memset(g->h_prog, 0, sizeof(ProgDesc));
         dev_alloc(g, &g->ctl, 1);
         HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
         dev_alloc(g, &g->bar, 1);
@@ -670,6 +748,8 @@ void cm_destroy(cm_graph *g) {
     release_all(g);
     dev_free(g->i64_scratch);
     dev_free(g->u64_scratch);
+    dev_free(g->d_prog);
+    if (g->h_prog) (void)hipHostFree(g->h_prog);
     if (g->ctl) (void)hipFree(g->ctl);
     if (g->bar) (void)hipFree(g->bar);
     if (g->hctl) (void)hipHostFree(g->hctl);
@@ -1090,6 +1170,208 @@ int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap, int64_
     } catch (const Fail &f) {
         return f.code;
     }
+    return CM_OK;
+}
+
+int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t *offsets,
+                   const int32_t *src, const int32_t *dst, const int32_t *sub, int32_t nsub,
+                   int on_device, cm_batch_stats *results, int32_t *sub_status) {
+    if (!g || nb < 0 || (nb > 0 && (!kinds || !offsets))) return CM_E_ARG;
+    if (nsub < 0 || (sub && nsub == 0)) return CM_E_ARG;
+    double t0 = now_ms();
+    if (results)
+        for (int32_t j = 0; j < nb; ++j) {
+            std::memset(&results[j], 0, sizeof(cm_batch_stats));
+            results[j].first_bad = -1;
+        }
+    if (sub_status)
+        for (int32_t b = 0; b < nsub; ++b) sub_status[b] = CM_OK;
+    try {
+        require_ready(g, true);
+        if (nb == 0) return CM_OK;
+        if (offsets[0] != 0) { g->err = "offsets[0] must be 0"; throw Fail{CM_E_ARG}; }
+        int64_t max_s = 0;
+        for (int32_t j = 0; j < nb; ++j) {
+            int64_t sj = offsets[j + 1] - offsets[j];
+            if (sj < 0) { g->err = "offsets must be non-decreasing"; throw Fail{CM_E_ARG}; }
+            if (kinds[j] != CM_BATCH_INSERT && kinds[j] != CM_BATCH_DELETE) {
+                g->err = "unknown batch kind";
+                throw Fail{CM_E_ARG};
+            }
+            max_s = std::max(max_s, sj);
+        }
+        const int64_t total = offsets[nb];
+        if (total > 0 && (!src || !dst)) throw Fail{CM_E_ARG};
+        if (max_s > INT_MAX / 2) { g->err = "batch too large"; throw Fail{CM_E_ARG}; }
+        hipStream_t st = g->stream;
+        ensure_batch(g, std::max<int64_t>(max_s, 1));
+        // items on the device
+        const int32_t *ds = src, *dd = dst, *dsub = sub;
+        if (!on_device && total > 0) {
+            if (total > g->items_cap) {
+                dev_free(g->d_isrc); dev_free(g->d_idst); dev_free(g->d_isub);
+                int64_t c = std::max<int64_t>(total, 1024);
+                dev_alloc(g, &g->d_isrc, c);
+                dev_alloc(g, &g->d_idst, c);
+                dev_alloc(g, &g->d_isub, c);
+                g->items_cap = c;
+            }
+            HIPCHK(hipMemcpyAsync(g->d_isrc, src, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(g->d_idst, dst, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, st));
+            if (sub)
+                HIPCHK(hipMemcpyAsync(g->d_isub, sub, sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, st));
+            ds = g->d_isrc;
+            dd = g->d_idst;
+            dsub = sub ? g->d_isub : nullptr;
+        }
+        if (sub) {
+            int64_t cap = g->sub_cap;
+            grow_dev(g, g->d_sub_bad, cap, nsub);
+            g->sub_cap = (int32_t)cap;
+            HIPCHK(fill_u64(g->d_sub_bad, ~0ull, nsub, st));
+        }
+        g->b.sub_bad = g->d_sub_bad;
+        const bool strict = g->cfg.strict != 0;
+
+        if (g->cfg.mode == CM_MODE_PLAIN) {
+            for (int32_t j = 0; j < nb; ++j) {
+                int64_t sj = offsets[j + 1] - offsets[j];
+                if (sj == 0) continue;
+                ensure_batch(g, sj);  // no reallocation (max size done above); clears the batch hash
+                g->b.src_in = const_cast<int32_t *>(ds + offsets[j]);
+                g->b.dst_in = const_cast<int32_t *>(dd + offsets[j]);
+                g->b.sub_in = dsub ? dsub + offsets[j] : nullptr;
+                cm_batch_stats tmp;
+                std::memset(&tmp, 0, sizeof(tmp));
+                tmp.first_bad = -1;
+                int64_t dropped = 0;
+                try {
+                    edge_batch(g, sj, kinds[j] == CM_BATCH_INSERT, &tmp, &dropped, false, false, dsub != nullptr);
+                } catch (const Fail &f) {
+                    if (g->poisoned || f.code > CM_E_RANGE || f.code < CM_E_DEAD) throw;
+                    tmp.status = f.code;
+                }
+                if (results) results[j] = tmp;
+            }
+            g->b.sub_in = nullptr;
+        } else {
+            if (nb > g->prog_cap) {
+                dev_free(g->d_pbatch);
+                dev_free(g->d_pout);
+                int32_t c = std::max(nb, 64);
+                dev_alloc(g, &g->d_pbatch, c);
+                dev_alloc(g, &g->d_pout, c);
+                g->prog_cap = c;
+            }
+            std::vector<ProgBatch> pb(nb);
+            for (int32_t j = 0; j < nb; ++j) {
+                pb[j].off = offsets[j];
+                pb[j].s = (int32_t)(offsets[j + 1] - offsets[j]);
+                pb[j].kind = kinds[j];
+            }
+            HIPCHK(hipMemcpyAsync(g->d_pbatch, pb.data(), sizeof(ProgBatch) * (size_t)nb, hipMemcpyHostToDevice, st));
+            std::vector<ProgOut> out(nb);
+            int32_t first = 0;
+            int used_graph = 0;
+            double kms = 0.0;
+            int launches = 0;
+            for (int attempt = 0; attempt < 8; ++attempt) {
+                ProgDesc *hd = g->h_prog;
+                hd->batches = g->d_pbatch;
+                hd->out = g->d_pout;
+                hd->src = ds;
+                hd->dst = dd;
+                hd->sub = dsub;
+                hd->sub_bad = dsub ? g->d_sub_bad : nullptr;
+                hd->nb = nb;
+                hd->first = first;
+                hd->strict = strict ? 1 : 0;
+                hd->bstamp0 = g->bstamp + 2;
+                hd->stop = first;
+                hd->pool_fail = 0;
+                g->bstamp += 2 * (nb - first) + 2;
+                HIPCHK(hipMemcpyAsync(g->d_prog, hd, sizeof(ProgDesc), hipMemcpyHostToDevice, st));
+                KArgs a = make_args(g);
+                a.prog = g->d_prog;
+                if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
+                used_graph |= launch_program(g, a);
+                if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
+                ++launches;
+                HIPCHK(hipMemcpyAsync(g->h_prog, g->d_prog, sizeof(ProgDesc), hipMemcpyDeviceToHost, st));
+                sync_ctl(g);
+                check_abort(g);
+                check_overflow(g);
+                if (g->cfg.timing) {
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+                    kms += ms;
+                }
+                g->epoch = g->hctl->epoch;
+                int32_t stop = g->h_prog->stop;
+                if (stop > first)
+                    HIPCHK(hipMemcpy(out.data() + first, g->d_pout + first, sizeof(ProgOut) * (size_t)(stop - first),
+                                     hipMemcpyDeviceToHost));
+                if (!g->h_prog->pool_fail) {
+                    if (stop != nb) {
+                        g->poisoned = true;
+                        g->err = "batch program stopped early";
+                        throw Fail{CM_E_INTERNAL};
+                    }
+                    break;
+                }
+                // adjacency pool exhausted at batch `stop`: repack with room, resume there
+                int64_t pending = 0;
+                for (int32_t j = stop; j < nb; ++j)
+                    if (kinds[j] == CM_BATCH_INSERT) pending += offsets[j + 1] - offsets[j];
+                repack(g, 4 * pending + g->g.pool_size / 2);
+                first = stop;
+                if (attempt == 7) {
+                    g->err = "adjacency pool could not be grown";
+                    throw Fail{CM_E_NOMEM};
+                }
+            }
+            for (int32_t j = 0; j < nb; ++j) {
+                const ProgOut &o = out[j];
+                if (o.status == 0) g->m += kinds[j] == CM_BATCH_INSERT ? o.valid : -(int64_t)o.valid;
+                if (!results) continue;
+                cm_batch_stats &r = results[j];
+                r.status = o.status;
+                r.iterations = o.iterations;
+                r.first_bad = o.first_bad;
+                r.applied = o.valid;
+                r.dropped = o.status == 0 ? (offsets[j + 1] - offsets[j]) - o.valid : 0;
+                r.remaining_sum = (int64_t)o.remaining;
+                r.candidates = (int64_t)o.candidates;
+                r.evicted = (int64_t)o.evicted;
+                r.changed = (int64_t)o.changed;
+                r.scanned = (int64_t)o.scanned;
+                r.rounds = (int64_t)o.rounds;
+                r.local_steps = (int64_t)o.steps;
+                Ctl tmp{};
+                tmp.st_remaining = o.remaining;
+                tmp.st_selected = o.selected;
+                tmp.st_scanned = o.scanned;
+                tmp.st_candidates = o.candidates;
+                tmp.st_changed = o.changed;
+                r.alg_bytes = alg_bytes(tmp, g->tune.rounds);
+                r.launches = j == 0 ? launches : 0;
+                r.graph_launch = used_graph;
+                r.kernel_ms = j == 0 ? kms : 0.0;
+            }
+        }
+        g->b.sub_in = nullptr;
+        if (sub && sub_status) {
+            std::vector<unsigned long long> sb(nsub);
+            HIPCHK(hipMemcpy(sb.data(), g->d_sub_bad, sizeof(unsigned long long) * (size_t)nsub, hipMemcpyDeviceToHost));
+            for (int32_t b = 0; b < nsub; ++b)
+                sub_status[b] = sb[b] == ~0ull ? CM_OK : -(int)(sb[b] & 0xff);
+        }
+        if (results && nb > 0) results[0].ms_total = now_ms() - t0;
+    } catch (const Fail &f) {
+        g->b.sub_in = nullptr;
+        return f.code;
+    }
+    g->err.clear();
     return CM_OK;
 }
 

@@ -120,6 +120,8 @@ struct DevBatch {
     int32_t *vlist;      // [n_cap] distinct batch endpoints (reservation / compaction)
     int64_t *scanq;      // [scap] (vertex, chunk) locate-scan items
     int32_t scap;
+    const int32_t *sub_in;  // sub-batch id per item (packed batches) or null
+    unsigned long long *sub_bad;  // per sub-batch min of (item << 8 | -code)
     int32_t *reloc;      // [n_cap] relocated vertices
     int64_t *reloc_off;  // [n_cap] their new first slot
     int32_t *reloc_cap;  // [n_cap] their new capacity
@@ -155,6 +157,8 @@ struct Tune {
 
 constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
 
+struct ProgDesc;
+
 struct KArgs {
     DevGraph g;
     DevBatch b;
@@ -162,29 +166,62 @@ struct KArgs {
     Tune t;
     Ctl *ctl;
     Bar *bar;
+    ProgDesc *prog;      // batch program of a persistent multi-batch launch
     int32_t inserting;   // 1 = insertion batch, 0 = deletion batch
     int32_t max_iters;   // iterations this launch may run
     int32_t s;           // batch items
     int32_t bstamp;      // batch stamp (bmark values bstamp, bstamp + 1)
     int32_t cur;         // remaining list that receives the validated batch
-    int32_t pad;
+    int32_t strict;      // packed sub-batches: drop a sub-batch with an invalid item
 };
 
 // Per-batch parameters of the validation / reservation steps.
 struct BatchCtx {
     const int32_t *src;  // raw items
     const int32_t *dst;
+    const int32_t *sub;  // sub-batch of each item (packed independent batches) or null
+    unsigned long long *sub_bad;  // per sub-batch min of (item << 8 | -code), ~0 if none
     int32_t s;           // item count
     int32_t inserting;   // 1 = insertion batch
     int32_t cur;         // remaining list that receives the valid items
     int32_t bstamp;      // per-vertex mark values bstamp (scan) and bstamp + 1 (endpoints)
     int32_t hcap;        // hash slots used (power of two, <= allocated)
-    int32_t pad;
+    int32_t strict;      // reject a whole (sub-)batch that has an invalid item
 };
 
 __device__ __forceinline__ BatchCtx batch_of(const KArgs &a) {
-    return BatchCtx{a.b.src_in, a.b.dst_in, a.s, a.inserting, a.cur, a.bstamp, a.b.hcap, 0};
+    return BatchCtx{a.b.src_in, a.b.dst_in, a.b.sub_in, a.b.sub_bad, a.s, a.inserting, a.cur, a.bstamp,
+                    a.b.hcap, a.strict};
 }
+
+// A sequence of batches run by one persistent launch.  Batch j covers items
+// [off, off + s) of src/dst (and of sub, when it packs independent batches).
+struct ProgBatch {
+    int64_t off;
+    int32_t s;
+    int32_t kind;        // 0 = insert edges, 1 = delete edges
+};
+struct ProgOut {
+    int32_t status;      // 0 or the error code of the first invalid item (strict)
+    int32_t first_bad;
+    int32_t valid;
+    int32_t iterations;
+    unsigned long long remaining, selected, candidates, evicted, changed, scanned, rounds, steps;
+};
+struct ProgDesc {
+    const ProgBatch *batches;
+    ProgOut *out;
+    const int32_t *src;
+    const int32_t *dst;
+    const int32_t *sub;  // sub-batch id per item (or null)
+    unsigned long long *sub_bad;  // per sub-batch min of (item << 8 | -code) (or null)
+    int32_t nb;
+    int32_t first;       // first batch to run
+    int32_t strict;
+    int32_t bstamp0;
+    int32_t stop;        // written: first batch not completed (nb when all ran)
+    int32_t pool_fail;   // written: 1 when the launch stopped for a pool repack
+};
 
 // ---------------------------------------------------------------------------
 // Wave helpers

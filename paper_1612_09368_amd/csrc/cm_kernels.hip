@@ -359,6 +359,7 @@ __global__ void k_val_canon(KArgs a) { val_canon(a, batch_of(a), grid_team()); }
 __global__ void k_val_dup_mark(KArgs a) { val_dup_mark(a, batch_of(a), grid_team()); }
 __global__ void k_val_scan(KArgs a) { val_scan(a, batch_of(a), grid_team()); }
 __global__ void k_val_final(KArgs a) { val_final(a, batch_of(a), grid_team()); }
+__global__ void k_val_subfilter(KArgs a) { val_subfilter(a, batch_of(a), grid_team()); }
 __global__ void k_res_gain(KArgs a) { res_gain(a, batch_of(a), grid_team()); }
 __global__ void k_res_alloc(KArgs a) { res_alloc(a, grid_team()); }
 __global__ void k_res_copy(KArgs a) { res_copy(a, grid_team()); }
@@ -374,6 +375,8 @@ __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
         a.ctl->iters_done = n;
     }
 }
+
+__global__ void __launch_bounds__(COOP_THREADS) k_program(KArgs a) { run_program(a); }
 
 // ---------------------------------------------------------------------------
 // Vertex operations
@@ -585,6 +588,7 @@ hipError_t validate_batch(const KArgs &a, int blocks, hipStream_t st) {
     k_val_dup_mark<<<blocks, 256, 0, st>>>(a);
     k_val_scan<<<blocks, 256, 0, st>>>(a);
     k_val_final<<<blocks, 256, 0, st>>>(a);
+    if (a.b.sub_in) k_val_subfilter<<<blocks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 hipError_t reserve_gain(const KArgs &a, int blocks, hipStream_t st) {
@@ -603,6 +607,10 @@ hipError_t delete_compact(const KArgs &a, int blocks, hipStream_t st) {
 hipError_t maintain_coop(const KArgs &a, int blocks, hipStream_t st) {
     return coop((const void *)k_maintain, a, blocks, st);
 }
+hipError_t program_coop(const KArgs &a, int blocks, hipStream_t st) {
+    return coop((const void *)k_program, a, blocks, st);
+}
+const void *program_kernel() { return (const void *)k_program; }
 hipError_t vins_init(const KArgs &a, int32_t first, int32_t c, hipStream_t st) {
     k_vins_init<<<grid_for(c, 4096), 256, 0, st>>>(a, first, c);
     return hipGetLastError();
@@ -638,7 +646,9 @@ hipError_t vdel_finish(const KArgs &a, const int32_t *ids, int32_t c, hipStream_
 }
 
 hipError_t coop_occupancy(int which, int *blocks_per_cu) {
-    const void *fn = which == 0 ? (const void *)k_maintain : (const void *)k_decompose;
+    const void *fn = which == 0 ? (const void *)k_maintain
+                     : which == 1 ? (const void *)k_decompose
+                                  : (const void *)k_program;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, COOP_THREADS, 0);
 }
 

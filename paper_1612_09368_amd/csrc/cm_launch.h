@@ -38,6 +38,8 @@ hipError_t reserve_gain(const KArgs &a, int blocks, hipStream_t st);
 hipError_t reserve_alloc_copy(const KArgs &a, int blocks, hipStream_t st);
 hipError_t delete_compact(const KArgs &a, int blocks, hipStream_t st);
 hipError_t maintain_coop(const KArgs &a, int blocks, hipStream_t st);
+hipError_t program_coop(const KArgs &a, int blocks, hipStream_t st);
+const void *program_kernel();
 
 hipError_t vins_init(const KArgs &a, int32_t first, int32_t c, hipStream_t st);
 hipError_t vins_revert(const KArgs &a, int32_t first, int32_t c, hipStream_t st);
@@ -50,7 +52,7 @@ hipError_t vdel_gather(const KArgs &a, const int32_t *ids, int32_t c, int32_t *x
                        int64_t cap, unsigned long long *tail, int blocks, hipStream_t st);
 hipError_t vdel_finish(const KArgs &a, const int32_t *ids, int32_t c, hipStream_t st);
 
-// which: 0 = maintenance kernel, 1 = decomposition kernel
+// which: 0 = maintenance kernel, 1 = decomposition kernel, 2 = batch program kernel
 hipError_t coop_occupancy(int which, int *blocks_per_cu);
 
 }  // namespace cm

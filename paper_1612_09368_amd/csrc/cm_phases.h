@@ -140,7 +140,8 @@ __device__ __forceinline__ void val_scan(const KArgs &a, const BatchCtx &bc, con
 }
 
 // V4: missing edges, smallest invalid index, emit valid item indices into
-// the remaining list `cur`.
+// the remaining list `cur`.  For packed independent batches the smallest
+// invalid item is kept per sub-batch and the emission waits for V5.
 __device__ __forceinline__ void val_final(const KArgs &a, const BatchCtx &bc, const Team &T) {
     for (int32_t i = T.rank; i < bc.s; i += T.size) {
         int32_t e = a.b.err[i];
@@ -148,9 +149,22 @@ __device__ __forceinline__ void val_final(const KArgs &a, const BatchCtx &bc, co
             e = ST_MISSING;
             a.b.err[i] = e;
         }
-        if (e != 0) atomicMin(&a.ctl->first_bad, i);
-        push_agg<int32_t>(a.b.rem[bc.cur], a.b.cap, &a.ctl->rem_count[bc.cur], i, e == 0,
+        if (e != 0) {
+            atomicMin(&a.ctl->first_bad, i);
+            if (bc.sub)
+                atomicMin(&bc.sub_bad[bc.sub[i]], ((unsigned long long)i << 8) | (unsigned long long)(-e));
+        }
+        push_agg<int32_t>(a.b.rem[bc.cur], a.b.cap, &a.ctl->rem_count[bc.cur], i, e == 0 && !bc.sub,
                           &a.ctl->overflow);
+    }
+}
+
+// V5 (packed batches): emit the valid items; in strict mode a sub-batch with
+// an invalid item is dropped whole, the others go on.
+__device__ __forceinline__ void val_subfilter(const KArgs &a, const BatchCtx &bc, const Team &T) {
+    for (int32_t i = T.rank; i < bc.s; i += T.size) {
+        bool ok = a.b.err[i] == 0 && !(bc.strict && bc.sub_bad[bc.sub[i]] != ~0ull);
+        push_agg<int32_t>(a.b.rem[bc.cur], a.b.cap, &a.ctl->rem_count[bc.cur], i, ok, &a.ctl->overflow);
     }
 }
 
@@ -924,6 +938,145 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
         if (pc.step != S_DONE) { ++it_n; break; }
     }
     return it_n;
+}
+
+// ===========================================================================
+// Batch program: a sequence of batches in one persistent launch.  For each
+// batch: clear the hash, validate, reserve (insertion) or count tombstones
+// (deletion), run all its iterations, compact (deletion), record the
+// outcome.  A strict batch with an invalid item (or a packed sub-batch with
+// one) is skipped without touching the graph.  When the adjacency pool runs
+// out during a reservation the launch stops before mutating anything of that
+// batch and reports where (the host repacks and relaunches from there).
+// ===========================================================================
+__device__ __forceinline__ int32_t hash_slots(int32_t s) {
+    int32_t want = 2 * s > 1024 ? 2 * s : 1024;
+    int32_t h = 1024;
+    while (h < want) h <<= 1;
+    return h;
+}
+
+__device__ __forceinline__ void prog_setup(const KArgs &a, const BatchCtx &bc, const ProgBatch &B,
+                                          const Team &T) {
+    Ctl *c = a.ctl;
+    if (T.lead()) {
+        c->rem_count[0] = 0;
+        c->rem_count[1] = 0;
+        c->sel_count = 0;
+        for (int j = 0; j < 3; ++j) {
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->eq_tail[j] = 0; c->eh_tail[j] = 0;
+        }
+        c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
+        c->touched_count = 0; c->changed_count = 0;
+        c->pool_fail = 0;
+        c->first_bad = 0x7fffffff;
+        c->scan_tail = 0;
+        c->vlist_count = 0;
+        c->reloc_count = 0;
+        c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
+        c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
+        c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
+    }
+    for (int32_t i = T.rank; i < bc.hcap; i += T.size) {
+        a.b.hkey[i] = EMPTY_KEY;
+        a.b.hval[i] = 0x7fffffff;
+    }
+}
+
+__device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t status, int32_t fb, int32_t valid,
+                                           int32_t iters) {
+    Ctl *c = a.ctl;
+    o.status = status;
+    o.first_bad = fb;
+    o.valid = valid;
+    o.iterations = iters;
+    o.remaining = c->st_remaining;
+    o.selected = c->st_selected;
+    o.candidates = c->st_candidates;
+    o.evicted = c->st_evicted;
+    o.changed = c->st_changed;
+    o.scanned = c->st_scanned;
+    o.rounds = c->st_rounds;
+    o.steps = c->st_grid_steps + c->st_local_steps;
+}
+
+__device__ __forceinline__ void run_program(const KArgs &a) {
+    Ctl *c = a.ctl;
+    ProgDesc *pd = a.prog;
+    int32_t ep = ld_rlx(&c->epoch);
+    long long scanned = 0;
+    int pubs = 0;
+    const int32_t nb = pd->nb;
+    int32_t j = pd->first;
+    int32_t failed = 0;
+    const Team G = grid_team();
+    for (; j < nb; ++j) {
+        if (bar_aborted(a.bar)) break;
+        const ProgBatch B = pd->batches[j];
+        BatchCtx bc;
+        bc.src = pd->src + B.off;
+        bc.dst = pd->dst + B.off;
+        bc.sub = pd->sub ? pd->sub + B.off : nullptr;
+        bc.sub_bad = pd->sub_bad;
+        bc.s = B.s;
+        bc.inserting = B.kind == 0;
+        bc.cur = (ep + 1) & 1;
+        bc.bstamp = pd->bstamp0 + 2 * (j - pd->first);
+        bc.hcap = hash_slots(B.s);
+        bc.strict = pd->strict;
+        if (bc.hcap > a.b.hcap || B.s > a.b.cap) {  // host sized the buffers for the largest batch
+            if (gtid() == 0) atomicOr(&c->overflow, 8);
+            break;
+        }
+        prog_setup(a, bc, B, G);
+        gbar(a.bar);
+        val_canon(a, bc, G);
+        gbar(a.bar);
+        val_dup_mark(a, bc, G);
+        gbar(a.bar);
+        val_scan(a, bc, G);
+        gbar(a.bar);
+        val_final(a, bc, G);
+        gbar(a.bar);
+        if (bc.sub) {
+            val_subfilter(a, bc, G);
+            gbar(a.bar);
+        }
+        const int32_t fb = ld_rlx(&c->first_bad);
+        const int32_t valid = qlen(&c->rem_count[bc.cur], a.b.cap);
+        if ((pd->strict && !bc.sub && fb != 0x7fffffff) || valid == 0) {
+            if (gtid() == 0) {
+                int32_t st = (pd->strict && !bc.sub && fb != 0x7fffffff) ? a.b.err[fb] : 0;
+                prog_record(a, pd->out[j], st, fb == 0x7fffffff ? -1 : fb, 0, 0);
+            }
+            gbar(a.bar);  // every workgroup has read the counters before the next setup
+            continue;
+        }
+        res_gain(a, bc, G);
+        gbar(a.bar);
+        if (bc.inserting) {
+            res_alloc(a, G);
+            gbar(a.bar);
+            if (ld_rlx(&c->pool_fail)) { failed = 1; break; }
+            res_copy(a, G);
+            gbar(a.bar);
+        }
+        const int iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
+        if (!bc.inserting) {
+            del_compact(a, G);
+            gbar(a.bar);
+        }
+        flush_stat(&c->st_scanned, scanned);
+        scanned = 0;
+        gbar(a.bar);
+        if (gtid() == 0) prog_record(a, pd->out[j], 0, fb == 0x7fffffff ? -1 : fb, valid, iters);
+    }
+    if (gtid() == 0) {
+        c->epoch = ep;
+        pd->stop = j;
+        pd->pool_fail = failed;
+    }
 }
 
 // ===========================================================================
