@@ -1,15 +1,32 @@
 """Benchmark: edge updates per second of batched core maintenance on one MI355X.
 
-Workload (one step = the whole maintenance path over one batch pair):
-Chung-Lu power-law graph, n = 1,000,000, m = 10,000,000, degree exponent 2.1,
-largest weight 50,000 (seeded, synthetic); every step inserts 100,000
-degree-weighted non-edges and then deletes 100,000 uniformly drawn existing
-edges, with exact core numbers after each batch.  `value` is the plain form
-(one cooperative launch per superior edge set, host checks termination);
-the persistent form (one launch per batch) is reported beside it on the same
-batches.  Inputs are resident in device memory before the timed region.
+Workloads (``--workload``; every graph and update stream is seeded and
+synthetic, and inputs are resident in device memory before the timed region):
 
-Prints one JSON line (see the fields below).
+chunglu-1m (default)
+    Chung-Lu power-law graph, n = 1,000,000, m = 10,000,000, degree exponent
+    2.1, largest weight 50,000.  One step inserts 100,000 degree-weighted
+    non-edges and then deletes 100,000 uniformly drawn existing edges, with
+    exact core numbers after each batch.  `value` is the plain form (one
+    cooperative launch per superior edge set, the host checks termination);
+    the persistent form (one launch per batch) and the batched form (every
+    timed batch in one launch) run beside it on the same batches.
+rmat22-stream
+    R-MAT scale 22 (edge factor 16, a=0.57 b=0.19 c=0.19, dedup, no loops,
+    random relabel) and 64 batches, sizes log-uniform in [1,000, 1,000,000],
+    half R-MAT-sampled insertions, half uniform deletions, shuffled.  One step
+    = the whole stream from the freshly loaded graph.  `value` is the batched
+    form (one persistent launch replayed from a hipGraph); the plain host
+    loop runs beside it.
+chunglu-pool512
+    512 independent Chung-Lu graphs (n log-uniform in [1,000, 200,000], mean
+    degree uniform in [4, 32], exponent 2.3), each with one insertion batch
+    of 5% of its edges and then one deletion batch of 5%.  One step = every
+    graph's two batches.  `value` is the batched form: the graphs packed as
+    one disjoint union, every batch as a sub-batch, one hipGraph launch; the
+    plain form runs the 1024 batches one after another.
+
+Prints one JSON line (fields below).
 """
 from __future__ import annotations
 
@@ -25,52 +42,114 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-N_VERT = 1_000_000
-N_EDGE = 10_000_000
-GAMMA = 2.1
-W_MAX = 50_000.0
-BATCH = 100_000
 HBM_PEAK_GBS = 8000.0
+METRIC = "edge updates/sec (insert & delete, exact cores) batched vs plain on 1 GPU; p99 latency"
+WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(steps: int):
+def pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else 0.0
+
+
+def contract(workload, value, steps, warmup, ms_per_step, global_batch, form):
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge_updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": workload, "form": form, "global_batch": global_batch,
+                   "parallelism": "single-gpu"},
+    }
+
+
+def roofline(kernel, stats, note):
+    """Algorithmic bytes of the launches over their HIP-event time."""
+    kms = sum(x["kernel_ms"] for x in stats)
+    launches = sum(x["launches"] for x in stats)
+    abytes = sum(x["alg_bytes"] for x in stats)
+    achieved = (abytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
+    return {
+        "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "alg_bytes_per_launch": abytes / max(launches, 1),
+        "avg_launch_us": kms * 1e3 / max(launches, 1), "launches": launches, "per_launch": note,
+    }
+
+
+def to_dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def tuned_params(args, n, m, batch_sizes, sample):
+    """Launch and work-split parameters for this workload: tuned now
+    (--tune, on `sample` = a function returning the tuning sample), else the
+    stored entry for the workload's signature, else the library defaults."""
+    from paper_1612_09368_amd import autotune
+    key = autotune.signature(n, m, batch_sizes)
+    if args.tune and sample is not None:
+        t0 = time.time()
+        best, bt, trials = autotune.tune(*sample(), sweeps=2, log=log, budget_s=args.tune_budget)
+        autotune.save_tuning(key, best, bt, note=f"{len(trials)} trials on the workload's tuning sample")
+        return best, {"source": "tuned in this run", "key": key, "trials": len(trials),
+                      "tune_s": time.time() - t0, "params": best}
+    stored = autotune.load_tuning(key)
+    if stored is not None:
+        return stored, {"source": "tuning.json", "key": key, "params": stored}
+    return dict(autotune.DEFAULTS), {"source": "library defaults", "key": key,
+                                     "params": dict(autotune.DEFAULTS)}
+
+
+# ---------------------------------------------------------------------------
+# chunglu-1m
+# ---------------------------------------------------------------------------
+CL_N, CL_M, CL_GAMMA, CL_WMAX, CL_BATCH = 1_000_000, 10_000_000, 2.1, 50_000.0, 100_000
+
+
+def cl1m_workload(steps):
     import graphgen
     rng = graphgen.rng_for("bench-cl-1m")
     t = time.time()
-    s, d = graphgen.chung_lu_graph(N_VERT, N_EDGE, GAMMA, W_MAX, rng)
+    s, d = graphgen.chung_lu_graph(CL_N, CL_M, CL_GAMMA, CL_WMAX, rng)
     log(f"graph generated in {time.time() - t:.1f}s (m={s.size})")
     es = graphgen.EdgeSet(s, d)
     batches = []
-    for k in range(steps):
-        a, b = graphgen.weighted_non_edges(BATCH, es, rng)
+    for _ in range(steps):
+        a, b = graphgen.weighted_non_edges(CL_BATCH, es, rng)
         es.insert(a, b)
-        x, y = graphgen.existing_edges(BATCH, es, rng)
+        x, y = graphgen.existing_edges(CL_BATCH, es, rng)
         es.delete(x, y)
         batches.append(((a, b), (x, y)))
     log(f"{steps} batch pairs generated")
     return s, d, batches
 
 
-def run_form(cm, torch, s, d, dev_batches, mode, warmup, steps, timing):
-    dev = torch.device("cuda:0")
-    g = cm.Graph(mode=mode, timing=timing)
-    g.load(N_VERT, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev))
+def cl1m_per_batch(cm, torch, s, d, dev_batches, mode, warmup, steps, params):
+    g = cm.Graph(mode=mode, timing=True, **params)
+    g.load(CL_N, to_dev(torch, s), to_dev(torch, d))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dst = g.decompose()
     torch.cuda.synchronize()
     dec_ms = (time.perf_counter() - t0) * 1e3
-    lat = []
-    stats = []
     for k in range(warmup):
         (a, b), (x, y) = dev_batches[k]
         g.insert_edges(a, b)
         g.delete_edges(x, y)
     torch.cuda.synchronize()
+    g.phase_times(reset=True)
+    lat, stats = [], []
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         (a, b), (x, y) = dev_batches[k]
@@ -83,26 +162,376 @@ def run_form(cm, torch, s, d, dev_batches, mode, warmup, steps, timing):
         stats += [si.as_dict(), sd.as_dict()]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    phases = g.phase_times()
     cores = g.cores()
     g.close()
     return {"elapsed": elapsed, "lat": lat, "stats": stats, "dec_ms": dec_ms,
-            "dec_stats": dst.as_dict(), "cores": cores}
+            "dec_stats": dst.as_dict(), "cores": cores, "phases": phases}
 
 
-def cpu_baseline(s, d, batch):
+def cl1m_program(cm, torch, s, d, batches, warmup, steps, params):
+    """Warm-up batches one by one, then every timed batch in one launch."""
+    g = cm.Graph(mode=cm.MODE_PERSISTENT, timing=True, use_graph=True, **params)
+    g.load(CL_N, to_dev(torch, s), to_dev(torch, d))
+    g.decompose()
+    kinds, xs, ys = [], [], []
+    for k in range(warmup + steps):
+        (a, b), (x, y) = batches[k]
+        kinds += [cm.BATCH_INSERT, cm.BATCH_DELETE]
+        xs += [a, x]
+        ys += [b, y]
+    offs = np.concatenate([[0], np.cumsum([v.size for v in xs])]).astype(np.int64)
+    dx, dy = to_dev(torch, np.concatenate(xs)), to_dev(torch, np.concatenate(ys))
+    w = 2 * warmup
+    g.run_batches(kinds[:w], offs[:w + 1], dx[:offs[w]], dy[:offs[w]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = g.run_batches(kinds[w:], offs[w:] - offs[w], dx[offs[w]:], dy[offs[w]:])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cores = g.cores()
+    g.close()
+    assert all(r.status == 0 for r in res)
+    return {"elapsed": elapsed, "stats": [r.as_dict() for r in res], "cores": cores}
+
+
+def cl1m_cpu_baseline(s, d, batch):
     """The oracle as it stands: apply the batch to its host edge set and
     recompute every core number (BZ), for one insert and one delete batch."""
     import oracle
     oracle.build(force=False)
-    ref = oracle.DynamicGraph(N_VERT, s, d)
+    ref = oracle.DynamicGraph(CL_N, s, d)
     (a, b), (x, y) = batch
     t0 = time.perf_counter()
     ref.insert_edges(a, b)
     ref.cores()
     ref.delete_edges(x, y)
-    c = ref.cores()
+    ref.cores()
     el = time.perf_counter() - t0
-    return 2 * BATCH / el, el, c
+    return {"value": 2 * CL_BATCH / el, "unit": "edge_updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one insert batch + one delete batch of the workload "
+                      f"(200000 updates, {el:.1f}s): host edge-set apply + "
+                      "Batagelj-Zaversnik recompute after each batch"}
+
+
+def bench_cl1m(args, cm, torch):
+    s, d, batches = cl1m_workload(args.warmup + args.steps)
+    dev_batches = [tuple(tuple(to_dev(torch, z) for z in pair) for pair in step) for step in batches]
+    torch.cuda.synchronize()
+
+    def sample():
+        (a, b), (x, y) = batches[0]
+        xs, ys = np.concatenate([a, x]), np.concatenate([b, y])
+        return (CL_N, to_dev(torch, s), to_dev(torch, d), np.array([0, 1], np.int32),
+                np.array([0, a.size, a.size + x.size], np.int64), to_dev(torch, xs), to_dev(torch, ys))
+    params, tuning = tuned_params(args, CL_N, CL_M, [CL_BATCH], sample)
+    plain = cl1m_per_batch(cm, torch, s, d, dev_batches, cm.MODE_PLAIN, args.warmup, args.steps, params)
+    log(f"plain: {plain['elapsed']:.3f}s for {args.steps} steps")
+    updates = 2 * CL_BATCH * args.steps
+    st = plain["stats"]
+    out = contract("chung-lu n=1000000 m=10000000 gamma=2.1 wmax=50000; per step insert 100000 "
+                   "degree-weighted non-edges then delete 100000 existing edges",
+                   updates / plain["elapsed"], args.steps, args.warmup,
+                   plain["elapsed"] * 1e3 / args.steps, 2 * CL_BATCH,
+                   "plain (one cooperative launch per superior edge set)")
+    out["roofline"] = roofline("k_maintain", st, "one superior edge set (partition, apply, cascade, "
+                                                "core and SD update)")
+    out["latency_ms"] = {"p50": pct(plain["lat"], 50), "p99": pct(plain["lat"], 99),
+                         "per": "batch of 100000 edges"}
+    out["tuning"] = tuning
+    out["phase_ms"] = {k: round(v[0], 3) for k, v in plain["phases"].items()}
+    out["iterations_per_batch"] = [x["iterations"] for x in st]
+    out["rounds_per_batch"] = [x["rounds"] for x in st]
+    out["steps_per_batch"] = [x["grid_steps"] + x["local_steps"] for x in st]
+    out["decompose"] = {"ms": plain["dec_ms"], "kernel_ms": plain["dec_stats"]["kernel_ms"],
+                        "edges_per_s": CL_M / (plain["dec_ms"] * 1e-3)}
+    if not args.no_persistent:
+        pers = cl1m_per_batch(cm, torch, s, d, dev_batches, cm.MODE_PERSISTENT, args.warmup, args.steps,
+                              params)
+        log(f"persistent: {pers['elapsed']:.3f}s")
+        assert np.array_equal(plain["cores"], pers["cores"]), "plain and persistent forms disagree"
+        prog = cl1m_program(cm, torch, s, d, batches, args.warmup, args.steps, params)
+        log(f"batched: {prog['elapsed']:.3f}s")
+        assert np.array_equal(plain["cores"], prog["cores"]), "plain and batched forms disagree"
+        pst = pers["stats"]
+        out["persistent"] = {
+            "form": "persistent (one cooperative launch per batch)",
+            "value": updates / pers["elapsed"],
+            "ms_per_step": pers["elapsed"] * 1e3 / args.steps,
+            "latency_ms": {"p50": pct(pers["lat"], 50), "p99": pct(pers["lat"], 99)},
+            "roofline_achieved_gbs": roofline("k_maintain", pst, "")["achieved"],
+            "avg_launch_us": roofline("k_maintain", pst, "")["avg_launch_us"],
+        }
+        out["batched"] = {
+            "form": "batched (every timed batch in one persistent launch, hipGraph replay)",
+            "value": updates / prog["elapsed"],
+            "ms_per_step": prog["elapsed"] * 1e3 / args.steps,
+            "speedup_vs_plain": plain["elapsed"] / prog["elapsed"],
+            "roofline_achieved_gbs": roofline("k_program", prog["stats"], "")["achieved"],
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cl1m_cpu_baseline(s, d, batches[0])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# rmat22-stream
+# ---------------------------------------------------------------------------
+RM_SCALE, RM_BATCHES, RM_LO, RM_HI = 22, 64, 1000, 1_000_000
+
+
+def bench_rmat22(args, cm, torch):
+    import graphgen
+    t = time.time()
+    n, s, d, kinds, offs, xs, ys = graphgen.rmat_stream(
+        RM_SCALE, RM_BATCHES, RM_LO, RM_HI, graphgen.rng_for("bench-rmat22"), workers=WORKERS,
+        progress=lambda m: log(f"{time.time() - t:.0f}s {m}"))
+    total = int(offs[-1])
+    log(f"stream ready: {total} updates in {RM_BATCHES} batches")
+    ds, dd, dx, dy = (to_dev(torch, z) for z in (s, d, xs, ys))
+    torch.cuda.synchronize()
+    ns = 16  # tuning sample: the first 16 batches of the stream
+
+    def sample():
+        return n, ds, dd, kinds[:ns], offs[:ns + 1], dx[:offs[ns]], dy[:offs[ns]]
+    params, tuning = tuned_params(args, n, s.size, np.diff(offs), sample)
+
+    def run(mode, use_graph, reps):
+        g = cm.Graph(mode=mode, timing=True, use_graph=use_graph, **params)
+        times, allstats, cores = [], [], None
+        for rep in range(reps):
+            g.load(n, ds, dd)
+            g.decompose()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, _ = g.run_batches(kinds, offs, dx, dy)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert all(r.status == 0 for r in res), [r.status for r in res]
+            allstats.append([r.as_dict() for r in res])
+            phases = g.phase_times()
+            log(f"mode {mode}: pass {rep} {times[-1]:.3f}s")
+        cores = g.cores()
+        g.close()
+        return times, allstats, cores, phases
+
+    bt, bstats, bcores, bph = run(cm.MODE_PERSISTENT, True, args.warmup + args.steps)
+    bt, bstats = bt[args.warmup:], bstats[args.warmup:]
+    pt, pstats, pcores, pph = run(cm.MODE_PLAIN, False, 1 + (args.steps > 1))
+    assert np.array_equal(bcores, pcores), "plain and batched forms disagree"
+    pt, pstats = pt[-1:], pstats[-1:]
+    value = total * len(bt) / sum(bt)
+    plain_value = total / pt[0]
+    out = contract(f"r-mat scale 22 edge factor 16 (m={s.size}); stream of 64 batches, sizes "
+                   "log-uniform [1000, 1000000], half r-mat non-edge inserts, half uniform deletes "
+                   f"({total} updates)", value, args.steps, args.warmup, sum(bt) * 1e3 / len(bt), total,
+                   "batched (the whole stream in one persistent launch, hipGraph replay)")
+    flat = [x for run_ in bstats for x in run_]
+    out["roofline"] = roofline("k_program", flat, "the whole 64-batch stream")
+    plat = [x["ms_total"] for x in pstats[0]]
+    out["plain"] = {
+        "form": "plain (host loop, one cooperative launch per superior edge set)",
+        "value": plain_value, "ms_per_step": pt[0] * 1e3, "speedup_batched_vs_plain": value / plain_value,
+        "latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "per": "batch"},
+        "roofline": roofline("k_maintain", pstats[0], "one superior edge set"),
+    }
+    out["tuning"] = tuning
+    out["phase_ms"] = {k: round(v[0], 3) for k, v in bph.items()}
+    out["phase_count"] = {k: v[1] for k, v in bph.items()}
+    out["iterations_per_batch"] = [x["iterations"] for x in pstats[0]]
+    out["batch_sizes"] = np.diff(offs).tolist()
+    out["per_batch"] = {k: [x[k] for x in pstats[0]] for k in
+                        ("rounds", "candidates", "evicted", "changed", "scanned", "remaining_sum")}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        ref = oracle.DynamicGraph(n, s, d)
+        t0 = time.perf_counter()
+        done = 0
+        for j in range(2):
+            a, b = xs[offs[j]:offs[j + 1]], ys[offs[j]:offs[j + 1]]
+            (ref.insert_edges if kinds[j] == 0 else ref.delete_edges)(a, b)
+            ref.cores()
+            done += a.size
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / el, "unit": "edge_updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first 2 batches of the stream ({done} updates, {el:.1f}s): "
+                                         "host edge-set apply + Batagelj-Zaversnik recompute per batch"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# chunglu-pool512
+# ---------------------------------------------------------------------------
+POOL_COUNT = 512
+
+
+def bench_pool512(args, cm, torch):
+    import graphgen
+    t = time.time()
+    pool = graphgen.chung_lu_pool(POOL_COUNT, graphgen.rng_for("bench-pool512"), workers=WORKERS)
+    graphs = [(n, s, d) for n, s, d, _, _ in pool]
+    batches = []
+    for gid, (_, _, _, ins, dele) in enumerate(pool):
+        batches.append((gid, cm.BATCH_INSERT, ins[0], ins[1]))
+        batches.append((gid, cm.BATCH_DELETE, dele[0], dele[1]))
+    total = int(sum(b[2].size for b in batches))
+    log(f"{POOL_COUNT} graphs, {sum(g[1].size for g in graphs)} edges, {total} updates "
+        f"generated in {time.time() - t:.0f}s")
+
+    base, us, ud = cm.union_edges(graphs)
+    union_n = int(base[-1])
+    kinds, offs, xs, ys, sub, nsub, order = cm.pack_batches(base, batches)
+    dus, dud, dx, dy, dsub = (to_dev(torch, z) for z in (us, ud, xs, ys, sub))
+    torch.cuda.synchronize()
+    log(f"packed: union n={union_n} m={us.size}, {len(kinds)} union batches, {nsub} sub-batches")
+
+    def sample():
+        return union_n, dus, dud, kinds, offs, dx, dy, dsub, nsub
+    params, tuning = tuned_params(args, union_n, us.size, [b[2].size for b in batches], sample)
+
+    def batched(reps):
+        g = cm.Graph(mode=cm.MODE_PERSISTENT, timing=True, use_graph=True, **params)
+        times, stats = [], []
+        for rep in range(reps):
+            g.load(union_n, dus, dud)
+            g.decompose()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, sst = g.run_batches(kinds, offs, dx, dy, sub=dsub, nsub=nsub)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert all(r.status == 0 for r in res) and (sst == 0).all()
+            stats.append([r.as_dict() for r in res])
+            phases = g.phase_times()
+            log(f"batched pass {rep}: {times[-1]:.3f}s")
+        cores = g.cores()
+        g.close()
+        return times, stats, cores, phases
+
+    def plain():
+        """The same 1024 member batches one after another (graph by graph)."""
+        g = cm.Graph(mode=cm.MODE_PLAIN, timing=True, **params)
+        g.load(union_n, dus, dud)
+        g.decompose()
+        pk = np.array([b[1] for b in batches], np.int32)
+        px = np.concatenate([b[2].astype(np.int64) + base[b[0]] for b in batches]).astype(np.int32)
+        py = np.concatenate([b[3].astype(np.int64) + base[b[0]] for b in batches]).astype(np.int32)
+        po = np.concatenate([[0], np.cumsum([b[2].size for b in batches])]).astype(np.int64)
+        dpx, dpy = to_dev(torch, px), to_dev(torch, py)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _ = g.run_batches(pk, po, dpx, dpy)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert all(r.status == 0 for r in res)
+        cores = g.cores()
+        g.close()
+        return el, [r.as_dict() for r in res], cores
+
+    bt, bstats, bcores, bph = batched(args.warmup + args.steps)
+    bt, bstats = bt[args.warmup:], bstats[args.warmup:]
+    pel, pstats, pcores = plain()
+    log(f"plain: {pel:.3f}s")
+    assert np.array_equal(bcores, pcores), "plain and batched forms disagree"
+    value = total * len(bt) / sum(bt)
+    out = contract(f"{POOL_COUNT} independent chung-lu graphs (n log-uniform [1000, 200000], mean degree "
+                   f"U[4, 32], gamma 2.3; union n={union_n} m={us.size}); per graph insert 5% "
+                   f"degree-weighted non-edges then delete 5% existing edges ({total} updates)",
+                   value, args.steps, args.warmup, sum(bt) * 1e3 / len(bt), total,
+                   "batched (graphs packed as one disjoint union, one hipGraph launch)")
+    out["roofline"] = roofline("k_program", [x for r in bstats for x in r],
+                               "every graph's insertion and deletion batch")
+    out["tuning"] = tuning
+    out["phase_ms"] = {k: round(v[0], 3) for k, v in bph.items()}
+    plat = [x["ms_total"] for x in pstats]
+    out["plain"] = {"form": "plain (1024 member batches one after another, one launch per superior "
+                            "edge set)", "value": total / pel, "ms_per_step": pel * 1e3,
+                    "speedup_batched_vs_plain": value / (total / pel),
+                    "latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "per": "member batch"}}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        done, used = 0, 0
+        for gid, (n, s, d, ins, dele) in enumerate(pool):
+            ref = oracle.DynamicGraph(n, s, d)
+            ref.insert_edges(*ins)
+            ref.cores()
+            ref.delete_edges(*dele)
+            c2 = ref.cores()
+            assert np.array_equal(c2, bcores[base[gid]:base[gid + 1]]), f"graph {gid} differs"
+            done += ins[0].size + dele[0].size
+            used += 1
+            if time.perf_counter() - t0 > 20.0:
+                break
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / el, "unit": "edge_updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {used} graphs' two batches ({done} updates, {el:.1f}s): "
+                                         "host edge-set apply + Batagelj-Zaversnik recompute per batch; "
+                                         "their final cores also checked against the batched form"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# rmat-serve
+# ---------------------------------------------------------------------------
+def bench_serve(args, cm, torch):
+    import graphgen
+    from paper_1612_09368_amd import serve
+    scale, nreq = args.scale, args.requests
+    t = time.time()
+    n, s, d, reqs = graphgen.serve_stream(scale, nreq, graphgen.rng_for("bench-serve"), workers=WORKERS,
+                                          progress=lambda m: log(f"{time.time() - t:.0f}s {m}"))
+    kinds = [r[0] for r in reqs]
+    new_ids = sum(len(r[1]) - 1 for r in reqs if r[0] == "vins")
+    log(f"stream ready in {time.time() - t:.0f}s: " +
+        ", ".join(f"{k} {kinds.count(k)}" for k in ("ins", "del", "vins", "vdel")))
+    ds, dd = to_dev(torch, s), to_dev(torch, d)
+    sizes = [len(r[1]) for r in reqs]
+    params, tuning = tuned_params(args, n, s.size, sizes, None)
+    scfg = dict(ring_requests=4096, ring_items=1 << 25, max_items=1 << 23, budget_bytes=4 << 30,
+                vertex_headroom=new_ids + 1024, idle_ms=20)
+
+    def one_run(arrivals):
+        g = cm.Graph(mode=cm.MODE_PERSISTENT, **params)
+        g.load(n, ds, dd)
+        g.decompose()
+        torch.cuda.synchronize()
+        srv = serve.Server(g, **scfg)
+        res = serve.run_stream(srv, reqs, arrivals)
+        srv.stop()
+        cores = g.cores()
+        g.close()
+        st = res["stats"]
+        assert all(x.status == 0 for x in st), "a served request failed"
+        upd = sum(int(x.applied) for x in st)
+        lat = (res["t_done"] - res["t_arrival"]) * 1e3
+        return res["elapsed"], upd, lat, cores
+
+    el, upd, lat_c, cores_c = one_run(None)
+    rate = nreq / el
+    log(f"closed loop: {el:.2f}s, {upd / el / 1e6:.2f} M updates/s, {rate:.0f} requests/s")
+    lam = 0.8 * rate
+    arrivals = np.cumsum(np.random.Generator(np.random.PCG64(7)).exponential(1.0 / lam, nreq))
+    el2, upd2, lat, cores_p = one_run(arrivals)
+    log(f"poisson at {lam:.0f}/s: {el2:.2f}s, p50 {np.percentile(lat, 50):.2f} ms, "
+        f"p99 {np.percentile(lat, 99):.2f} ms")
+    assert np.array_equal(cores_c, cores_p), "served results depend on arrival timing"
+    out = contract(f"serving: r-mat scale {scale} (n={n} m={s.size}); {nreq} requests, sizes log-uniform "
+                   "[1, 100000]: 40% edge insert, 40% edge delete, 10% vertex insert (power-law degree "
+                   "1-1000), 10% vertex delete; continuous batching in one persistent launch",
+                   upd / el, 1, 0, el * 1e3, upd, "served (closed loop: every request submitted at once, "
+                                                   "admitted as the ring and memory budget allow)")
+    out["served_poisson"] = {
+        "arrival_rate_per_s": lam, "rate_rule": "0.8 x the closed-loop request rate",
+        "value": upd2 / el2, "requests_per_s": nreq / el2,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "per": "request, arrival to result"},
+    }
+    out["closed_loop"] = {"requests_per_s": rate, "latency_ms": {"p50": pct(lat_c, 50), "p99": pct(lat_c, 99)}}
+    out["tuning"] = tuning
+    out["roofline"] = None
+    return out
 
 
 def main():
@@ -110,8 +539,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chunglu-1m",
+                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve"])
+    ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
+    ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-persistent", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch parameters on the workload's sample first and store them")
+    ap.add_argument("--tune-budget", type=float, default=300.0, help="seconds for --tune")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="chunglu-1m: time the plain form only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -119,104 +556,22 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described but not built)", file=sys.stderr)
         sys.exit(2)
-    rank = int(os.environ.get("RANK", "0"))
 
     import torch
     import paper_1612_09368_amd as cm
     cm.library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-
     if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         src.fill_(1)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    s, d, batches = make_workload(args.warmup + args.steps)
-    dev_batches = [tuple(tuple(torch.from_numpy(np.ascontiguousarray(z)).to(dev) for z in pair)
-                         for pair in step) for step in batches]
-    torch.cuda.synchronize()
-
-    plain = run_form(cm, torch, s, d, dev_batches, cm.MODE_PLAIN, args.warmup, args.steps, True)
-    log(f"plain: {plain['elapsed']:.3f}s for {args.steps} steps")
-    pers = None
-    if not args.no_persistent:
-        pers = run_form(cm, torch, s, d, dev_batches, cm.MODE_PERSISTENT, args.warmup, args.steps, True)
-        log(f"persistent: {pers['elapsed']:.3f}s")
-        assert np.array_equal(plain["cores"], pers["cores"]), "plain and persistent forms disagree"
-
-    updates = 2 * BATCH * args.steps
-    value = updates / plain["elapsed"]
-    st = plain["stats"]
-    kms = sum(x["kernel_ms"] for x in st)
-    launches = sum(x["launches"] for x in st)
-    abytes = sum(x["alg_bytes"] for x in st)
-    achieved = (abytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
-    lat = np.asarray(plain["lat"])
-    out = {
-        "metric": "edge updates/sec (insert & delete, exact cores) batched vs plain on 1 GPU; p99 latency",
-        "value": value,
-        "unit": "edge_updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": plain["elapsed"] * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": "chung-lu n=1000000 m=10000000 gamma=2.1 wmax=50000; per step insert 100000 "
-                        "degree-weighted non-edges then delete 100000 existing edges",
-            "form": "plain (one cooperative launch per superior edge set)",
-            "global_batch": 2 * BATCH,
-            "parallelism": "single-gpu",
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_maintain",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "alg_bytes_per_launch": abytes / max(launches, 1),
-            "avg_launch_us": kms * 1e3 / max(launches, 1),
-            "launches": launches,
-        },
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "per": "batch of 100000 edges"},
-        "iterations_per_batch": [x["iterations"] for x in st],
-        "rounds_per_batch": [x["rounds"] for x in st],
-        "steps_per_batch": [x["grid_steps"] + x["local_steps"] for x in st],
-        "decompose": {"ms": plain["dec_ms"], "kernel_ms": plain["dec_stats"]["kernel_ms"],
-                      "edges_per_s": N_EDGE / (plain["dec_ms"] * 1e-3)},
-    }
-    if pers is not None:
-        pst = pers["stats"]
-        pk = sum(x["kernel_ms"] for x in pst)
-        pl = sum(x["launches"] for x in pst)
-        pb = sum(x["alg_bytes"] for x in pst)
-        plat = np.asarray(pers["lat"])
-        out["batched"] = {
-            "form": "persistent (one cooperative launch per batch)",
-            "value": updates / pers["elapsed"],
-            "ms_per_step": pers["elapsed"] * 1e3 / args.steps,
-            "speedup_vs_plain": plain["elapsed"] / pers["elapsed"],
-            "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99))},
-            "roofline_achieved_gbs": (pb / (pk * 1e-3)) / 1e9 if pk > 0 else 0.0,
-            "avg_launch_us": pk * 1e3 / max(pl, 1),
-        }
-    if rank == 0 and not args.no_cpu_baseline:
-        v, el, cref = cpu_baseline(s, d, batches[0])
-        out["cpu_baseline"] = {"value": v, "unit": "edge_updates/s", "cores": 1, "kind": "oracle",
-                               "sample": "one insert batch + one delete batch of the workload "
-                                         f"(200000 updates, {el:.1f}s): host edge-set apply + "
-                                         "Batagelj-Zaversnik recompute after each batch"}
+    fn = {"chunglu-1m": bench_cl1m, "rmat22-stream": bench_rmat22, "chunglu-pool512": bench_pool512,
+          "rmat-serve": bench_serve}
+    out = fn[args.workload](args, cm, torch)
     print(json.dumps(out), flush=True)
 
 

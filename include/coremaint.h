@@ -63,6 +63,7 @@ extern "C" {
 #define CM_E_STATE (-10)    /* call not valid in the handle's state (e.g. no graph loaded) */
 #define CM_E_DEVICE (-11)   /* HIP runtime error; the handle is poisoned */
 #define CM_E_INTERNAL (-12) /* internal invariant violated (queue overflow); handle poisoned */
+#define CM_E_BUSY (-13)     /* serving: the request must wait (ring, payload space or budget full) */
 
 /* Execution forms of the update path. */
 #define CM_MODE_PLAIN 0     /* host loop: one cooperative launch per superior edge set */
@@ -206,8 +207,11 @@ int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap,
  * CM_MODE_PLAIN: host loop, one cooperative launch per superior edge set.
  * CM_MODE_PERSISTENT: one cooperative launch runs every batch (validation,
  * reservation, all iterations, compaction); with use_graph it is replayed
- * from a hipGraph.  results (nb entries) may be NULL.  Returns CM_OK unless
- * the call itself failed (bad arguments, device error). */
+ * from a hipGraph.  results (nb entries) may be NULL.  Timing fields: in
+ * the plain mode every entry holds its own batch (ms_total, kernel_ms,
+ * launches); in the persistent mode results[0] holds the whole call (the one
+ * launch, its HIP-event time and the wall time) and the other entries zero.
+ * Returns CM_OK unless the call itself failed (bad arguments, device error). */
 int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t *offsets,
                    const int32_t *src, const int32_t *dst, const int32_t *sub, int32_t nsub,
                    int on_device, cm_batch_stats *results, int32_t *sub_status);
@@ -215,6 +219,88 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
 /* Copy the maintained superior degree SD(v) (Section IV-B definition) of
  * ids [0, n) to out; dead ids report 0. */
 int cm_get_superior_degrees(cm_graph *g, int32_t *out, int32_t n, int on_device);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of update requests on one resident graph.
+ *
+ * Requests (edge insertions or deletions, vertex insertions or deletions,
+ * in the Introduction's reduction to edge updates) are copied into a ring of
+ * pinned host memory and published; one persistent cooperative launch reads
+ * each request from the ring as soon as it is published, applies it exactly
+ * as the one-call API would (validation through compaction; in strict mode
+ * an invalid request changes nothing), records its outcome and moves on,
+ * so requests that arrive while others run join the running launch without
+ * a host round trip.  Requests apply in ticket order.  The launch leaves
+ * after idle_ms without work, when stopped, or when the adjacency pool must
+ * be repacked or vertex capacity grown; the next submit or poll launches it
+ * again.  Admission is by memory: a request waits (CM_E_BUSY) while the
+ * ring has no free slot, the payload ring no room, or the device bytes that
+ * unfinished requests may claim (payload plus an estimate of adjacency
+ * growth for insertions) would exceed budget_bytes.  While serving, the
+ * other calls on the handle return CM_E_STATE (cm_num_* excepted); call
+ * cm_serve_stop first.
+ * ------------------------------------------------------------------------- */
+typedef struct cm_serve_config {
+    int32_t ring_requests;    /* request slots (default 4096) */
+    int32_t idle_ms;          /* launch leaves after this long without work (default 20) */
+    int64_t ring_items;       /* payload slots of the pinned ring, int32 pairs (default 2^24) */
+    int64_t max_items;        /* largest request, in items (edges; ids for a vertex deletion); also
+                                 the most incident edges one vertex deletion may gather (default 2^22) */
+    int64_t budget_bytes;     /* device bytes unfinished requests may claim (default 2^30) */
+    int32_t vertex_headroom;  /* vertex capacity kept beyond the ids in use (default 2^20) */
+    int32_t reserved;
+} cm_serve_config;
+
+#define CM_REQ_INSERT_EDGES 0
+#define CM_REQ_DELETE_EDGES 1
+#define CM_REQ_INSERT_VERTICES 2
+#define CM_REQ_DELETE_VERTICES 3
+
+void cm_serve_config_default(cm_serve_config *cfg);
+
+/* Enter serving on a decomposed graph (cfg may be NULL for the defaults). */
+int cm_serve_start(cm_graph *g, const cm_serve_config *cfg);
+
+/* Submit an edge request (kind CM_REQ_INSERT_EDGES / CM_REQ_DELETE_EDGES; s
+ * pairs in host arrays, copied before return).  *ticket receives its
+ * position in the request order.  CM_E_BUSY: not admitted now, submit it
+ * again later; CM_E_CAPACITY: larger than max_items. */
+int cm_serve_submit_edges(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
+                          int64_t *ticket);
+
+/* Submit a vertex insertion: c new vertices with neighbour lists in CSR
+ * form (off int64[c+1] with off[0] = 0, nbrs int32[off[c]], host memory).
+ * Ids are assigned at submission (*first_new_id); if the request is
+ * rejected when it runs, its ids stay allocated as dead ids. */
+int cm_serve_submit_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs,
+                                    int32_t *first_new_id, int64_t *ticket);
+
+/* Submit a vertex deletion of c ids (host memory).  A request whose ids
+ * have more than max_items incident edges fails with CM_E_CAPACITY. */
+int cm_serve_submit_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int64_t *ticket);
+
+/* Progress: collect finished requests, relaunch if work is pending; never
+ * blocks.  *finished (may be NULL) = number of requests finished (every
+ * ticket below it). */
+int cm_serve_poll(cm_graph *g, int64_t *finished);
+
+/* Outcome of a finished request (CM_E_BUSY while it is unfinished).
+ * status is the request's own status; applied counts its edges. */
+int cm_serve_result(cm_graph *g, int64_t ticket, cm_batch_stats *out);
+
+/* Finish every admitted request, end the launch and leave serving. */
+int cm_serve_stop(cm_graph *g);
+
+/* Phase clock of the maintenance kernels, for profiling one persistent
+ * launch from the inside: ms[i] (host, n <= 16 entries) receives the device
+ * wall-clock time summed over every phase i since the graph was loaded or
+ * the clock was last reset, counts[i] (may be NULL) how often it ran.
+ * Slots 0..7 are grid-wide steps of an iteration (claim, select, apply,
+ * expansion round, eviction round, peel round, core update, SD update),
+ * 8 chains of steps run inside one workgroup, 9..11 validation, capacity
+ * reservation and compaction inside cm_run_batches' persistent launch.
+ * reset != 0 clears the clock afterwards.  No device work is started. */
+int cm_phase_times(cm_graph *g, double *ms, int64_t *counts, int32_t n, int reset);
 
 #ifdef __cplusplus
 }

@@ -263,9 +263,13 @@ class DynamicGraph:
                                  assume_unique=True)
         return OK, fb, int(ok.sum())
 
-    def insert_vertices(self, off, nbrs, strict=True):
+    def insert_vertices(self, off, nbrs, strict=True, keep_failed_ids=False):
         """New ids n..n+c-1 (core 0), then the edges (new id, nbr) of each
-        neighbour list.  Returns (status, first_bad, first_new_id)."""
+        neighbour list.  Returns (status, first_bad, first_new_id).
+
+        A rejected request frees its ids again, except with keep_failed_ids
+        (the serving convention: ids are handed out at submission, so a
+        rejected request's ids stay allocated as dead ids)."""
         off = np.asarray(off, dtype=np.int64)
         nbrs = np.asarray(nbrs, dtype=np.int64)
         c = off.size - 1
@@ -276,6 +280,9 @@ class DynamicGraph:
         self.alive = np.concatenate([self.alive, np.ones(c, dtype=np.uint8)])
         st, fb, _ = self.insert_edges(own, nbrs, strict)
         if st != OK:
+            if keep_failed_ids:
+                self.alive[first:first + c] = 0
+                return st, fb, first
             self.n, self.alive = saved
             return st, fb, -1
         return OK, fb, first

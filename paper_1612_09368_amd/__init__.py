@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcoremaint.so")
 
 OK = 0
 E_ARG, E_RANGE, E_SELF_LOOP, E_DUP, E_EXISTS, E_MISSING, E_DEAD = -1, -2, -3, -4, -5, -6, -7
-E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL = -8, -9, -10, -11, -12
+E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL, E_BUSY = -8, -9, -10, -11, -12, -13
 MODE_PLAIN, MODE_PERSISTENT = 0, 1
 BATCH_INSERT, BATCH_DELETE = 0, 1
 
@@ -29,8 +29,11 @@ EXPORTED = [
     "cm_config_default", "cm_create", "cm_destroy", "cm_strerror", "cm_last_error",
     "cm_load_graph", "cm_core_decompose", "cm_insert_edges", "cm_delete_edges",
     "cm_insert_vertices", "cm_delete_vertices", "cm_get_cores", "cm_num_vertices",
-    "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees", "cm_run_batches",
+    "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees", "cm_run_batches", "cm_phase_times",
+    "cm_serve_config_default", "cm_serve_start", "cm_serve_submit_edges", "cm_serve_submit_insert_vertices",
+    "cm_serve_submit_delete_vertices", "cm_serve_poll", "cm_serve_result", "cm_serve_stop",
 ]
+REQ_INSERT_EDGES, REQ_DELETE_EDGES, REQ_INSERT_VERTICES, REQ_DELETE_VERTICES = 0, 1, 2, 3
 
 
 class Config(ctypes.Structure):
@@ -50,6 +53,18 @@ class Config(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [
+        ("ring_requests", ctypes.c_int32),
+        ("idle_ms", ctypes.c_int32),
+        ("ring_items", ctypes.c_int64),
+        ("max_items", ctypes.c_int64),
+        ("budget_bytes", ctypes.c_int64),
+        ("vertex_headroom", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -115,6 +130,15 @@ def library():
         "cm_export_edges": (ctypes.c_int, [P, P, P, I64, P, ctypes.c_int]),
         "cm_get_superior_degrees": (ctypes.c_int, [P, P, I32, ctypes.c_int]),
         "cm_run_batches": (ctypes.c_int, [P, I32, P, P, P, P, P, I32, ctypes.c_int, P, P]),
+        "cm_phase_times": (ctypes.c_int, [P, P, P, I32, ctypes.c_int]),
+        "cm_serve_config_default": (None, [P]),
+        "cm_serve_start": (ctypes.c_int, [P, P]),
+        "cm_serve_submit_edges": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "cm_serve_submit_insert_vertices": (ctypes.c_int, [P, I32, P, P, P, P]),
+        "cm_serve_submit_delete_vertices": (ctypes.c_int, [P, I32, P, P]),
+        "cm_serve_poll": (ctypes.c_int, [P, P]),
+        "cm_serve_result": (ctypes.c_int, [P, I64, P]),
+        "cm_serve_stop": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -307,6 +331,19 @@ class Graph:
         self._check(self._lib.cm_get_cores(self._h, p, min(n, cnt), dev), "cm_get_cores")
         return out
 
+    PHASES = ("claim", "select", "apply", "expand", "evict", "peel", "core", "sd",
+              "local", "validate", "reserve", "compact")
+
+    def phase_times(self, reset=False):
+        """{phase: (ms, count)} of the device phase clock (see cm_phase_times)."""
+        k = len(self.PHASES)
+        ms = np.zeros(k, dtype=np.float64)
+        cnt = np.zeros(k, dtype=np.int64)
+        self._check(self._lib.cm_phase_times(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                             ctypes.c_void_p(cnt.ctypes.data), k, 1 if reset else 0),
+                    "cm_phase_times")
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(self.PHASES)}
+
     def superior_degrees(self):
         n, _ = self.num_vertices()
         arr = np.empty(n, dtype=np.int32)
@@ -325,65 +362,79 @@ class Graph:
         return s[:got.value], d[:got.value]
 
 
+def union_edges(graphs):
+    """Disjoint union of [(n, src, dst), ...]: (base int64[len+1], src, dst)
+    with graph i's ids offset by base[i]."""
+    base = np.concatenate([[0], np.cumsum([int(n) for n, _, _ in graphs])]).astype(np.int64)
+    if not graphs:
+        return base, np.empty(0, np.int32), np.empty(0, np.int32)
+    src = np.concatenate([np.asarray(s, np.int64) + b for (_, s, _), b in zip(graphs, base)])
+    dst = np.concatenate([np.asarray(d, np.int64) + b for (_, _, d), b in zip(graphs, base)])
+    return base, src.astype(np.int32), dst.astype(np.int32)
+
+
+def pack_batches(base, batches):
+    """Group per-graph batches into union batches with sub-batch ids.
+
+    batches: list of (graph_id, kind, src, dst) in submission order (ids
+    local to the graph).  The t-th batch of every graph forms stage t; each
+    stage becomes one insertion batch and one deletion batch of the union
+    (in that order; a graph's own order is kept because its t-th batch is
+    in stage t).  Returns (kinds, offsets, src, dst, sub, nsub, order), where
+    order[k] is the sub-batch id of submission k."""
+    per_graph = {}
+    stage_of = []
+    for gid, kind, s, d in batches:
+        t = per_graph.get(gid, 0)
+        per_graph[gid] = t + 1
+        stage_of.append(t)
+    nstages = max(stage_of) + 1 if batches else 0
+    kinds, offs, srcs, dsts, subs = [], [0], [], [], []
+    order = np.full(len(batches), -1, dtype=np.int64)
+    nsub = 0
+    for t in range(nstages):
+        for kind in (BATCH_INSERT, BATCH_DELETE):
+            members = [k for k in range(len(batches)) if stage_of[k] == t and batches[k][1] == kind]
+            if not members:
+                continue
+            for k in members:
+                gid, _, s, d = batches[k]
+                b = base[gid]
+                srcs.append(np.asarray(s, np.int64) + b)
+                dsts.append(np.asarray(d, np.int64) + b)
+                subs.append(np.full(len(s), nsub, np.int32))
+                order[k] = nsub
+                nsub += 1
+            kinds.append(kind)
+            offs.append(offs[-1] + sum(len(batches[k][2]) for k in members))
+    cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.empty(0, dt))
+    return (np.asarray(kinds, np.int32), np.asarray(offs, np.int64), cat(srcs, np.int32),
+            cat(dsts, np.int32), cat(subs, np.int32), nsub, order)
+
+
 class GraphPool:
     """Many independent graphs updated together.
 
     The graphs are packed as one disjoint union (graph i's ids are offset by
     the sizes of the graphs before it); a disjoint union has no edge between
     two members, so its core numbers are exactly the members' core numbers.
-    Per-graph batches are grouped into stages (the t-th batch of every graph)
-    and each stage becomes one insertion and one deletion batch of the union,
-    packed with a sub-batch id per member batch, so that one
+    Per-graph batches are grouped into stages (see pack_batches) so that one
     ``cm_run_batches`` call (one persistent launch, optionally a hipGraph
     replay) updates every graph; an invalid member batch is dropped alone.
     """
 
     def __init__(self, graphs, **cfg):
-        self.sizes = [int(n) for n, _, _ in graphs]
-        self.base = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
-        src = np.concatenate([np.asarray(s, np.int64) + b for (_, s, _), b in zip(graphs, self.base)]) \
-            if graphs else np.empty(0, np.int64)
-        dst = np.concatenate([np.asarray(d, np.int64) + b for (_, _, d), b in zip(graphs, self.base)]) \
-            if graphs else np.empty(0, np.int64)
+        self.base, src, dst = union_edges(graphs)
+        self.sizes = np.diff(self.base).tolist()
         self.graph = Graph(**cfg)
-        self.graph.load(int(self.base[-1]), src.astype(np.int32), dst.astype(np.int32))
+        self.graph.load(int(self.base[-1]), src, dst)
         self.graph.decompose()
 
     def pack(self, batches):
-        """batches: list of (graph_id, kind, src, dst) in submission order.
-        Returns (kinds, offsets, src, dst, sub, nsub, order) where order[k] is
-        the sub-batch id of submission k."""
-        per_graph = {}
-        stage_of = []
-        for k, (gid, kind, s, d) in enumerate(batches):
-            t = per_graph.get(gid, 0)
-            per_graph[gid] = t + 1
-            stage_of.append(t)
-        nstages = max(stage_of) + 1 if batches else 0
-        kinds, offs, srcs, dsts, subs = [], [0], [], [], []
-        order = np.full(len(batches), -1, dtype=np.int64)
-        nsub = 0
-        for t in range(nstages):
-            for kind in (BATCH_INSERT, BATCH_DELETE):
-                members = [k for k in range(len(batches)) if stage_of[k] == t and batches[k][1] == kind]
-                if not members:
-                    continue
-                for k in members:
-                    gid, _, s, d = batches[k]
-                    b = self.base[gid]
-                    srcs.append(np.asarray(s, np.int64) + b)
-                    dsts.append(np.asarray(d, np.int64) + b)
-                    subs.append(np.full(len(s), nsub, np.int32))
-                    order[k] = nsub
-                    nsub += 1
-                kinds.append(kind)
-                offs.append(offs[-1] + sum(len(batches[k][2]) for k in members))
-        cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.empty(0, dt))
-        return (np.asarray(kinds, np.int32), np.asarray(offs, np.int64), cat(srcs, np.int32),
-                cat(dsts, np.int32), cat(subs, np.int32), nsub, order)
+        return pack_batches(self.base, batches)
 
     def run(self, batches, device=None):
-        """Apply the per-graph batches; returns one status per submission."""
+        """Apply the per-graph batches; returns (one status per submission, stats)."""
         kinds, offs, s, d, sub, nsub, order = self.pack(batches)
         if device is not None:
             torch = _torch()

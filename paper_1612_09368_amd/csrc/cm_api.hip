@@ -1,6 +1,7 @@
 // C ABI of libcoremaint: host orchestration of the device graph store, the
 // initial decomposition and the batched maintenance drivers.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <initializer_list>
 #include <climits>
@@ -65,6 +66,27 @@ struct cm_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<char> graph_key;
+    // serving (cm_serve_*): pinned request ring read by a persistent launch
+    bool serving = false;
+    bool serve_live = false;        // a serving launch is in flight
+    cm_serve_config scfg{};
+    int coop_serve = 0;
+    ServeHdr *shdr = nullptr;       // pinned
+    ProgBatch *sring = nullptr;     // pinned [ring_requests]
+    ProgOut *sout = nullptr;        // pinned [ring_requests]
+    int32_t *ssrc = nullptr, *sdst = nullptr;  // pinned payload [ring_items]
+    int64_t s_next = 0;             // tickets issued (= batches published)
+    int64_t s_done = 0;             // batches finished (host view)
+    int64_t s_first = 0;            // first batch of the live launch
+    int64_t s_pay_tail = 0;         // payload slots handed out (monotonic)
+    std::vector<int64_t> s_pstart;  // per ring slot: monotonic payload start
+    std::vector<int64_t> s_bytes;   // per ring slot: bytes charged to the budget
+    std::vector<int32_t> s_nids;    // per ring slot: ids in use after the batch
+    int64_t s_inflight = 0;         // bytes charged by unfinished requests
+    int32_t s_n_ids = 0;            // ids handed out (host view, pending insertions included)
+    bool s_grow = false;            // vertex capacity must grow at the next stop
+    int64_t s_pending_ins = 0;      // items of unfinished insertions (repack sizing)
+    std::vector<cm_batch_stats> s_results;
 
     bool loaded = false;
     bool decomposed = false;
@@ -84,6 +106,8 @@ namespace {
 struct Fail {
     int code;
 };
+
+void serve_free(cm_graph *g);
 
 #define HIPCHK(expr)                                                                   \
     do {                                                                               \
@@ -608,6 +632,10 @@ void require_ready(cm_graph *g, bool need_cores) {
     if (g->poisoned) {
         throw Fail{CM_E_DEVICE};
     }
+    if (g->serving) {
+        g->err = "the graph is being served (call cm_serve_stop first)";
+        throw Fail{CM_E_STATE};
+    }
     if (!g->loaded || (need_cores && !g->decomposed)) {
         g->err = need_cores ? "no decomposed graph (call cm_load_graph and cm_core_decompose)"
                             : "no graph loaded";
@@ -662,6 +690,7 @@ void cm_config_default(cm_config *cfg) {
 const char *cm_strerror(int status) {
     switch (status) {
     case CM_OK: return "ok";
+    case CM_E_BUSY: return "request must wait (serving ring, payload space or budget full)";
     case CM_E_ARG: return "invalid argument";
     case CM_E_RANGE: return "vertex id out of range";
     case CM_E_SELF_LOOP: return "self-loop";
@@ -703,10 +732,10 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         }
         g->tune.small_deg = g->cfg.small_degree > 0 ? g->cfg.small_degree : 4;
         g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 256;
-        g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 128;
+        g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 256;
         g->tune.rounds = g->cfg.partition_rounds > 0 ? std::min(g->cfg.partition_rounds, 8) : 2;
         g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 8192;
-        g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 2048;
+        g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 128;
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
@@ -744,7 +773,9 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
 
 void cm_destroy(cm_graph *g) {
     if (!g) return;
+    if (g->serving && g->shdr) __atomic_store_n(&g->shdr->stop, 1, __ATOMIC_RELEASE);
     (void)hipStreamSynchronize(g->stream);
+    serve_free(g);
     release_all(g);
     dev_free(g->i64_scratch);
     dev_free(g->u64_scratch);
@@ -763,6 +794,7 @@ int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const i
                   int on_device) {
     if (!g || n < 0 || m < 0 || (m > 0 && (!src || !dst))) return CM_E_ARG;
     if (g->poisoned) return CM_E_DEVICE;
+    if (g->serving) return CM_E_STATE;
     hipStream_t st = g->stream;
     try {
         release_all(g);
@@ -1128,6 +1160,449 @@ int cm_get_superior_degrees(cm_graph *g, int32_t *out, int32_t n, int on_device)
     return CM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Serving: continuous batching through a pinned request ring
+// ---------------------------------------------------------------------------
+void cm_serve_config_default(cm_serve_config *c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->ring_requests = 4096;
+    c->idle_ms = 20;
+    c->ring_items = (int64_t)1 << 24;
+    c->max_items = (int64_t)1 << 22;
+    c->budget_bytes = (int64_t)1 << 30;
+    c->vertex_headroom = 1 << 20;
+}
+
+}  // extern "C"
+
+namespace {
+
+void serve_free(cm_graph *g) {
+    if (g->shdr) (void)hipHostFree(g->shdr);
+    if (g->sring) (void)hipHostFree(g->sring);
+    if (g->sout) (void)hipHostFree(g->sout);
+    if (g->ssrc) (void)hipHostFree(g->ssrc);
+    if (g->sdst) (void)hipHostFree(g->sdst);
+    g->shdr = nullptr;
+    g->sring = nullptr;
+    g->sout = nullptr;
+    g->ssrc = g->sdst = nullptr;
+}
+
+template <class T>
+T *host_dev_ptr(cm_graph *g, T *p) {
+    void *d = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&d, p, 0));
+    return (T *)d;
+}
+
+// Copy the finished batches' outcomes out of the ring and settle accounts.
+void serve_collect(cm_graph *g) {
+    const long long head = __atomic_load_n(&g->shdr->head, __ATOMIC_ACQUIRE);
+    const int32_t R = g->scfg.ring_requests;
+    for (long long t = g->s_done; t < head; ++t) {
+        const int32_t slot = (int32_t)(t % R);
+        const ProgOut &o = g->sout[slot];
+        const ProgBatch &b = g->sring[slot];
+        cm_batch_stats &r = g->s_results[t];
+        std::memset(&r, 0, sizeof(r));
+        r.status = o.status;
+        r.iterations = o.iterations;
+        r.first_bad = o.first_bad;
+        r.applied = o.valid;
+        r.remaining_sum = (int64_t)o.remaining;
+        r.candidates = (int64_t)o.candidates;
+        r.evicted = (int64_t)o.evicted;
+        r.changed = (int64_t)o.changed;
+        r.scanned = (int64_t)o.scanned;
+        r.rounds = (int64_t)o.rounds;
+        r.local_steps = (int64_t)o.steps;
+        Ctl tmp{};
+        tmp.st_remaining = o.remaining;
+        tmp.st_selected = o.selected;
+        tmp.st_scanned = o.scanned;
+        tmp.st_candidates = o.candidates;
+        tmp.st_changed = o.changed;
+        r.alg_bytes = alg_bytes(tmp, g->tune.rounds);
+        if (o.status == 0) {
+            const bool ins = b.kind == 0 || b.kind == 2;
+            g->m += ins ? o.valid : -(int64_t)o.valid;
+            if (b.kind == 2) g->n_alive += o.vdone;
+            if (b.kind == 3) g->n_alive -= o.vdone;
+        }
+        if (b.kind == 0 || b.kind == 2) g->s_pending_ins -= b.s;
+        g->s_inflight -= g->s_bytes[slot];
+        g->g.n_ids = std::max(g->g.n_ids, g->s_nids[slot]);
+    }
+    g->s_done = std::max<int64_t>(g->s_done, head);
+}
+
+void serve_launch(cm_graph *g) {
+    hipStream_t st = g->stream;
+    ProgDesc *hd = g->h_prog;
+    std::memset(hd, 0, sizeof(ProgDesc));
+    hd->batches = host_dev_ptr(g, g->sring);
+    hd->out = host_dev_ptr(g, g->sout);
+    hd->src = host_dev_ptr(g, g->ssrc);
+    hd->dst = host_dev_ptr(g, g->sdst);
+    hd->gsrc = g->src_buf;
+    hd->gdst = g->dst_buf;
+    hd->gcap = g->batch_cap;
+    hd->firstidx = g->firstidx;
+    hd->hdr = host_dev_ptr(g, g->shdr);
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+    hd->idle_ticks = (unsigned long long)std::max(1, g->scfg.idle_ms) * (unsigned long long)std::max(khz, 1);
+    hd->ring = g->scfg.ring_requests;
+    hd->sfirst = g->s_done;
+    hd->strict = g->cfg.strict ? 1 : 0;
+    hd->bstamp0 = g->bstamp + 2;
+    g->shdr->exit_at = g->s_done;
+    __atomic_store_n(&g->shdr->exit_reason, 0, __ATOMIC_RELEASE);
+    g->s_first = g->s_done;
+    HIPCHK(hipMemcpyAsync(g->d_prog, hd, sizeof(ProgDesc), hipMemcpyHostToDevice, st));
+    KArgs a = make_args(g);
+    a.prog = g->d_prog;
+    HIPCHK(serve_coop(a, g->coop_serve, st));
+    g->serve_live = true;
+}
+
+// After the serving launch has left: settle, then handle why it left.
+void serve_after_exit(cm_graph *g) {
+    HIPCHK(hipStreamSynchronize(g->stream));
+    g->serve_live = false;
+    serve_collect(g);
+    sync_ctl(g);
+    check_abort(g);
+    check_overflow(g);
+    g->epoch = g->hctl->epoch;
+    const long long at = g->shdr->exit_at;
+    g->bstamp += 2 * (int32_t)(at - g->s_first) + 2;
+    const int32_t reason = __atomic_load_n(&g->shdr->exit_reason, __ATOMIC_ACQUIRE);
+    if (reason == SV_POOL) {
+        repack(g, 4 * std::max<int64_t>(g->s_pending_ins, 0) + g->g.pool_size / 2);
+    } else if (reason == SV_TOOBIG || reason == SV_ABORT) {
+        g->poisoned = true;
+        g->err = reason == SV_TOOBIG ? "internal: served batch larger than the staged capacity"
+                                     : "internal: serving launch aborted";
+        throw Fail{CM_E_INTERNAL};
+    }
+    __atomic_store_n(&g->shdr->stop, 0, __ATOMIC_RELEASE);
+    if (g->s_grow) {
+        // ids of unfinished insertions are kept too (their slots are re-initialised on activation)
+        int32_t keep = g->g.n_ids;
+        g->g.n_ids = g->s_n_ids;
+        ensure_vertex_capacity(g, (int64_t)g->s_n_ids + std::max(g->scfg.vertex_headroom, 1024));
+        g->g.n_ids = keep;
+        g->s_grow = false;
+    }
+}
+
+// Poll the live launch; relaunch when work is pending and none is live.
+void serve_pump(cm_graph *g) {
+    serve_collect(g);
+    if (g->serve_live && __atomic_load_n(&g->shdr->exit_reason, __ATOMIC_ACQUIRE) != 0) serve_after_exit(g);
+    if (!g->serve_live && g->s_done < g->s_next) serve_launch(g);
+}
+
+void serve_require(cm_graph *g) {
+    if (g->poisoned) throw Fail{CM_E_DEVICE};
+    if (!g->serving) {
+        g->err = "not serving (call cm_serve_start)";
+        throw Fail{CM_E_STATE};
+    }
+}
+
+// Reserve a ring slot and `items` payload slots; false when the request must
+// wait (ring, payload or budget full).  On success returns the payload
+// position.
+bool serve_admit(cm_graph *g, int64_t items, int64_t bytes, int64_t *pos_out) {
+    const int32_t R = g->scfg.ring_requests;
+    const int64_t P = g->scfg.ring_items;
+    if (g->s_next - g->s_done >= R) return false;
+    if (g->s_next > g->s_done && g->s_inflight + bytes > g->scfg.budget_bytes) return false;
+    // payload: contiguous [pos, pos + items) on the ring, wrapping to 0 if needed
+    int64_t start = g->s_pay_tail;
+    int64_t pos = start % P;
+    if (pos + items > P) start += P - pos;
+    const int64_t oldest = g->s_next > g->s_done ? g->s_pstart[g->s_done % R] : g->s_pay_tail;
+    if (start + items - oldest > P) return false;
+    *pos_out = start;
+    return true;
+}
+
+void serve_publish(cm_graph *g, const ProgBatch &b, int64_t start, int64_t bytes, int32_t nids_after,
+                   int64_t *ticket) {
+    const int32_t R = g->scfg.ring_requests;
+    const int64_t t = g->s_next;
+    const int32_t slot = (int32_t)(t % R);
+    g->sring[slot] = b;
+    g->s_pstart[slot] = start;
+    g->s_bytes[slot] = bytes;
+    g->s_nids[slot] = nids_after;
+    g->s_pay_tail = start + std::max<int64_t>(b.s, 0);
+    g->s_inflight += bytes;
+    if (b.kind == 0 || b.kind == 2) g->s_pending_ins += b.s;
+    if ((int64_t)g->s_results.size() <= t) g->s_results.resize((size_t)std::max<int64_t>(t + 1, 2 * (int64_t)g->s_results.size()));
+    std::atomic_thread_fence(std::memory_order_release);
+    __atomic_store_n(&g->shdr->tail, (long long)(t + 1), __ATOMIC_RELEASE);
+    g->s_next = t + 1;
+    if (ticket) *ticket = t;
+}
+
+// Device bytes a request may claim while unfinished: its payload plus, for
+// insertions, room for both list entries of every edge and a relocated list.
+int64_t serve_bytes(int32_t kind, int64_t items) {
+    return 8 * items + ((kind == 0 || kind == 2) ? 32 * items : 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
+    if (!g) return CM_E_ARG;
+    try {
+        require_ready(g, true);
+        cm_serve_config c;
+        if (cfg) c = *cfg;
+        else cm_serve_config_default(&c);
+        if (c.ring_requests < 1 || c.ring_items < 1 || c.max_items < 1 || c.max_items > c.ring_items ||
+            c.max_items > INT_MAX / 4 || c.idle_ms < 1 || c.budget_bytes < 1 || c.vertex_headroom < 0) {
+            g->err = "bad serving configuration";
+            throw Fail{CM_E_ARG};
+        }
+        g->scfg = c;
+        ensure_batch(g, c.max_items);
+        ensure_vertex_capacity(g, (int64_t)g->g.n_ids + c.vertex_headroom);
+        HIPCHK(hipStreamSynchronize(g->stream));
+        int bpc = 0;
+        HIPCHK(coop_occupancy(3, &bpc));
+        int want = g->cfg.blocks_per_cu > 0 ? g->cfg.blocks_per_cu : 1;
+        g->coop_serve = g->num_cu * std::max(1, std::min(want, bpc));
+        serve_free(g);
+        HIPCHK(hipHostMalloc((void **)&g->shdr, sizeof(ServeHdr), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g->sring, sizeof(ProgBatch) * (size_t)c.ring_requests, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g->sout, sizeof(ProgOut) * (size_t)c.ring_requests, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g->ssrc, sizeof(int32_t) * (size_t)c.ring_items, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g->sdst, sizeof(int32_t) * (size_t)c.ring_items, hipHostMallocDefault));
+        std::memset(g->shdr, 0, sizeof(ServeHdr));
+        std::memset(g->sring, 0, sizeof(ProgBatch) * (size_t)c.ring_requests);
+        std::memset(g->sout, 0, sizeof(ProgOut) * (size_t)c.ring_requests);
+        g->s_pstart.assign((size_t)c.ring_requests, 0);
+        g->s_bytes.assign((size_t)c.ring_requests, 0);
+        g->s_nids.assign((size_t)c.ring_requests, 0);
+        g->s_results.clear();
+        g->s_results.resize(1024);
+        g->s_next = g->s_done = g->s_first = g->s_pay_tail = 0;
+        g->s_inflight = 0;
+        g->s_pending_ins = 0;
+        g->s_n_ids = g->g.n_ids;
+        g->s_grow = false;
+        g->serve_live = false;
+        g->serving = true;
+    } catch (const Fail &f) {
+        serve_free(g);
+        return f.code;
+    }
+    g->err.clear();
+    return CM_OK;
+}
+
+int cm_serve_submit_edges(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
+                          int64_t *ticket) {
+    if (!g || (kind != CM_REQ_INSERT_EDGES && kind != CM_REQ_DELETE_EDGES) || s < 0 ||
+        (s > 0 && (!src || !dst)))
+        return CM_E_ARG;
+    try {
+        serve_require(g);
+        if (s > g->scfg.max_items) { g->err = "request larger than max_items"; return CM_E_CAPACITY; }
+        const int64_t bytes = serve_bytes(kind, s);
+        int64_t start = 0;
+        if (!serve_admit(g, s, bytes, &start)) {
+            serve_pump(g);
+            if (!serve_admit(g, s, bytes, &start)) return CM_E_BUSY;
+        }
+        const int64_t pos = start % g->scfg.ring_items;
+        if (s > 0) {
+            std::memcpy(g->ssrc + pos, src, sizeof(int32_t) * (size_t)s);
+            std::memcpy(g->sdst + pos, dst, sizeof(int32_t) * (size_t)s);
+        }
+        ProgBatch b{};
+        b.off = pos;
+        b.s = (int32_t)s;
+        b.kind = kind;
+        b.n_ids = g->s_n_ids;
+        serve_publish(g, b, start, bytes, g->s_n_ids, ticket);
+        serve_pump(g);
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_serve_submit_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs,
+                                    int32_t *first_new_id, int64_t *ticket) {
+    if (!g || c < 0 || (c > 0 && !off)) return CM_E_ARG;
+    try {
+        serve_require(g);
+        if (c > 0 && off[0] != 0) { g->err = "off[0] must be 0"; return CM_E_ARG; }
+        for (int32_t i = 0; i < c; ++i)
+            if (off[i + 1] < off[i]) { g->err = "offsets must be non-decreasing"; return CM_E_ARG; }
+        const int64_t total = c > 0 ? off[c] : 0;
+        if (total > 0 && !nbrs) return CM_E_ARG;
+        if (total > g->scfg.max_items) { g->err = "request larger than max_items"; return CM_E_CAPACITY; }
+        if ((int64_t)g->s_n_ids + c > INT_MAX - 1) { g->err = "vertex ids exceed int32"; return CM_E_CAPACITY; }
+        if ((int64_t)g->s_n_ids + c > g->g.n_cap) {
+            // the ids must exist before the request is admitted
+            if (g->serve_live) {
+                g->s_grow = true;
+                __atomic_store_n(&g->shdr->stop, 1, __ATOMIC_RELEASE);
+                serve_pump(g);
+                if (g->serve_live) return CM_E_BUSY;
+            }
+            int32_t keep = g->g.n_ids;
+            g->g.n_ids = g->s_n_ids;
+            ensure_vertex_capacity(g, (int64_t)g->s_n_ids + c + g->scfg.vertex_headroom);
+            g->g.n_ids = keep;
+            g->s_grow = false;
+        }
+        const int64_t bytes = serve_bytes(CM_REQ_INSERT_VERTICES, total);
+        int64_t start = 0;
+        if (!serve_admit(g, total, bytes, &start)) {
+            serve_pump(g);
+            if (!serve_admit(g, total, bytes, &start)) return CM_E_BUSY;
+        }
+        const int64_t pos = start % g->scfg.ring_items;
+        const int32_t v0 = g->s_n_ids;
+        for (int32_t i = 0; i < c; ++i)
+            for (int64_t j = off[i]; j < off[i + 1]; ++j) {
+                g->ssrc[pos + j] = v0 + i;
+                g->sdst[pos + j] = nbrs[j];
+            }
+        ProgBatch b{};
+        b.off = pos;
+        b.s = (int32_t)total;
+        b.kind = CM_REQ_INSERT_VERTICES;
+        b.v0 = v0;
+        b.nv = c;
+        b.n_ids = v0 + c;
+        g->s_n_ids = v0 + c;
+        if (first_new_id) *first_new_id = v0;
+        serve_publish(g, b, start, bytes, v0 + c, ticket);
+        serve_pump(g);
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_serve_submit_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int64_t *ticket) {
+    if (!g || c < 0 || (c > 0 && !ids)) return CM_E_ARG;
+    try {
+        serve_require(g);
+        if (c > g->scfg.max_items) { g->err = "request larger than max_items"; return CM_E_CAPACITY; }
+        const int64_t bytes = serve_bytes(CM_REQ_DELETE_VERTICES, c);
+        int64_t start = 0;
+        if (!serve_admit(g, c, bytes, &start)) {
+            serve_pump(g);
+            if (!serve_admit(g, c, bytes, &start)) return CM_E_BUSY;
+        }
+        const int64_t pos = start % g->scfg.ring_items;
+        if (c > 0) std::memcpy(g->ssrc + pos, ids, sizeof(int32_t) * (size_t)c);
+        ProgBatch b{};
+        b.off = pos;
+        b.s = c;
+        b.kind = CM_REQ_DELETE_VERTICES;
+        b.n_ids = g->s_n_ids;
+        serve_publish(g, b, start, bytes, g->s_n_ids, ticket);
+        serve_pump(g);
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_serve_poll(cm_graph *g, int64_t *finished) {
+    if (!g) return CM_E_ARG;
+    try {
+        serve_require(g);
+        serve_pump(g);
+        if (finished) *finished = g->s_done;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_serve_result(cm_graph *g, int64_t ticket, cm_batch_stats *out) {
+    if (!g || !out || ticket < 0) return CM_E_ARG;
+    if (ticket >= g->s_done) return CM_E_BUSY;
+    *out = g->s_results[(size_t)ticket];
+    return CM_OK;
+}
+
+int cm_serve_stop(cm_graph *g) {
+    if (!g) return CM_E_ARG;
+    if (!g->serving) return CM_OK;
+    try {
+        // finish every admitted request, then end the launch
+        const double t0 = now_ms();
+        while (g->s_done < g->s_next) {
+            serve_pump(g);
+            if (now_ms() - t0 > 600000.0) {
+                g->poisoned = true;
+                g->err = "serving did not drain";
+                throw Fail{CM_E_INTERNAL};
+            }
+        }
+        if (g->serve_live) {
+            __atomic_store_n(&g->shdr->stop, 1, __ATOMIC_RELEASE);
+            while (__atomic_load_n(&g->shdr->exit_reason, __ATOMIC_ACQUIRE) == 0) {
+                if (now_ms() - t0 > 600000.0) {
+                    g->poisoned = true;
+                    g->err = "serving launch did not stop";
+                    throw Fail{CM_E_INTERNAL};
+                }
+            }
+            serve_after_exit(g);
+        }
+        g->g.n_ids = std::max(g->g.n_ids, g->s_n_ids);
+        g->serving = false;
+        serve_free(g);
+    } catch (const Fail &f) {
+        g->serving = false;
+        return f.code;
+    }
+    return CM_OK;
+}
+
+int cm_phase_times(cm_graph *g, double *ms, int64_t *counts, int32_t n, int reset) {
+    if (!g || n < 0 || n > PH_SLOTS || (n > 0 && !ms)) return CM_E_ARG;
+    try {
+        if (!g->ctl) return CM_E_STATE;
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+        if (khz <= 0) { g->err = "device wall clock rate unknown"; throw Fail{CM_E_DEVICE}; }
+        unsigned long long buf[2 * PH_SLOTS];
+        HIPCHK(hipMemcpyAsync(buf, &g->ctl->ph_ticks[0], sizeof(buf), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        for (int32_t i = 0; i < n; ++i) {
+            ms[i] = (double)buf[i] / (double)khz;
+            if (counts) counts[i] = (int64_t)buf[PH_SLOTS + i];
+        }
+        if (reset) {
+            std::memset(buf, 0, sizeof(buf));
+            HIPCHK(hipMemcpyAsync(&g->ctl->ph_ticks[0], buf, sizeof(buf), hipMemcpyHostToDevice, g->stream));
+            HIPCHK(hipStreamSynchronize(g->stream));
+        }
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
 int cm_num_vertices(cm_graph *g, int32_t *n_ids, int32_t *n_alive) {
     if (!g) return CM_E_ARG;
     if (n_ids) *n_ids = g->g.n_ids;
@@ -1244,6 +1719,7 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
                 cm_batch_stats tmp;
                 std::memset(&tmp, 0, sizeof(tmp));
                 tmp.first_bad = -1;
+                const double tb = now_ms();
                 int64_t dropped = 0;
                 try {
                     edge_batch(g, sj, kinds[j] == CM_BATCH_INSERT, &tmp, &dropped, false, false, dsub != nullptr);
@@ -1251,6 +1727,7 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
                     if (g->poisoned || f.code > CM_E_RANGE || f.code < CM_E_DEAD) throw;
                     tmp.status = f.code;
                 }
+                tmp.ms_total = now_ms() - tb;
                 if (results) results[j] = tmp;
             }
             g->b.sub_in = nullptr;
@@ -1366,7 +1843,7 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
             for (int32_t b = 0; b < nsub; ++b)
                 sub_status[b] = sb[b] == ~0ull ? CM_OK : -(int)(sb[b] & 0xff);
         }
-        if (results && nb > 0) results[0].ms_total = now_ms() - t0;
+        if (results && nb > 0 && g->cfg.mode != CM_MODE_PLAIN) results[0].ms_total = now_ms() - t0;
     } catch (const Fail &f) {
         g->b.sub_in = nullptr;
         return f.code;

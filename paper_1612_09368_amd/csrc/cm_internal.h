@@ -18,6 +18,18 @@ constexpr int WAVE = 64;
 constexpr int32_t TOMB = -1;             // deleted adjacency slot
 constexpr uint64_t EMPTY_KEY = ~0ull;    // empty hash slot
 
+// One batch of a batch program: items [off, off + s) of the program's
+// src/dst (and of sub, when it packs independent batches).
+struct ProgBatch {
+    int64_t off;
+    int32_t s;
+    int32_t kind;        // 0 insert edges, 1 delete edges, 2 insert vertices, 3 delete vertices
+    int32_t v0;          // kind 2: first new id
+    int32_t nv;          // kind 2: new ids [v0, v0 + nv); items are their edges (new id, neighbour)
+    int32_t n_ids;       // ids in use for this batch (0: the launch's); kind 3: items are ids
+    int32_t pad;
+};
+
 // ---------------------------------------------------------------------------
 // Control block: counters shared by all workgroups of a launch.  Rotating
 // queue tails use three slots: in round r the tail r%3 is read, (r+1)%3
@@ -64,7 +76,26 @@ struct Ctl {
     unsigned long long st_rounds;       // cascade rounds (expansion, eviction, peel)
     unsigned long long st_grid_steps;   // steps run by the whole grid
     unsigned long long st_local_steps;  // steps run inside one workgroup
+    // phase clock (device wall clock ticks, summed until the host clears them;
+    // written by global thread 0 only): indices are StepKind for grid steps,
+    // then PH_LOCAL .. PH_COMPACT below
+    unsigned long long ph_ticks[16];
+    unsigned long long ph_count[16];
+    // vertex deletion inside a batch program
+    unsigned long long vd_total;  // list slots of the valid ids
+    int32_t vd_tail;              // gathered edges
+    int32_t vd_bad;               // smallest invalid id index
+    int32_t vd_count;             // valid ids
+    int32_t sv_decision;          // serving: decision of the waiting thread
+    ProgBatch sv_batch;           // serving: descriptor of the current batch
 };
+
+// Phase-clock slots after the step kinds (0 .. 7).
+constexpr int PH_LOCAL = 8;      // a chain of steps run inside workgroup 0 (plus its barrier)
+constexpr int PH_VALIDATE = 9;   // batch validation in a batch program
+constexpr int PH_RESERVE = 10;   // capacity reservation in a batch program
+constexpr int PH_COMPACT = 11;   // tombstone compaction in a batch program
+constexpr int PH_SLOTS = 16;
 
 // Grid barrier state: one arrival counter per group of workgroups (a group is
 // the workgroups that share blockIdx % NGRP, i.e. one XCD under round-robin
@@ -187,26 +218,39 @@ struct BatchCtx {
     int32_t bstamp;      // per-vertex mark values bstamp (scan) and bstamp + 1 (endpoints)
     int32_t hcap;        // hash slots used (power of two, <= allocated)
     int32_t strict;      // reject a whole (sub-)batch that has an invalid item
+    int32_t n_ids;       // ids in use (range check)
 };
 
 __device__ __forceinline__ BatchCtx batch_of(const KArgs &a) {
     return BatchCtx{a.b.src_in, a.b.dst_in, a.b.sub_in, a.b.sub_bad, a.s, a.inserting, a.cur, a.bstamp,
-                    a.b.hcap, a.strict};
+                    a.b.hcap, a.strict, a.g.n_ids};
 }
 
-// A sequence of batches run by one persistent launch.  Batch j covers items
-// [off, off + s) of src/dst (and of sub, when it packs independent batches).
-struct ProgBatch {
-    int64_t off;
-    int32_t s;
-    int32_t kind;        // 0 = insert edges, 1 = delete edges
-};
+// Outcome of one batch of a batch program.
 struct ProgOut {
     int32_t status;      // 0 or the error code of the first invalid item (strict)
     int32_t first_bad;
-    int32_t valid;
+    int32_t valid;       // edges applied
     int32_t iterations;
+    int32_t vdone;       // vertex batches: vertices inserted / deleted
+    int32_t pad;
     unsigned long long remaining, selected, candidates, evicted, changed, scanned, rounds, steps;
+};
+// Why a serving launch ended (ServeHdr.exit_reason; 0 while it runs).
+enum ServeExit : int32_t { SV_RUN = 1, SV_STOP = 2, SV_IDLE = 3, SV_POOL = 4, SV_ABORT = 5, SV_TOOBIG = 6 };
+
+// Serving header in pinned host memory; each word on its own 128-byte line.
+struct ServeHdr {
+    long long tail;       // batches published by the host
+    char pad0[120];
+    long long head;       // batches finished by the device
+    char pad1[120];
+    int32_t stop;         // host: leave after the current batch
+    char pad2[124];
+    int32_t exit_reason;  // device: why the launch ended (0 while running)
+    int32_t pad3;
+    long long exit_at;    // device: first batch not finished
+    char pad4[112];
 };
 struct ProgDesc {
     const ProgBatch *batches;
@@ -215,6 +259,14 @@ struct ProgDesc {
     const int32_t *dst;
     const int32_t *sub;  // sub-batch id per item (or null)
     unsigned long long *sub_bad;  // per sub-batch min of (item << 8 | -code) (or null)
+    int32_t *gsrc;       // vertex deletion: gathered edges (capacity gcap)
+    int32_t *gdst;
+    int64_t gcap;
+    int32_t *firstidx;   // [n_cap] vertex-deletion duplicate marks (INT_MAX between uses)
+    ServeHdr *hdr;       // serving: request ring header (null for a fixed program)
+    long long sfirst;    // serving: first batch of this launch
+    unsigned long long idle_ticks;  // serving: wall-clock ticks without work before leaving
+    int32_t ring;        // serving: ring slots
     int32_t nb;
     int32_t first;       // first batch to run
     int32_t strict;
@@ -238,6 +290,18 @@ __device__ __forceinline__ int gthreads() { return (int)(gridDim.x * blockDim.x)
 __device__ __forceinline__ int wave_sum(int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+// Phase clock: global thread 0 reads the device wall clock before a phase
+// and adds the elapsed ticks after the barrier that ends it.
+__device__ __forceinline__ unsigned long long ph_start() {
+    return gtid() == 0 ? (unsigned long long)wall_clock64() : 0ull;
+}
+__device__ __forceinline__ void ph_stop(Ctl *c, int slot, unsigned long long t0) {
+    if (gtid() == 0) {
+        c->ph_ticks[slot] += (unsigned long long)wall_clock64() - t0;
+        c->ph_count[slot] += 1;
+    }
 }
 
 // Coherent read of a control word.  Relaxed (no cache invalidation): the

@@ -377,6 +377,7 @@ __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
 }
 
 __global__ void __launch_bounds__(COOP_THREADS) k_program(KArgs a) { run_program(a); }
+__global__ void __launch_bounds__(COOP_THREADS) k_serve(KArgs a) { run_server(a); }
 
 // ---------------------------------------------------------------------------
 // Vertex operations
@@ -611,6 +612,9 @@ hipError_t program_coop(const KArgs &a, int blocks, hipStream_t st) {
     return coop((const void *)k_program, a, blocks, st);
 }
 const void *program_kernel() { return (const void *)k_program; }
+hipError_t serve_coop(const KArgs &a, int blocks, hipStream_t st) {
+    return coop((const void *)k_serve, a, blocks, st);
+}
 hipError_t vins_init(const KArgs &a, int32_t first, int32_t c, hipStream_t st) {
     k_vins_init<<<grid_for(c, 4096), 256, 0, st>>>(a, first, c);
     return hipGetLastError();
@@ -646,9 +650,10 @@ hipError_t vdel_finish(const KArgs &a, const int32_t *ids, int32_t c, hipStream_
 }
 
 hipError_t coop_occupancy(int which, int *blocks_per_cu) {
-    const void *fn = which == 0 ? (const void *)k_maintain
+    const void *fn = which == 0   ? (const void *)k_maintain
                      : which == 1 ? (const void *)k_decompose
-                                  : (const void *)k_program;
+                     : which == 2 ? (const void *)k_program
+                                  : (const void *)k_serve;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, COOP_THREADS, 0);
 }
 

@@ -40,6 +40,7 @@ hipError_t delete_compact(const KArgs &a, int blocks, hipStream_t st);
 hipError_t maintain_coop(const KArgs &a, int blocks, hipStream_t st);
 hipError_t program_coop(const KArgs &a, int blocks, hipStream_t st);
 const void *program_kernel();
+hipError_t serve_coop(const KArgs &a, int blocks, hipStream_t st);
 
 hipError_t vins_init(const KArgs &a, int32_t first, int32_t c, hipStream_t st);
 hipError_t vins_revert(const KArgs &a, int32_t first, int32_t c, hipStream_t st);

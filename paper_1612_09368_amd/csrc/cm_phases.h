@@ -42,7 +42,7 @@ __device__ __forceinline__ void count_agg(int32_t *ctr, bool pred) {
 // V1: range / dead / self-loop checks, canonical (min, max), hash insert
 // (the smallest item index of each pair wins the slot).
 __device__ __forceinline__ void val_canon(const KArgs &a, const BatchCtx &bc, const Team &T) {
-    const int32_t n = a.g.n_ids;
+    const int32_t n = bc.n_ids;
     const uint32_t mask = (uint32_t)bc.hcap - 1u;
     for (int32_t i = T.rank; i < bc.s; i += T.size) {
         int32_t u = bc.src[i], v = bc.dst[i];
@@ -454,6 +454,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     auto claim = [&](int32_t w, int32_t k) -> bool {
         if (w < 0) return false;
         if (g.core[w] != k || g.mcd[w] <= k) return false;
+        if (ld_rlx(&g.stamp[w]) == ep) return false;  // already claimed: skip the atomic
         if (atomicExch(&g.stamp[w], ep) == ep) return false;
         g.cd[w] = 0;
         return true;
@@ -901,11 +902,14 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
             int64_t work = step_work(a, it, pc);
             if (force || !step_is_local(a, pc, work)) {
                 force = false;
+                const unsigned long long t0 = ph_start();
                 run_step(a, it, pc, grid_team(), scanned);
                 if (gtid() == 0) c->st_grid_steps += 1;
                 gbar(a.bar);
+                ph_stop(c, pc.step, t0);
                 pc = next_pc(a, it, pc);
             } else {
+                const unsigned long long t0 = ph_start();
                 const int slot = pubs & 1;
                 if (blockIdx.x == 0) {
                     const Team T = block_team();
@@ -931,6 +935,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                 pc.r = ld_rlx(&c->ipub[slot][1]);
                 force = ld_rlx(&c->ipub[slot][2]) != 0;
                 ++pubs;
+                ph_stop(c, PH_LOCAL, t0);
             }
             if (bar_aborted(a.bar)) break;
         }
@@ -948,6 +953,12 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
 // one) is skipped without touching the graph.  When the adjacency pool runs
 // out during a reservation the launch stops before mutating anything of that
 // batch and reports where (the host repacks and relaunches from there).
+//
+// Vertex batches follow the reduction of vertex updates to edge updates:
+// an insertion activates its new ids (core 0, empty list) and inserts their
+// edges (a rejected batch leaves the new ids dead); a deletion checks its
+// ids, gathers their live edges (an edge between two deleted ids once),
+// deletes them as one edge batch and then marks the ids dead.
 // ===========================================================================
 __device__ __forceinline__ int32_t hash_slots(int32_t s) {
     int32_t want = 2 * s > 1024 ? 2 * s : 1024;
@@ -956,8 +967,7 @@ __device__ __forceinline__ int32_t hash_slots(int32_t s) {
     return h;
 }
 
-__device__ __forceinline__ void prog_setup(const KArgs &a, const BatchCtx &bc, const ProgBatch &B,
-                                          const Team &T) {
+__device__ __forceinline__ void prog_reset_ctl(const KArgs &a, const BatchCtx &bc, const Team &T) {
     Ctl *c = a.ctl;
     if (T.lead()) {
         c->rem_count[0] = 0;
@@ -974,9 +984,6 @@ __device__ __forceinline__ void prog_setup(const KArgs &a, const BatchCtx &bc, c
         c->scan_tail = 0;
         c->vlist_count = 0;
         c->reloc_count = 0;
-        c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
-        c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
-        c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
     }
     for (int32_t i = T.rank; i < bc.hcap; i += T.size) {
         a.b.hkey[i] = EMPTY_KEY;
@@ -984,13 +991,27 @@ __device__ __forceinline__ void prog_setup(const KArgs &a, const BatchCtx &bc, c
     }
 }
 
+__device__ __forceinline__ void prog_clear_stats(const KArgs &a, const Team &T) {
+    Ctl *c = a.ctl;
+    if (T.lead()) {
+        c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
+        c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
+        c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
+        c->vd_total = 0;
+        c->vd_tail = 0;
+        c->vd_bad = 0x7fffffff;
+        c->vd_count = 0;
+    }
+}
+
 __device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t status, int32_t fb, int32_t valid,
-                                           int32_t iters) {
+                                           int32_t iters, int32_t vdone) {
     Ctl *c = a.ctl;
     o.status = status;
     o.first_bad = fb;
     o.valid = valid;
     o.iterations = iters;
+    o.vdone = vdone;
     o.remaining = c->st_remaining;
     o.selected = c->st_selected;
     o.candidates = c->st_candidates;
@@ -999,6 +1020,238 @@ __device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t 
     o.scanned = c->st_scanned;
     o.rounds = c->st_rounds;
     o.steps = c->st_grid_steps + c->st_local_steps;
+}
+
+// One edge batch described by bc (validation through compaction).  Returns
+// 1 when the adjacency pool ran out during the reservation (nothing of the
+// batch was applied), else 0; *status/*fb/*valid/*iters describe the outcome
+// (the same values in every thread).
+__device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &bc, int32_t &ep, long long &scanned,
+                                               int &pubs, int32_t &status, int32_t &fb, int32_t &valid,
+                                               int32_t &iters) {
+    Ctl *c = a.ctl;
+    const Team G = grid_team();
+    unsigned long long t0 = ph_start();
+    prog_reset_ctl(a, bc, G);
+    gbar(a.bar);
+    val_canon(a, bc, G);
+    gbar(a.bar);
+    val_dup_mark(a, bc, G);
+    gbar(a.bar);
+    val_scan(a, bc, G);
+    gbar(a.bar);
+    val_final(a, bc, G);
+    gbar(a.bar);
+    if (bc.sub) {
+        val_subfilter(a, bc, G);
+        gbar(a.bar);
+    }
+    ph_stop(c, PH_VALIDATE, t0);
+    const int32_t f = ld_rlx(&c->first_bad);
+    fb = f == 0x7fffffff ? -1 : f;
+    valid = qlen(&c->rem_count[bc.cur], a.b.cap);
+    iters = 0;
+    status = 0;
+    if (bc.strict && !bc.sub && f != 0x7fffffff) {
+        status = a.b.err[f];
+        valid = 0;
+        return 0;
+    }
+    if (valid == 0) return 0;
+    t0 = ph_start();
+    res_gain(a, bc, G);
+    gbar(a.bar);
+    if (bc.inserting) {
+        res_alloc(a, G);
+        gbar(a.bar);
+        if (ld_rlx(&c->pool_fail)) return 1;
+        res_copy(a, G);
+        gbar(a.bar);
+    }
+    ph_stop(c, PH_RESERVE, t0);
+    iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
+    if (!bc.inserting) {
+        t0 = ph_start();
+        del_compact(a, G);
+        gbar(a.bar);
+        ph_stop(c, PH_COMPACT, t0);
+    }
+    flush_stat(&c->st_scanned, scanned);
+    scanned = 0;
+    gbar(a.bar);
+    return 0;
+}
+
+// Vertex deletion, first part: check the ids (range, dead, repeated: the
+// smallest index wins) and sum the list lengths of the valid ones.
+__device__ __forceinline__ void vdel_check_ids(const KArgs &a, const ProgDesc *pd, const int32_t *ids, int32_t s,
+                                               int32_t n_ids, const Team &T) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    for (int32_t i = T.rank; i < s; i += T.size) {
+        int32_t x = ids[i];
+        int32_t e = 0;
+        if (x < 0 || x >= n_ids) e = ST_RANGE;
+        else if (g.core[x] < 0) e = ST_DEAD;
+        a.b.err[i] = e;
+        if (e == 0) atomicMin(&pd->firstidx[x], i);
+    }
+}
+__device__ __forceinline__ void vdel_dup_count(const KArgs &a, const ProgDesc *pd, const int32_t *ids, int32_t s,
+                                               const Team &T) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    long long tot = 0;
+    int32_t good = 0;
+    for (int32_t i = T.rank; i < s; i += T.size) {
+        if (a.b.err[i] != 0) { atomicMin(&c->vd_bad, i); continue; }
+        int32_t x = ids[i];
+        if (pd->firstidx[x] != i) {
+            a.b.err[i] = ST_DUP;
+            atomicMin(&c->vd_bad, i);
+            continue;
+        }
+        tot += g.len[x];
+        ++good;
+    }
+    flush_stat(&c->vd_total, tot);
+    for (int o = 32; o > 0; o >>= 1) good += __shfl_xor(good, o);
+    if (lane() == 0 && good) atomicAdd(&c->vd_count, good);
+}
+// Gather the live edges of the valid ids; an edge whose other end is also
+// deleted is taken from its smaller end only.
+__device__ __forceinline__ void vdel_gather_edges(const KArgs &a, const ProgDesc *pd, const int32_t *ids, int32_t s,
+                                                  const Team &T) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    for (int32_t i = T.wave(); i < s; i += T.nwaves()) {
+        if (a.b.err[i] != 0) continue;
+        int32_t x = ids[i];
+        int32_t L = g.len[x];
+        wave_walk(g, x, 0, L, [&](int32_t w, int32_t) {
+            bool take = w >= 0 && !(w < x && pd->firstidx[w] != 0x7fffffff);
+            unsigned long long m = __ballot(take);
+            int rank = __popcll(m & ((1ull << lane()) - 1ull));
+            int32_t base = 0;
+            if (lane() == 0 && m) base = atomicAdd(&c->vd_tail, (int32_t)__popcll(m));
+            base = __shfl(base, 0);
+            if (take && (int64_t)base + rank < pd->gcap) {
+                pd->gsrc[base + rank] = x;
+                pd->gdst[base + rank] = w;
+            }
+        });
+    }
+}
+// Mark the deleted ids dead and clear their duplicate marks (also for an
+// invalid batch, which only set marks).
+__device__ __forceinline__ void vdel_finish_ids(const KArgs &a, const ProgDesc *pd, const int32_t *ids, int32_t s,
+                                                bool apply, const Team &T) {
+    const DevGraph &g = a.g;
+    for (int32_t i = T.rank; i < s; i += T.size) {
+        if (a.b.err[i] == ST_RANGE) continue;
+        int32_t x = ids[i];
+        if (apply && a.b.err[i] == 0) {
+            g.core[x] = -1;
+            g.mcd[x] = 0;
+            g.len[x] = 0;
+        }
+        pd->firstidx[x] = 0x7fffffff;
+    }
+}
+
+// Run batch B (index j of the launch).  Returns 1 when the launch must stop
+// for a pool repack before this batch, else 0 (outcome recorded in out).
+__device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd, const ProgBatch &B, ProgOut &out,
+                                             int32_t bstamp, int32_t &ep, long long &scanned, int &pubs) {
+    Ctl *c = a.ctl;
+    const Team G = grid_team();
+    const int32_t n_ids = B.n_ids > 0 ? B.n_ids : a.g.n_ids;
+    BatchCtx bc;
+    bc.src = pd->src + B.off;
+    bc.dst = pd->dst + B.off;
+    bc.sub = (pd->sub && B.kind <= 1) ? pd->sub + B.off : nullptr;
+    bc.sub_bad = pd->sub_bad;
+    bc.s = B.s;
+    bc.inserting = B.kind == 0 || B.kind == 2;
+    bc.cur = (ep + 1) & 1;
+    bc.bstamp = bstamp;
+    bc.hcap = hash_slots(B.s);
+    bc.strict = pd->strict;
+    bc.n_ids = n_ids;
+    prog_clear_stats(a, G);
+    int32_t status = 0, fb = -1, valid = 0, iters = 0, vdone = 0;
+    if (B.kind == 3) {
+        // vertex deletion
+        const int32_t *ids = pd->src + B.off;
+        if (B.s > a.b.cap) {
+            if (gtid() == 0) prog_record(a, out, -9, -1, 0, 0, 0);
+            gbar(a.bar);
+            return 0;
+        }
+        vdel_check_ids(a, pd, ids, B.s, n_ids, G);
+        gbar(a.bar);
+        vdel_dup_count(a, pd, ids, B.s, G);
+        gbar(a.bar);
+        const int32_t bad = ld_rlx(&c->vd_bad);
+        const long long total = (long long)__hip_atomic_load(&c->vd_total, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+        const bool reject = (pd->strict && bad != 0x7fffffff) || total > pd->gcap;
+        if (reject) {
+            const int32_t code = total > pd->gcap && !(pd->strict && bad != 0x7fffffff) ? -9 : a.b.err[bad];
+            gbar(a.bar);  // every thread has read the counters and err[bad]
+            vdel_finish_ids(a, pd, ids, B.s, false, G);
+            if (gtid() == 0) prog_record(a, out, code, bad == 0x7fffffff ? -1 : bad, 0, 0, 0);
+            gbar(a.bar);
+            return 0;
+        }
+        vdel_gather_edges(a, pd, ids, B.s, G);
+        gbar(a.bar);
+        const int32_t ng = ld_rlx(&c->vd_tail);
+        vdone = ld_rlx(&c->vd_count);
+        const int32_t vbad = bad;
+        if (ng > 0) {
+            BatchCtx eb = bc;
+            eb.src = pd->gsrc;
+            eb.dst = pd->gdst;
+            eb.sub = nullptr;
+            eb.s = ng;
+            eb.inserting = 0;
+            eb.hcap = hash_slots(ng);
+            eb.strict = 1;
+            int32_t efb = -1;
+            prog_edge_batch(a, eb, ep, scanned, pubs, status, efb, valid, iters);
+        }
+        // a deletion needs no reservation, so status can only be 0 here
+        vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
+        gbar(a.bar);
+        if (gtid() == 0) prog_record(a, out, status, vbad == 0x7fffffff ? -1 : vbad, valid, iters, vdone);
+        gbar(a.bar);
+        return 0;
+    }
+    if (B.kind == 2) {
+        // vertex insertion: the new ids exist (core 0, empty list) before validation
+        for (int32_t i = G.rank; i < B.nv; i += G.size) {
+            int32_t v = B.v0 + i;
+            a.g.core[v] = 0;
+            a.g.mcd[v] = 0;
+            a.g.len[v] = 0;
+            a.g.cap[v] = 0;
+            a.g.off[v] = 0;
+        }
+        gbar(a.bar);
+    }
+    if (B.s > 0) {
+        if (prog_edge_batch(a, bc, ep, scanned, pubs, status, fb, valid, iters)) return 1;
+    }
+    if (B.kind == 2) {
+        vdone = status == 0 ? B.nv : 0;
+        if (status != 0) {
+            for (int32_t i = G.rank; i < B.nv; i += G.size) a.g.core[B.v0 + i] = -1;
+        }
+    }
+    gbar(a.bar);  // every thread has read the counters before the next batch resets them
+    if (gtid() == 0) prog_record(a, out, status, fb, valid, iters, vdone);
+    return 0;
 }
 
 __device__ __forceinline__ void run_program(const KArgs &a) {
@@ -1010,72 +1263,73 @@ __device__ __forceinline__ void run_program(const KArgs &a) {
     const int32_t nb = pd->nb;
     int32_t j = pd->first;
     int32_t failed = 0;
-    const Team G = grid_team();
     for (; j < nb; ++j) {
         if (bar_aborted(a.bar)) break;
         const ProgBatch B = pd->batches[j];
-        BatchCtx bc;
-        bc.src = pd->src + B.off;
-        bc.dst = pd->dst + B.off;
-        bc.sub = pd->sub ? pd->sub + B.off : nullptr;
-        bc.sub_bad = pd->sub_bad;
-        bc.s = B.s;
-        bc.inserting = B.kind == 0;
-        bc.cur = (ep + 1) & 1;
-        bc.bstamp = pd->bstamp0 + 2 * (j - pd->first);
-        bc.hcap = hash_slots(B.s);
-        bc.strict = pd->strict;
-        if (bc.hcap > a.b.hcap || B.s > a.b.cap) {  // host sized the buffers for the largest batch
+        if (hash_slots(B.s) > a.b.hcap || B.s > a.b.cap) {  // host sized the buffers for the largest batch
             if (gtid() == 0) atomicOr(&c->overflow, 8);
             break;
         }
-        prog_setup(a, bc, B, G);
-        gbar(a.bar);
-        val_canon(a, bc, G);
-        gbar(a.bar);
-        val_dup_mark(a, bc, G);
-        gbar(a.bar);
-        val_scan(a, bc, G);
-        gbar(a.bar);
-        val_final(a, bc, G);
-        gbar(a.bar);
-        if (bc.sub) {
-            val_subfilter(a, bc, G);
-            gbar(a.bar);
+        if (run_one_batch(a, pd, B, pd->out[j], pd->bstamp0 + 2 * (j - pd->first), ep, scanned, pubs)) {
+            failed = 1;
+            break;
         }
-        const int32_t fb = ld_rlx(&c->first_bad);
-        const int32_t valid = qlen(&c->rem_count[bc.cur], a.b.cap);
-        if ((pd->strict && !bc.sub && fb != 0x7fffffff) || valid == 0) {
-            if (gtid() == 0) {
-                int32_t st = (pd->strict && !bc.sub && fb != 0x7fffffff) ? a.b.err[fb] : 0;
-                prog_record(a, pd->out[j], st, fb == 0x7fffffff ? -1 : fb, 0, 0);
-            }
-            gbar(a.bar);  // every workgroup has read the counters before the next setup
-            continue;
-        }
-        res_gain(a, bc, G);
-        gbar(a.bar);
-        if (bc.inserting) {
-            res_alloc(a, G);
-            gbar(a.bar);
-            if (ld_rlx(&c->pool_fail)) { failed = 1; break; }
-            res_copy(a, G);
-            gbar(a.bar);
-        }
-        const int iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
-        if (!bc.inserting) {
-            del_compact(a, G);
-            gbar(a.bar);
-        }
-        flush_stat(&c->st_scanned, scanned);
-        scanned = 0;
-        gbar(a.bar);
-        if (gtid() == 0) prog_record(a, pd->out[j], 0, fb == 0x7fffffff ? -1 : fb, valid, iters);
     }
     if (gtid() == 0) {
         c->epoch = ep;
         pd->stop = j;
         pd->pool_fail = failed;
+    }
+}
+
+// Serving: the same per-batch work, with batches taken from a request ring
+// that the host fills while the launch runs.  Batch j is slot j % ring.
+// Global thread 0 waits for the host's published count (system-scope
+// acquire on the pinned header), a stop request or the idle limit, and
+// broadcasts the decision through the grid barrier; after each batch it
+// publishes the finished count (system-scope release).  Every wave leaves
+// when the decision is not "run".
+__device__ __forceinline__ void run_server(const KArgs &a) {
+    Ctl *c = a.ctl;
+    ProgDesc *pd = a.prog;
+    ServeHdr *h = pd->hdr;
+    int32_t ep = ld_rlx(&c->epoch);
+    long long scanned = 0;
+    int pubs = 0;
+    long long j = pd->sfirst;
+    int32_t reason = SV_STOP;
+    for (;;) {
+        if (bar_aborted(a.bar)) { reason = SV_ABORT; break; }
+        if (gtid() == 0) {
+            int32_t d = SV_RUN;
+            const unsigned long long t0 = (unsigned long long)wall_clock64();
+            for (;;) {
+                long long tail = __hip_atomic_load(&h->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (tail > j) break;
+                if (__hip_atomic_load(&h->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) { d = SV_STOP; break; }
+                if ((unsigned long long)wall_clock64() - t0 > pd->idle_ticks) { d = SV_IDLE; break; }
+                __builtin_amdgcn_s_sleep(16);
+            }
+            if (d == SV_RUN) c->sv_batch = pd->batches[j % pd->ring];  // one host read, not one per thread
+            c->sv_decision = d;
+        }
+        gbar(a.bar);
+        const int32_t d = ld_rlx(&c->sv_decision);
+        if (d != SV_RUN) { reason = d; break; }
+        const ProgBatch B = c->sv_batch;
+        if (hash_slots(B.s) > a.b.hcap || B.s > a.b.cap) { reason = SV_TOOBIG; break; }
+        if (run_one_batch(a, pd, B, pd->out[j % pd->ring], pd->bstamp0 + 2 * (int32_t)(j - pd->sfirst), ep,
+                          scanned, pubs)) {
+            reason = SV_POOL;
+            break;
+        }
+        if (gtid() == 0) __hip_atomic_store(&h->head, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        ++j;
+    }
+    if (gtid() == 0) {
+        c->epoch = ep;
+        h->exit_at = j;
+        __hip_atomic_store(&h->exit_reason, reason, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -1,9 +1,9 @@
 // Load-balanced walks over frontier queues (gfx950, wave64).
 //
 // A frontier is a list of vertices plus a list of chunk items for long
-// adjacency lists.  Each wave takes 64 queue entries: a vertex whose list is
-// short (len <= small) is walked by its own lane; longer lists are walked by
-// the whole wave, one vertex after another (coalesced 256-byte reads);
+// adjacency lists.  Each wave takes up to 64 queue entries: a vertex whose
+// list is short (len <= small) is walked by its own lane; longer lists are
+// walked by the whole wave, one vertex after another (coalesced reads);
 // lists longer than `large` never enter the vertex list -- the pusher splits
 // them into chunk items that separate waves walk.
 #pragma once
@@ -32,13 +32,20 @@ __device__ __forceinline__ void push_vertex(const KArgs &a, int32_t *vq, int32_t
 
 // Team-stride over a vertex queue.  fl(v, L) runs on the owning lane for
 // short lists; fw(v, L) runs on the whole wave (uniform) for the others.
+// A wave takes `per` consecutive entries, per = ceil(n / waves) capped at
+// 64: a queue shorter than 64 entries per wave is spread over every wave
+// instead of leaving most waves idle while a few walk up to 64 lists each.
+// n must be the same in every thread of the team.
 template <class FL, class FW>
 __device__ __forceinline__ void for_vertices(const Team &T, const int32_t *q, int32_t n, const DevGraph &g,
                                              int32_t small, FL &&fl, FW &&fw) {
-    const int step = T.nwaves() * WAVE;
-    for (int32_t base = T.wave() * WAVE; base < n; base += step) {
+    const int nw = T.nwaves();
+    int per = (int)(((int64_t)n + nw - 1) / nw);
+    per = per < 1 ? 1 : (per > WAVE ? WAVE : per);
+    const int step = nw * per;
+    for (int32_t base = T.wave() * per; base < n; base += step) {
         int32_t i = base + lane();
-        int32_t v = (i < n) ? q[i] : -1;
+        int32_t v = (lane() < per && i < n) ? q[i] : -1;
         int32_t L = (v >= 0) ? g.len[v] : 0;
         if (v >= 0 && L <= small) fl(v, L);
         unsigned long long m = __ballot(v >= 0 && L > small);

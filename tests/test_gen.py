@@ -50,3 +50,51 @@ def test_update_streams():
     assert np.unique(graphgen.keys_of(a, b)).size == 700
     sz = graphgen.log_uniform_sizes(1000, 1000, 1_000_000, rng)
     assert sz.min() >= 1000 and sz.max() <= 1_000_000
+
+
+def test_rmat_independent_of_workers():
+    a = graphgen.rmat_graph(10, 16, graphgen.rng_for("rw"), chunk=4096, workers=1)
+    b = graphgen.rmat_graph(10, 16, graphgen.rng_for("rw"), chunk=4096, workers=2)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    _simple(a[0], a[1], a[2])
+
+
+def test_dynamic_edge_set_matches_edge_set():
+    rng = graphgen.rng_for("dyn")
+    s, d = graphgen.er_graph(500, 3000, rng)
+    es = graphgen.EdgeSet(s, d)
+    dyn = graphgen.DynamicEdgeSet(s, d)
+    probe = graphgen.keys_of(rng.integers(0, 500, 4000), rng.integers(0, 500, 4000))
+    for step in range(30):
+        if step % 2 == 0:
+            a, b = graphgen.uniform_non_edges(500, 200, dyn, rng)
+            assert not es.contains(graphgen.keys_of(a, b)).any()
+            es.insert(a, b)
+            dyn.insert(a, b)
+        else:
+            a, b = graphgen.existing_edges(250, dyn, rng)
+            k = graphgen.keys_of(a, b)
+            assert es.contains(k).all() and np.unique(k).size == k.size
+            es.delete(a, b)
+            dyn.delete(a, b)
+        assert len(es) == len(dyn)
+        assert np.array_equal(es.contains(probe), dyn.contains(probe))
+        assert np.array_equal(np.sort(graphgen.keys_of(*dyn.edges())), es.keys)
+
+
+def test_serve_stream_requests_are_valid_in_order():
+    import oracle
+    n, s, d, reqs = graphgen.serve_stream(10, 150, graphgen.rng_for("sv-valid"), max_size=300)
+    kinds = [r[0] for r in reqs]
+    assert {"ins", "del", "vins", "vdel"} <= set(kinds)
+    ref = oracle.DynamicGraph(n, s, d)
+    for r in reqs:
+        if r[0] == "ins":
+            st = ref.insert_edges(r[1], r[2])[0]
+        elif r[0] == "del":
+            st = ref.delete_edges(r[1], r[2])[0]
+        elif r[0] == "vins":
+            st = ref.insert_vertices(r[1], r[2])[0]
+        else:
+            st = ref.delete_vertices(r[1])[0]
+        assert st == 0, r[0]
