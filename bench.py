@@ -43,6 +43,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per k_maintain launch on the default workload (plain form), from two rocprofv3 counter
+# passes (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, both scaled by what they read for a 1 GiB
+# device copy); the summary and commands are in profiles/k_maintain_chunglu_1m_hbm_traffic.md.
+# It describes the kernel sources it was measured on: reported only while their hash matches.
+TRAFFIC = {"kernel": "k_maintain", "bytes_per_launch": 286.9e6,
+           "sources_sha256": "49496640dcd13d263fd1e2379d35db8f34022519b51fd4aa5f503c0c243ebaa2"}
+KERNEL_SOURCES = ["cm_internal.h", "cm_kernels.hip", "cm_phases.h", "cm_walk.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(KERNEL_SOURCES):
+        with open(os.path.join(ROOT, "paper_1612_09368_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 METRIC = "edge updates/sec (insert & delete, exact cores) batched vs plain on 1 GPU; p99 latency"
 WORKERS = max(1, min(16, os.cpu_count() or 1))
 
@@ -236,6 +253,9 @@ def bench_cl1m(args, cm, torch):
                    "plain (one cooperative launch per superior edge set)")
     out["roofline"] = roofline("k_maintain", st, "one superior edge set (partition, apply, cascade, "
                                                 "core and SD update)")
+    if kernel_sources_sha256() == TRAFFIC["sources_sha256"]:
+        out["roofline"]["traffic"] = TRAFFIC["bytes_per_launch"]
+        out["roofline"]["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     out["latency_ms"] = {"p50": pct(plain["lat"], 50), "p99": pct(plain["lat"], 99),
                          "per": "batch of 100000 edges"}
     out["tuning"] = tuning

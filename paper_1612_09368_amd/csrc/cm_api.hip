@@ -1754,6 +1754,11 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
             int launches = 0;
             for (int attempt = 0; attempt < 8; ++attempt) {
                 ProgDesc *hd = g->h_prog;
+                std::memset(hd, 0, sizeof(ProgDesc));
+                hd->gsrc = g->src_buf;
+                hd->gdst = g->dst_buf;
+                hd->gcap = g->batch_cap;
+                hd->firstidx = g->firstidx;
                 hd->batches = g->d_pbatch;
                 hd->out = g->d_pout;
                 hd->src = ds;

@@ -268,11 +268,24 @@ __device__ __forceinline__ void del_compact(const KArgs &a, const Team &T) {
 // takes the same path.
 // ===========================================================================
 
+// Vertex-star iterations (see the star section below): mode 0 = ordinary
+// edge iterations, 1 = insertion stars, 2 = deletion stars.
+struct StarCtx {
+    int32_t mode;
+    int32_t v0, nv;          // insertion: new ids [v0, v0 + nv)
+    int32_t s;               // insertion: batch items
+    const int32_t *src;      // insertion: raw items, src = new id (runs in id order)
+    const int32_t *dst;
+    int32_t ng;              // deletion: gathered edges
+    const int32_t *firstidx; // deletion: != INT_MAX for the ids being deleted
+};
+
 struct Iter {
     int32_t ep;    // iteration stamp
-    int32_t cur;   // remaining list read by this iteration
+    int32_t cur;   // remaining list read by this iteration (edges, or pending stars)
     int32_t n_r;   // its length
     int32_t ins;   // 1 = insertion batch, 0 = deletion batch
+    StarCtx sc;
 };
 
 enum StepKind : int32_t { S_CLAIM = 0, S_SELECT, S_APPLY, S_EXPAND, S_EVICT, S_PEEL, S_CORE, S_MCD, S_DONE };
@@ -435,6 +448,295 @@ __device__ __forceinline__ void apply_delete(const KArgs &a, const Iter &it, con
 __device__ __forceinline__ bool is_support(const DevGraph &g, int32_t w, int32_t k) {
     int32_t cw = g.core[w];
     return cw > k || (cw == k && g.mcd[w] > k);
+}
+
+// ===========================================================================
+// Vertex stars: a vertex insertion or deletion in few iterations.
+//
+// A new vertex v enters with all its edges to existing vertices at once, its
+// core pre-set to hK(v) = the h-index of its neighbours' current cores (the
+// largest h with at least h neighbours of core >= h).  The core numbers of a
+// graph satisfy core(x) = h-index of the neighbours' cores, and inserting v
+// raises no other vertex by more than one, so hK(v) <= core'(v) <= hK(v) + 1;
+// an existing neighbour w is constrained by v's edge when core(w) <= hK(v)
+// (only then can v support its rise), and in one iteration every existing
+// vertex takes at most one constraining edge (claims, as in the superior edge
+// set partition).  Then every vertex moves by at most one and the usual
+// expansion / eviction rounds find who rises: roots are the constrained
+// neighbours whose SD exceeds their core and v itself when SD(v) > hK(v).
+// Edges between two new vertices wait for an ordinary edge pass.
+//
+// A deleted vertex x leaves with all its remaining edges at once: a remaining
+// neighbour w is constrained when core(w) <= core(x) (the edge's constrained
+// endpoint in the deletion set sense) and takes at most one constraining
+// edge per iteration; two deleted vertices that are adjacent never go in the
+// same iteration.  x itself is dead afterwards, so its own core is not
+// maintained; every other vertex drops by at most one and the usual peel
+// rounds find who drops.
+// ===========================================================================
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *p, int32_t n, int32_t key) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (p[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned long long star_key(const Iter &it, const KArgs &a, uint32_t id) {
+    const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds;
+    return ((unsigned long long)(0xFFFFFFFFu - sr) << 32) | mix32(id);
+}
+__device__ __forceinline__ uint32_t star_mstamp(const Iter &it, const KArgs &a) {
+    return (uint32_t)it.ep * (uint32_t)a.t.rounds + 1u;
+}
+
+// Insertion star i: item j of [lo, hi) is an edge of v = v0 + i to an
+// existing vertex when it is valid and its other end is not new.
+__device__ __forceinline__ bool star_old_edge(const KArgs &a, const StarCtx &sc, int32_t j, int32_t &w) {
+    w = sc.dst[j];
+    return a.b.err[j] == 0 && !(w >= sc.v0 && w < sc.v0 + sc.nv);
+}
+
+// h-index of the current cores of star v's existing neighbours (wave-wide;
+// every lane returns it).
+__device__ __forceinline__ int32_t star_hindex(const KArgs &a, const StarCtx &sc, int32_t lo, int32_t hi,
+                                               long long &scanned) {
+    int32_t deg = 0;
+    for (int32_t j = lo + lane(); j < hi; j += WAVE) {
+        int32_t w;
+        if (star_old_edge(a, sc, j, w)) ++deg;
+    }
+    deg = wave_sum(deg);
+    int32_t l = 0, h = deg;
+    while (l < h) {  // uniform across the wave
+        const int32_t mid = (l + h + 1) >> 1;
+        int32_t cnt = 0;
+        for (int32_t j = lo + lane(); j < hi; j += WAVE) {
+            int32_t w;
+            if (star_old_edge(a, sc, j, w) && a.g.core[w] >= mid) ++cnt;
+        }
+        cnt = wave_sum(cnt);
+        if (cnt >= mid) l = mid;
+        else h = mid - 1;
+    }
+    if (lane() == 0) scanned += (long long)(hi - lo);
+    return l;
+}
+
+__device__ __forceinline__ void star_run(const StarCtx &sc, int32_t i, int32_t &lo, int32_t &hi) {
+    lo = lower_bound_i32(sc.src, sc.s, sc.v0 + i);
+    hi = lower_bound_i32(sc.src, sc.s, sc.v0 + i + 1);
+}
+
+// Pending deletion star x and its remaining neighbour w: w is claimed when
+// it is itself a pending deleted vertex or constrained by the edge.
+__device__ __forceinline__ bool star_del_claims(const KArgs &a, const StarCtx &sc, int32_t x, int32_t w) {
+    return sc.firstidx[w] != 0x7fffffff || a.g.core[w] <= a.g.core[x];
+}
+
+__device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
+    Ctl *c = a.ctl;
+    const StarCtx &sc = it.sc;
+    if (T.lead()) {
+        c->sel_count = 0;
+        c->rem_count[it.cur ^ 1] = 0;
+        for (int j = 0; j < 3; ++j) {
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->eq_tail[j] = 0; c->eh_tail[j] = 0;
+        }
+        c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
+        c->touched_count = 0; c->changed_count = 0;
+        c->st_iters += 1;
+        c->st_remaining += (unsigned long long)it.n_r;
+    }
+    const int32_t *R = a.b.rem[it.cur];
+    for (int32_t idx = T.wave(); sc.mode == 1 && idx < it.n_r; idx += T.nwaves()) {
+        const int32_t id = R[idx];
+        const unsigned long long key = star_key(it, a, (uint32_t)id);
+        {
+            const int32_t v = sc.v0 + id;
+            int32_t lo, hi;
+            star_run(sc, id, lo, hi);
+            const int32_t hk = star_hindex(a, sc, lo, hi, scanned);
+            if (lane() == 0) a.g.dec[v] = hk + 1;  // kept until the star is applied
+            for (int32_t j = lo + lane(); j < hi; j += WAVE) {
+                int32_t w;
+                if (star_old_edge(a, sc, j, w) && a.g.core[w] <= hk) atomicMin(&a.g.claim[w], key);
+            }
+        }
+    }
+    if (sc.mode == 2) {
+        // deletion stars: each claims itself, and every remaining gathered
+        // edge claims, for each of its pending deleted ends o, the other end
+        // when that is pending too or constrained by the edge
+        for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
+            const int32_t x = R[idx];
+            atomicMin(&a.g.claim[x], star_key(it, a, (uint32_t)x));
+            a.g.cd[x] = 0;  // lost mark of this iteration (set by the select step)
+        }
+        for (int32_t i = T.rank; i < sc.ng; i += T.size) {
+            if (a.b.err[i] != 0) continue;
+            const int32_t u = a.b.eu[i], v = a.b.ev[i];
+            if (sc.firstidx[u] != 0x7fffffff && star_del_claims(a, sc, u, v))
+                atomicMin(&a.g.claim[v], star_key(it, a, (uint32_t)u));
+            if (sc.firstidx[v] != 0x7fffffff && star_del_claims(a, sc, v, u))
+                atomicMin(&a.g.claim[u], star_key(it, a, (uint32_t)v));
+        }
+        if (T.lead()) scanned += sc.ng;
+    }
+}
+
+__device__ __forceinline__ void star_select(const KArgs &a, const Iter &it, const Team &T) {
+    Ctl *c = a.ctl;
+    const StarCtx &sc = it.sc;
+    const int32_t *R = a.b.rem[it.cur];
+    const uint32_t mstamp = star_mstamp(it, a);
+    if (sc.mode == 2) {
+        // a deletion star that lost any of its claims is marked (cd is free
+        // during deletion iterations); the decision is taken in the apply step
+        for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
+            const int32_t x = R[idx];
+            if (a.g.claim[x] != star_key(it, a, (uint32_t)x)) a.g.cd[x] = it.ep;
+        }
+        for (int32_t i = T.rank; i < sc.ng; i += T.size) {
+            if (a.b.err[i] != 0) continue;
+            const int32_t u = a.b.eu[i], v = a.b.ev[i];
+            if (sc.firstidx[u] != 0x7fffffff && star_del_claims(a, sc, u, v) &&
+                a.g.claim[v] != star_key(it, a, (uint32_t)u))
+                a.g.cd[u] = it.ep;
+            if (sc.firstidx[v] != 0x7fffffff && star_del_claims(a, sc, v, u) &&
+                a.g.claim[u] != star_key(it, a, (uint32_t)v))
+                a.g.cd[v] = it.ep;
+        }
+        return;
+    }
+    for (int32_t idx = T.wave(); idx < it.n_r; idx += T.nwaves()) {
+        const int32_t id = R[idx];
+        const unsigned long long key = star_key(it, a, (uint32_t)id);
+        bool lost = false;
+        const int32_t vtx = sc.v0 + id;
+        const int32_t hk = a.g.dec[vtx] - 1;
+        int32_t lo, hi;
+        star_run(sc, id, lo, hi);
+        for (int32_t j = lo + lane(); j < hi; j += WAVE) {
+            int32_t w;
+            if (star_old_edge(a, sc, j, w) && a.g.core[w] <= hk && a.g.claim[w] != key) lost = true;
+        }
+        const bool win = __ballot(lost) == 0ull;
+        if (win && lane() == 0) a.g.matched[vtx] = (int32_t)mstamp;
+        push_agg<int32_t>(a.b.sel, a.b.cap, &c->sel_count, id, win && lane() == 0, &c->overflow);
+        push_agg<int32_t>(a.b.rem[it.cur ^ 1], a.b.cap, &c->rem_count[it.cur ^ 1], id, !win && lane() == 0,
+                          &c->overflow);
+    }
+}
+
+// Selected insertion stars enter with all their edges to existing vertices.
+__device__ __forceinline__ void star_apply_insert(const KArgs &a, const Iter &it, const Team &T) {
+    Ctl *c = a.ctl;
+    const StarCtx &sc = it.sc;
+    const DevGraph &g = a.g;
+    const int32_t n = qlen(&c->sel_count, a.b.cap);
+    for (int32_t idx = T.wave(); idx < n; idx += T.nwaves()) {
+        const int32_t id = a.b.sel[idx];
+        const int32_t v = sc.v0 + id;
+        const int32_t hk = g.dec[v] - 1;
+        int32_t lo, hi;
+        star_run(sc, id, lo, hi);
+        int32_t sd = 0, ne = 0;
+        for (int32_t j0 = lo; j0 < hi; j0 += WAVE) {
+            const int32_t j = j0 + lane();
+            int32_t w = -1;
+            const bool e = j < hi && star_old_edge(a, sc, j, w);
+            bool root = false;
+            if (e) {
+                const int32_t cw = g.core[w];
+                int32_t pv = atomicAdd(&g.len[v], 1);
+                if (pv < g.cap[v]) g.nbr[g.off[v] + pv] = w;
+                else atomicOr(&c->overflow, 2);
+                int32_t pw = atomicAdd(&g.len[w], 1);
+                if (pw < g.cap[w]) g.nbr[g.off[w] + pw] = v;
+                else atomicOr(&c->overflow, 2);
+                if (cw >= hk) ++sd;
+                ++ne;
+                if (cw <= hk) {  // constrained: v supports w's rise
+                    int32_t m = atomicAdd(&g.mcd[w], 1) + 1;
+                    if (m > cw) { g.stamp[w] = it.ep; g.cd[w] = 0; root = true; }
+                }
+            }
+            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], w, root, &c->overflow);
+        }
+        sd = wave_sum(sd);
+        ne = wave_sum(ne);
+        const bool rv = sd > hk;
+        if (lane() == 0) {
+            g.core[v] = hk;
+            g.mcd[v] = sd;
+            g.dec[v] = 0;
+            if (rv) { g.stamp[v] = it.ep; g.cd[v] = 0; }
+            atomicAdd(&c->st_selected, (unsigned long long)ne);
+        }
+        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv && lane() == 0, &c->overflow);
+    }
+}
+
+// Selected deletion stars lose all their remaining edges (the gathered
+// edges carry both slots; err[i] = 1 marks an edge already removed).
+__device__ __forceinline__ void star_apply_delete(const KArgs &a, const Iter &it, const Team &T) {
+    Ctl *c = a.ctl;
+    const StarCtx &sc = it.sc;
+    const DevGraph &g = a.g;
+    const int32_t mstamp = (int32_t)star_mstamp(it, a);
+    // decide: a pending star that lost no claim leaves in this iteration
+    // (always on the whole grid: star steps never run inside one workgroup)
+    const int32_t *R = a.b.rem[it.cur];
+    for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
+        const int32_t x = R[idx];
+        const bool win = g.cd[x] != it.ep;
+        if (win) g.matched[x] = mstamp;
+        push_agg<int32_t>(a.b.sel, a.b.cap, &c->sel_count, x, win, &c->overflow);
+        push_agg<int32_t>(a.b.rem[it.cur ^ 1], a.b.cap, &c->rem_count[it.cur ^ 1], x, !win, &c->overflow);
+    }
+    gbar(a.bar);
+    int32_t ne = 0;
+    for (int32_t i = T.rank; i < sc.ng; i += T.size) {
+        bool pq = false;
+        int32_t q = -1;
+        if (a.b.err[i] == 0) {
+            const int32_t u = a.b.eu[i], v = a.b.ev[i];
+            const bool su = sc.firstidx[u] != 0x7fffffff && g.matched[u] == mstamp;
+            const bool sv = sc.firstidx[v] != 0x7fffffff && g.matched[v] == mstamp;
+            if (su || sv) {
+                g.nbr[a.b.su[i]] = TOMB;
+                g.nbr[a.b.sv[i]] = TOMB;
+                a.b.err[i] = 1;
+                ++ne;
+                const int32_t x = su ? u : v;  // the leaving star (never both: they claim each other)
+                q = su ? v : u;
+                const int32_t cq = g.core[q], cx = g.core[x];
+                if (cq <= cx) {
+                    int32_t m = atomicSub(&g.mcd[q], 1) - 1;
+                    if (m < cq) { g.stamp[q] = it.ep; pq = true; }
+                }
+            }
+        }
+        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], q, pq);
+        push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, q, pq);
+    }
+    ne = wave_sum(ne);
+    if (lane() == 0 && ne) atomicAdd(&c->st_selected, (unsigned long long)ne);
+}
+
+// Deletion stars of this iteration are dead once their edges are gone.
+__device__ __forceinline__ void star_kill(const KArgs &a, const Iter &it, const Team &T) {
+    const int32_t n = qlen(&a.ctl->sel_count, a.b.cap);
+    for (int32_t idx = T.rank; idx < n; idx += T.size) {
+        const int32_t x = a.b.sel[idx];
+        a.g.core[x] = -1;
+        a.g.mcd[x] = 0;
+        a.g.len[x] = 0;
+    }
 }
 
 __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
@@ -827,7 +1129,8 @@ __device__ __forceinline__ int64_t step_work(const KArgs &a, const Iter &it, con
     }
 }
 
-__device__ __forceinline__ bool step_is_local(const KArgs &a, const PC &pc, int64_t work) {
+__device__ __forceinline__ bool step_is_local(const KArgs &a, const Iter &it, const PC &pc, int64_t work) {
+    if (it.sc.mode && (pc.step <= S_APPLY || pc.step == S_CORE)) return false;
     if (pc.step <= S_APPLY) return work <= a.t.local_edges;
     return work <= a.t.local_items;
 }
@@ -845,7 +1148,9 @@ __device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
 __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &pc) {
     switch (pc.step) {
     case S_CLAIM: return PC{S_SELECT, pc.r};
-    case S_SELECT: return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
+    case S_SELECT:
+        if (it.sc.mode) return PC{S_APPLY, 0};
+        return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
     case S_APPLY:
         if (it.ins) {
             if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
@@ -865,16 +1170,27 @@ __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &
 __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Team &T,
                                          long long &scanned) {
     switch (pc.step) {
-    case S_CLAIM: part_claim(a, it, pc.r, T); break;
-    case S_SELECT: part_select(a, it, pc.r, T); break;
+    case S_CLAIM:
+        if (it.sc.mode) star_claim(a, it, T, scanned);
+        else part_claim(a, it, pc.r, T);
+        break;
+    case S_SELECT:
+        if (it.sc.mode) star_select(a, it, T);
+        else part_select(a, it, pc.r, T);
+        break;
     case S_APPLY:
-        if (it.ins) apply_insert(a, it, T);
+        if (it.sc.mode == 1) star_apply_insert(a, it, T);
+        else if (it.sc.mode == 2) star_apply_delete(a, it, T);
+        else if (it.ins) apply_insert(a, it, T);
         else apply_delete(a, it, T);
         break;
     case S_EXPAND: expand_round(a, it, pc.r, T, scanned); break;
     case S_EVICT: evict_round(a, it, pc.r, T, scanned); break;
     case S_PEEL: peel_round(a, it, pc.r, T, scanned); break;
-    case S_CORE: apply_core(a, it, T); break;
+    case S_CORE:
+        apply_core(a, it, T);
+        if (it.sc.mode == 2) star_kill(a, it, T);
+        break;
     case S_MCD: mcd_phase(a, it, T, scanned); break;
     default: break;
     }
@@ -886,7 +1202,7 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
 // in one of two slots (alternating), so a slow workgroup still reading the
 // previous publication is never overtaken.
 __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_iters, int32_t &ep, long long &scanned,
-                              int &pubs) {
+                              int &pubs, const StarCtx &sc = StarCtx{}) {
     Ctl *c = a.ctl;
     int it_n = 0;
     for (; it_n < max_iters; ++it_n) {
@@ -895,12 +1211,13 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
         it.cur = it.ep & 1;
         it.n_r = qlen(&c->rem_count[it.cur], a.b.cap);
         it.ins = ins;
+        it.sc = sc;
         if (it.n_r == 0 || bar_aborted(a.bar)) break;
         PC pc{S_CLAIM, 0};
         bool force = false;  // published by workgroup 0: run pc on the grid
         while (pc.step != S_DONE) {
             int64_t work = step_work(a, it, pc);
-            if (force || !step_is_local(a, pc, work)) {
+            if (force || !step_is_local(a, it, pc, work)) {
                 force = false;
                 const unsigned long long t0 = ph_start();
                 run_step(a, it, pc, grid_team(), scanned);
@@ -922,7 +1239,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                         pc = next_pc(a, it, pc);
                         if (pc.step == S_DONE) break;
                         work = step_work(a, it, pc);
-                        if (!step_is_local(a, pc, work)) break;
+                        if (!step_is_local(a, it, pc, work)) break;
                     }
                     if (threadIdx.x == 0) {
                         c->ipub[slot][0] = pc.step;
@@ -1022,13 +1339,13 @@ __device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t 
     o.steps = c->st_grid_steps + c->st_local_steps;
 }
 
-// One edge batch described by bc (validation through compaction).  Returns
-// 1 when the adjacency pool ran out during the reservation (nothing of the
-// batch was applied), else 0; *status/*fb/*valid/*iters describe the outcome
-// (the same values in every thread).
-__device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &bc, int32_t &ep, long long &scanned,
-                                               int &pubs, int32_t &status, int32_t &fb, int32_t &valid,
-                                               int32_t &iters) {
+// Validation and (insertion) capacity reservation of the edge batch bc.
+// Returns 1 when the adjacency pool ran out during the reservation (nothing
+// of the batch was applied), else 0; status / fb / valid describe the
+// validation (the same values in every thread).  On success the valid item
+// indices are in the remaining list bc.cur.
+__device__ __forceinline__ int prog_prepare(const KArgs &a, const BatchCtx &bc, int32_t &status, int32_t &fb,
+                                            int32_t &valid) {
     Ctl *c = a.ctl;
     const Team G = grid_team();
     unsigned long long t0 = ph_start();
@@ -1050,7 +1367,6 @@ __device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &b
     const int32_t f = ld_rlx(&c->first_bad);
     fb = f == 0x7fffffff ? -1 : f;
     valid = qlen(&c->rem_count[bc.cur], a.b.cap);
-    iters = 0;
     status = 0;
     if (bc.strict && !bc.sub && f != 0x7fffffff) {
         status = a.b.err[f];
@@ -1069,17 +1385,51 @@ __device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &b
         gbar(a.bar);
     }
     ph_stop(c, PH_RESERVE, t0);
-    iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
-    if (!bc.inserting) {
-        t0 = ph_start();
-        del_compact(a, G);
+    return 0;
+}
+
+// After the iterations: compaction (deletion) and the scan statistic.
+__device__ __forceinline__ void prog_finish(const KArgs &a, bool inserting, long long &scanned) {
+    Ctl *c = a.ctl;
+    if (!inserting) {
+        const unsigned long long t0 = ph_start();
+        del_compact(a, grid_team());
         gbar(a.bar);
         ph_stop(c, PH_COMPACT, t0);
     }
     flush_stat(&c->st_scanned, scanned);
     scanned = 0;
     gbar(a.bar);
+}
+
+// One edge batch described by bc (validation through compaction).  Returns
+// 1 on a pool failure (nothing applied), else 0.
+__device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &bc, int32_t &ep, long long &scanned,
+                                               int &pubs, int32_t &status, int32_t &fb, int32_t &valid,
+                                               int32_t &iters) {
+    iters = 0;
+    if (prog_prepare(a, bc, status, fb, valid)) return 1;
+    if (status != 0 || valid == 0) return 0;
+    iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
+    prog_finish(a, bc.inserting, scanned);
     return 0;
+}
+
+// Replace the remaining list of the next iteration (read by the iteration
+// with stamp ep + 1) by the entries fill(i) accepts, i in [0, n).
+template <class F>
+__device__ __forceinline__ void prog_refill(const KArgs &a, int32_t ep, int32_t n, F &&fill) {
+    Ctl *c = a.ctl;
+    const int cur = (ep + 1) & 1;
+    if (gtid() == 0) c->rem_count[cur] = 0;
+    gbar(a.bar);
+    const Team G = grid_team();
+    for (int32_t i = G.rank; i < n; i += G.size) {
+        int32_t val = -1;
+        const bool ok = fill(i, val);
+        push_agg<int32_t>(a.b.rem[cur], a.b.cap, &c->rem_count[cur], val, ok, &c->overflow);
+    }
+    gbar(a.bar);
 }
 
 // Vertex deletion, first part: check the ids (range, dead, repeated: the
@@ -1209,7 +1559,9 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
         const int32_t ng = ld_rlx(&c->vd_tail);
         vdone = ld_rlx(&c->vd_count);
         const int32_t vbad = bad;
-        if (ng > 0) {
+        {
+            // the gathered edges are validated (slot location) and counted
+            // for compaction; then the ids leave as stars
             BatchCtx eb = bc;
             eb.src = pd->gsrc;
             eb.dst = pd->gdst;
@@ -1219,7 +1571,19 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
             eb.hcap = hash_slots(ng);
             eb.strict = 1;
             int32_t efb = -1;
-            prog_edge_batch(a, eb, ep, scanned, pubs, status, efb, valid, iters);
+            if (ng > 0) prog_prepare(a, eb, status, efb, valid);
+            if (status == 0) {
+                prog_refill(a, ep, B.s, [&](int32_t i, int32_t &x) {
+                    x = ids[i];
+                    return x >= 0 && x < n_ids && pd->firstidx[x] == i;
+                });
+                StarCtx sc{};
+                sc.mode = 2;
+                sc.ng = ng;
+                sc.firstidx = pd->firstidx;
+                iters = run_iterations(a, 0, 0x7fffffff, ep, scanned, pubs, sc);
+                if (ng > 0) prog_finish(a, false, scanned);
+            }
         }
         // a deletion needs no reservation, so status can only be 0 here
         vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
@@ -1240,7 +1604,44 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
         }
         gbar(a.bar);
     }
-    if (B.s > 0) {
+    if (B.kind == 2 && B.s > 0) {
+        if (pd->gsrc && B.s <= pd->gcap) {
+            // device copy of the items: the star passes read them repeatedly
+            for (int32_t i = G.rank; i < B.s; i += G.size) {
+                pd->gsrc[i] = bc.src[i];
+                pd->gdst[i] = bc.dst[i];
+            }
+            gbar(a.bar);
+            bc.src = pd->gsrc;
+            bc.dst = pd->gdst;
+        }
+        if (prog_prepare(a, bc, status, fb, valid)) return 1;
+        if (status == 0 && valid > 0) {
+            StarCtx sc{};
+            sc.mode = 1;
+            sc.v0 = B.v0;
+            sc.nv = B.nv;
+            sc.s = B.s;
+            sc.src = bc.src;
+            sc.dst = bc.dst;
+            // stars: the new vertices with at least one item
+            prog_refill(a, ep, B.nv, [&](int32_t i, int32_t &x) {
+                int32_t lo, hi;
+                star_run(sc, i, lo, hi);
+                x = i;
+                return hi > lo;
+            });
+            iters = run_iterations(a, 1, 0x7fffffff, ep, scanned, pubs, sc);
+            // edges between two new vertices: ordinary iterations
+            prog_refill(a, ep, B.s, [&](int32_t j, int32_t &x) {
+                const int32_t u = bc.src[j], w = bc.dst[j];
+                x = j;
+                return a.b.err[j] == 0 && u >= B.v0 && u < B.v0 + B.nv && w >= B.v0 && w < B.v0 + B.nv;
+            });
+            iters += run_iterations(a, 1, 0x7fffffff, ep, scanned, pubs);
+            prog_finish(a, true, scanned);
+        }
+    } else if (B.s > 0) {
         if (prog_edge_batch(a, bc, ep, scanned, pubs, status, fb, valid, iters)) return 1;
     }
     if (B.kind == 2) {
