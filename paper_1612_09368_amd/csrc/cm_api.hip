@@ -607,6 +607,121 @@ int launch_program(cm_graph *g, const KArgs &a) {
     return 1;
 }
 
+// Run the batch program pb (items in ds / dd [/ dsub], device memory) in
+// persistent launches: one launch, or more when the adjacency pool must be
+// repacked (the launch stops before mutating the batch that ran out; the
+// host repacks and relaunches from there).  out receives every batch's
+// outcome.
+void program_execute(cm_graph *g, const std::vector<ProgBatch> &pb, const int32_t *ds, const int32_t *dd,
+                     const int32_t *dsub, bool strict, std::vector<ProgOut> &out, int *used_graph_out,
+                     double *kms_out, int *launches_out) {
+    hipStream_t st = g->stream;
+    const int32_t nb = (int32_t)pb.size();
+    out.assign((size_t)nb, ProgOut{});
+    if (nb > g->prog_cap) {
+        dev_free(g->d_pbatch);
+        dev_free(g->d_pout);
+        int32_t c = std::max(nb, 64);
+        dev_alloc(g, &g->d_pbatch, c);
+        dev_alloc(g, &g->d_pout, c);
+        g->prog_cap = c;
+    }
+    HIPCHK(hipMemcpyAsync(g->d_pbatch, pb.data(), sizeof(ProgBatch) * (size_t)nb, hipMemcpyHostToDevice, st));
+    int32_t first = 0;
+    int used_graph = 0;
+    double kms = 0.0;
+    int launches = 0;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        ProgDesc *hd = g->h_prog;
+        std::memset(hd, 0, sizeof(ProgDesc));
+        hd->gsrc = g->src_buf;
+        hd->gdst = g->dst_buf;
+        hd->gcap = g->batch_cap;
+        hd->firstidx = g->firstidx;
+        hd->batches = g->d_pbatch;
+        hd->out = g->d_pout;
+        hd->src = ds;
+        hd->dst = dd;
+        hd->sub = dsub;
+        hd->sub_bad = dsub ? g->d_sub_bad : nullptr;
+        hd->nb = nb;
+        hd->first = first;
+        hd->strict = strict ? 1 : 0;
+        hd->bstamp0 = g->bstamp + 2;
+        hd->stop = first;
+        hd->pool_fail = 0;
+        g->bstamp += 2 * (nb - first) + 2;
+        HIPCHK(hipMemcpyAsync(g->d_prog, hd, sizeof(ProgDesc), hipMemcpyHostToDevice, st));
+        KArgs a = make_args(g);
+        a.prog = g->d_prog;
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
+        used_graph |= launch_program(g, a);
+        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
+        ++launches;
+        HIPCHK(hipMemcpyAsync(g->h_prog, g->d_prog, sizeof(ProgDesc), hipMemcpyDeviceToHost, st));
+        sync_ctl(g);
+        check_abort(g);
+        check_overflow(g);
+        if (g->cfg.timing) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+            kms += ms;
+        }
+        g->epoch = g->hctl->epoch;
+        int32_t stop = g->h_prog->stop;
+        if (stop > first)
+            HIPCHK(hipMemcpy(out.data() + first, g->d_pout + first, sizeof(ProgOut) * (size_t)(stop - first),
+                             hipMemcpyDeviceToHost));
+        if (!g->h_prog->pool_fail) {
+            if (stop != nb) {
+                g->poisoned = true;
+                g->err = "batch program stopped early";
+                throw Fail{CM_E_INTERNAL};
+            }
+            break;
+        }
+        // adjacency pool exhausted at batch `stop`: repack with room, resume there
+        int64_t pending = 0;
+        for (int32_t j = stop; j < nb; ++j)
+            if (pb[j].kind == 0 || pb[j].kind == 2) pending += pb[j].s;
+        repack(g, 4 * pending + g->g.pool_size / 2);
+        first = stop;
+        if (attempt == 7) {
+            g->err = "adjacency pool could not be grown";
+            throw Fail{CM_E_NOMEM};
+        }
+    }
+    *used_graph_out = used_graph;
+    *kms_out = kms;
+    *launches_out = launches;
+}
+
+// Outcome of one program batch as the one-call statistics.
+void stats_from_out(cm_graph *g, const ProgOut &o, int64_t items, int launches, double kms, cm_batch_stats *r) {
+    if (!r) return;
+    r->status = o.status;
+    r->iterations = o.iterations;
+    r->first_bad = o.first_bad;
+    r->applied = o.valid;
+    r->dropped = o.status == 0 ? items - o.valid : 0;
+    r->remaining_sum = (int64_t)o.remaining;
+    r->candidates = (int64_t)o.candidates;
+    r->evicted = (int64_t)o.evicted;
+    r->changed = (int64_t)o.changed;
+    r->scanned = (int64_t)o.scanned;
+    r->rounds = (int64_t)o.rounds;
+    r->local_steps = (int64_t)o.steps;
+    Ctl tmp{};
+    tmp.st_remaining = o.remaining;
+    tmp.st_selected = o.selected;
+    tmp.st_scanned = o.scanned;
+    tmp.st_candidates = o.candidates;
+    tmp.st_changed = o.changed;
+    r->alg_bytes = alg_bytes(tmp, g->tune.rounds);
+    r->launches = launches;
+    r->kernel_ms = kms;
+}
+
 template <class T>
 void grow_dev(cm_graph *g, T *&p, int64_t &cap_io, int64_t need) {
     if (need <= cap_io && p) return;
@@ -969,6 +1084,7 @@ int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t
     if (c < 0 || (c > 0 && !off)) return finish(g, CM_E_ARG, stats, t0);
     int32_t first = -1;
     bool created = false;
+    bool counted = false;
     try {
         require_ready(g, true);
         hipStream_t st = g->stream;
@@ -1022,10 +1138,34 @@ int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t
             g->b.dst_in = g->dst_buf;
         }
         if (own_off) dev_free(doff);
-        g->n_alive += c;
-        if (total > 0) {
-            int64_t dropped = 0;
-            edge_batch(g, total, true, stats, &dropped, false, false);
+        if (total > 0 && g->cfg.mode == CM_MODE_PERSISTENT) {
+            // one persistent launch: the new vertices enter as stars
+            std::vector<ProgBatch> pb(1);
+            pb[0].off = 0;
+            pb[0].s = (int32_t)total;
+            pb[0].kind = 2;
+            pb[0].v0 = first;
+            pb[0].nv = c;
+            pb[0].n_ids = first + c;
+            std::vector<ProgOut> out;
+            int used = 0, launches = 0;
+            double kms = 0.0;
+            program_execute(g, pb, g->src_buf, g->dst_buf, nullptr, g->cfg.strict != 0, out, &used, &kms, &launches);
+            stats_from_out(g, out[0], total, launches, kms, stats);
+            if (out[0].status != 0) {
+                g->err = std::string("invalid neighbour item ") + std::to_string(out[0].first_bad) + ": " +
+                         cm_strerror(out[0].status);
+                throw Fail{out[0].status};
+            }
+            g->m += out[0].valid;
+            g->n_alive += c;
+        } else {
+            g->n_alive += c;
+            counted = true;
+            if (total > 0) {
+                int64_t dropped = 0;
+                edge_batch(g, total, true, stats, &dropped, false, false);
+            }
         }
         created = false;
     } catch (const Fail &f) {
@@ -1034,7 +1174,7 @@ int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t
             (void)vins_revert(a, first, c, g->stream);
             (void)hipStreamSynchronize(g->stream);
             g->g.n_ids = first;
-            g->n_alive -= c;
+            if (counted) g->n_alive -= c;
         }
         return finish(g, f.code, stats, t0);
     }
@@ -1106,6 +1246,35 @@ int cm_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int on_device
             HIPCHK(hipMemcpyAsync(g->hu64, g->u64_scratch, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             total = (int64_t)g->hu64[1];
+        }
+        if (g->cfg.mode == CM_MODE_PERSISTENT && c > 0) {
+            // one persistent launch: the ids leave as stars
+            ensure_batch(g, std::max<int64_t>(std::max<int64_t>(total, c), 1));
+            std::vector<ProgBatch> pb(1);
+            pb[0].off = 0;
+            pb[0].s = c;
+            pb[0].kind = 3;
+            pb[0].n_ids = g->g.n_ids;
+            std::vector<ProgOut> out;
+            int used = 0, launches = 0;
+            double kms = 0.0;
+            const int64_t fb_host = stats ? stats->first_bad : -1;
+            const int64_t dropped_host = stats ? stats->dropped : 0;
+            program_execute(g, pb, dids, nullptr, nullptr, true, out, &used, &kms, &launches);
+            stats_from_out(g, out[0], total, launches, kms, stats);
+            if (stats) {
+                stats->first_bad = fb_host;
+                stats->dropped = dropped_host;
+            }
+            if (out[0].status != 0) {
+                if (own) dev_free(dids);
+                g->err = std::string("vertex deletion failed: ") + cm_strerror(out[0].status);
+                return finish(g, out[0].status, stats, t0);
+            }
+            g->m -= out[0].valid;
+            if (own) dev_free(dids);
+            g->n_alive -= c;
+            return finish(g, CM_OK, stats, t0);
         }
         if (total > 0) {
             ensure_batch(g, total);
@@ -1732,86 +1901,17 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
             }
             g->b.sub_in = nullptr;
         } else {
-            if (nb > g->prog_cap) {
-                dev_free(g->d_pbatch);
-                dev_free(g->d_pout);
-                int32_t c = std::max(nb, 64);
-                dev_alloc(g, &g->d_pbatch, c);
-                dev_alloc(g, &g->d_pout, c);
-                g->prog_cap = c;
-            }
             std::vector<ProgBatch> pb(nb);
             for (int32_t j = 0; j < nb; ++j) {
                 pb[j].off = offsets[j];
                 pb[j].s = (int32_t)(offsets[j + 1] - offsets[j]);
                 pb[j].kind = kinds[j];
             }
-            HIPCHK(hipMemcpyAsync(g->d_pbatch, pb.data(), sizeof(ProgBatch) * (size_t)nb, hipMemcpyHostToDevice, st));
             std::vector<ProgOut> out(nb);
-            int32_t first = 0;
             int used_graph = 0;
             double kms = 0.0;
             int launches = 0;
-            for (int attempt = 0; attempt < 8; ++attempt) {
-                ProgDesc *hd = g->h_prog;
-                std::memset(hd, 0, sizeof(ProgDesc));
-                hd->gsrc = g->src_buf;
-                hd->gdst = g->dst_buf;
-                hd->gcap = g->batch_cap;
-                hd->firstidx = g->firstidx;
-                hd->batches = g->d_pbatch;
-                hd->out = g->d_pout;
-                hd->src = ds;
-                hd->dst = dd;
-                hd->sub = dsub;
-                hd->sub_bad = dsub ? g->d_sub_bad : nullptr;
-                hd->nb = nb;
-                hd->first = first;
-                hd->strict = strict ? 1 : 0;
-                hd->bstamp0 = g->bstamp + 2;
-                hd->stop = first;
-                hd->pool_fail = 0;
-                g->bstamp += 2 * (nb - first) + 2;
-                HIPCHK(hipMemcpyAsync(g->d_prog, hd, sizeof(ProgDesc), hipMemcpyHostToDevice, st));
-                KArgs a = make_args(g);
-                a.prog = g->d_prog;
-                if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
-                used_graph |= launch_program(g, a);
-                if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
-                ++launches;
-                HIPCHK(hipMemcpyAsync(g->h_prog, g->d_prog, sizeof(ProgDesc), hipMemcpyDeviceToHost, st));
-                sync_ctl(g);
-                check_abort(g);
-                check_overflow(g);
-                if (g->cfg.timing) {
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-                    kms += ms;
-                }
-                g->epoch = g->hctl->epoch;
-                int32_t stop = g->h_prog->stop;
-                if (stop > first)
-                    HIPCHK(hipMemcpy(out.data() + first, g->d_pout + first, sizeof(ProgOut) * (size_t)(stop - first),
-                                     hipMemcpyDeviceToHost));
-                if (!g->h_prog->pool_fail) {
-                    if (stop != nb) {
-                        g->poisoned = true;
-                        g->err = "batch program stopped early";
-                        throw Fail{CM_E_INTERNAL};
-                    }
-                    break;
-                }
-                // adjacency pool exhausted at batch `stop`: repack with room, resume there
-                int64_t pending = 0;
-                for (int32_t j = stop; j < nb; ++j)
-                    if (kinds[j] == CM_BATCH_INSERT) pending += offsets[j + 1] - offsets[j];
-                repack(g, 4 * pending + g->g.pool_size / 2);
-                first = stop;
-                if (attempt == 7) {
-                    g->err = "adjacency pool could not be grown";
-                    throw Fail{CM_E_NOMEM};
-                }
-            }
+            program_execute(g, pb, ds, dd, dsub, strict, out, &used_graph, &kms, &launches);
             for (int32_t j = 0; j < nb; ++j) {
                 const ProgOut &o = out[j];
                 if (o.status == 0) g->m += kinds[j] == CM_BATCH_INSERT ? o.valid : -(int64_t)o.valid;

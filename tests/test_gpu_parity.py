@@ -269,13 +269,16 @@ def test_filter_mode_drops_invalid(cm, dev, oracle_mod):
         check_state(g, ref, "filter insert")
 
 
-def test_vertex_ops(cm, dev, oracle_mod):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_vertex_ops(cm, dev, oracle_mod, mode):
+    # mode 0: the Introduction's reduction (edges through superior edge sets);
+    # mode 1: one persistent launch, vertices entering / leaving as stars
     rng = graphgen.rng_for("vops")
     n = 3000
     s, d = graphgen.chung_lu_graph(n, 15_000, 2.2, 300.0, rng)
     ref = oracle_mod.DynamicGraph(n, s, d)
     es = graphgen.EdgeSet(s, d)
-    with new_graph(cm, n, s, d, dev, vertex_capacity=0) as g:
+    with new_graph(cm, n, s, d, dev, vertex_capacity=0, mode=mode) as g:
         # insert 200 vertices with power-law degrees, neighbours degree-weighted
         degs = graphgen.power_law_degrees(200, 1, 60, 2.1, rng)
         off, nb = graphgen.vertex_insert_payload(n, 200, degs, es, rng)
@@ -383,3 +386,37 @@ def test_root_list_grows_during_apply(cm, dev, oracle_mod, mode):
         g.delete_edges(_t(ins_b, dev), _t(ins_a, dev))
         ref.delete_edges(ins_b, ins_a)
         check_state(g, ref, "after delete")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_vertex_ops_dense(cm, dev, oracle_mod, mode):
+    """Many new vertices of high degree sharing neighbours, then deletions
+    of the highest-degree vertices (adjacent to each other): cores after
+    every operation equal the oracle's in both forms."""
+    rng = graphgen.rng_for("vops-dense")
+    n = 4000
+    s, d = graphgen.chung_lu_graph(n, 40_000, 2.1, 800.0, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    with new_graph(cm, n, s, d, dev, mode=mode) as g:
+        nid = n
+        for step in range(4):
+            degs = graphgen.power_law_degrees(300, 5, 400, 1.6, rng)
+            off, nb = graphgen.vertex_insert_payload(nid, 300, degs, es, rng)
+            first, _ = g.insert_vertices(_t(off, dev), _t(nb, dev))
+            assert ref.insert_vertices(off, nb)[0] == 0
+            own = np.repeat(np.arange(nid, nid + 300), np.diff(off))
+            es.insert(own, nb)
+            nid += 300
+            check_state(g, ref, f"dense vertex insert {step}")
+            cores = g.cores()
+            deg = np.bincount(np.concatenate(es.edges()), minlength=nid)
+            top = np.argsort(-deg)[:60]
+            top = top[cores[top] >= 0][:40].astype(np.int32)
+            g.delete_vertices(_t(top, dev))
+            assert ref.delete_vertices(top)[0] == 0
+            ks = graphgen.keys_of(*es.edges())
+            lo, hi = ks >> 32, ks & 0xFFFFFFFF
+            hit = np.isin(lo, top) | np.isin(hi, top)
+            es = graphgen.EdgeSet(*graphgen.split_keys(ks[~hit]))
+            check_state(g, ref, f"dense vertex delete {step}")

@@ -224,3 +224,76 @@ def test_dynamic_graph_validation(oracle_mod):
     assert st == E.OK and g.cores()[1] == -1 and g.num_edges() == 1
     st, fb, first = g.insert_vertices(np.array([0, 2]), np.array([3, 4]))
     assert st == E.OK and first == 5 and g.cores()[5] == 2
+
+
+def _hindex(vals):
+    vals = sorted(vals, reverse=True)
+    h = 0
+    for i, x in enumerate(vals):
+        if x >= i + 1:
+            h = i + 1
+    return h
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_vertex_star_bounds(oracle_mod, seed):
+    """The vertex-star step used for one-pass vertex operations, checked
+    against Batagelj-Zaversnik on random graphs: (a) new vertices inserted
+    with all their edges, several per step, such that every existing vertex
+    is constrained (core <= hK of the star) by at most one of them: every
+    existing vertex ends at its old core or one more, every star at hK or
+    hK + 1, where hK is the h-index of the neighbours' old cores; (b) deleted
+    vertices removed with all their edges, pairwise non-adjacent, every other
+    vertex constrained (core <= the star's core) by at most one of them:
+    every other vertex ends at its old core or one less."""
+    rng = np.random.default_rng(1000 + seed)
+    for trial in range(40):
+        n = int(rng.integers(8, 40))
+        m = int(rng.integers(n, 4 * n))
+        s, d = graphgen.er_graph(n, min(m, n * (n - 1) // 2), rng)
+        K = oracle_mod.bz_cores(n, s, d)
+        # (a) insertion stars, greedily admitted under the one-constraint rule
+        c = int(rng.integers(1, 6))
+        taken = set()
+        stars = []
+        for i in range(c):
+            nb = sorted(set(rng.integers(0, n, int(rng.integers(1, n))).tolist()))
+            hk = _hindex([K[w] for w in nb])
+            cons = {w for w in nb if K[w] <= hk}
+            if cons & taken:
+                continue
+            taken |= cons
+            stars.append((nb, hk))
+        ss, dd = list(s), list(d)
+        for j, (nb, _) in enumerate(stars):
+            for w in nb:
+                ss.append(w)
+                dd.append(n + j)
+        C = oracle_mod.bz_cores(n + len(stars), np.array(ss), np.array(dd))
+        assert all(K[u] <= C[u] <= K[u] + 1 for u in range(n)), (seed, trial)
+        for j, (nb, hk) in enumerate(stars):
+            assert hk <= C[n + j] <= hk + 1, (seed, trial, j)
+        # (b) deletion stars
+        order = rng.permutation(n)
+        adj = [set() for _ in range(n)]
+        for a, b in zip(s, d):
+            adj[a].add(b)
+            adj[b].add(a)
+        chosen, used = [], set()
+        for x in order[: int(rng.integers(1, 6))]:
+            x = int(x)
+            if any(y in adj[x] for y in chosen):
+                continue
+            cons = {w for w in adj[x] if K[w] <= K[x]}
+            if cons & used:
+                continue
+            used |= cons
+            chosen.append(x)
+        dead = set(chosen)
+        keep = [(a, b) for a, b in zip(s, d) if a not in dead and b not in dead]
+        ks = np.array([a for a, _ in keep], dtype=np.int64)
+        kd = np.array([b for _, b in keep], dtype=np.int64)
+        C2 = oracle_mod.bz_cores(n, ks, kd)
+        for u in range(n):
+            if u not in dead:
+                assert K[u] - 1 <= C2[u] <= K[u], (seed, trial, u)
