@@ -89,6 +89,8 @@ typedef struct cm_config {
     int32_t timing;             /* 1 = time each maintenance launch with HIP events */
     int32_t use_graph;          /* 1 = cm_run_batches replays its persistent launch from an
                                    instantiated hipGraph (rebuilt when buffers move) */
+    int32_t async_steps;        /* 1 = each expansion / eviction / peel cascade runs as one
+                                   work-queue step instead of one grid-wide step per round */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 

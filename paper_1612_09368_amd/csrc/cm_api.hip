@@ -279,16 +279,30 @@ void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
 void alloc_chunk_queues(cm_graph *g) {
     int64_t h = (int64_t)g->g.n_cap + g->g.pool_size / std::max(1, g->tune.chunk) + 1024;
     if (h > INT_MAX) h = INT_MAX;
-    if (h <= g->q.hcap) return;
-    for (int i = 0; i < 2; ++i) {
-        dev_free(g->q.fh[i]); dev_free(g->q.fx[i]); dev_free(g->q.eh[i]);
-        dev_alloc(g, &g->q.fh[i], h);
-        dev_alloc(g, &g->q.fx[i], h);
-        dev_alloc(g, &g->q.eh[i], h);
+    if (h > g->q.hcap) {
+        for (int i = 0; i < 2; ++i) {
+            dev_free(g->q.fh[i]); dev_free(g->q.fx[i]); dev_free(g->q.eh[i]);
+            dev_alloc(g, &g->q.fh[i], h);
+            dev_alloc(g, &g->q.fx[i], h);
+            dev_alloc(g, &g->q.eh[i], h);
+        }
+        dev_free(g->q.chh);
+        dev_alloc(g, &g->q.chh, h);
+        g->q.hcap = (int32_t)h;
     }
-    dev_free(g->q.chh);
-    dev_alloc(g, &g->q.chh, h);
-    g->q.hcap = (int32_t)h;
+    if (g->tune.async_steps) {
+        // an asynchronous step holds every item it creates: vertices (each at
+        // most once) plus two chunk items per chunk of a claimed list
+        const int64_t ac = std::min<int64_t>((int64_t)g->g.n_cap + 2 * (int64_t)g->q.hcap, INT_MAX);
+        if (ac > g->q.acap) {
+            for (int i = 0; i < 2; ++i) {
+                dev_free(g->q.aq[i]);
+                dev_alloc(g, &g->q.aq[i], ac);
+                HIPCHK(fill_u64(g->q.aq[i], ~0ull, ac, g->stream));
+            }
+            g->q.acap = (int32_t)ac;
+        }
+    }
 }
 
 void ensure_vertex_capacity(cm_graph *g, int64_t need) {
@@ -773,6 +787,7 @@ void release_all(cm_graph *g) {
         dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.fx[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
     }
     dev_free(q.cand); dev_free(q.chg); dev_free(q.chh); dev_free(q.touched);
+    dev_free(q.aq[0]); dev_free(q.aq[1]);
     dev_free(g->d_pbatch); dev_free(g->d_pout); dev_free(g->d_isrc); dev_free(g->d_idst);
     dev_free(g->d_isub); dev_free(g->d_sub_bad);
     g->prog_cap = 0; g->items_cap = 0; g->sub_cap = 0;
@@ -852,6 +867,7 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 8192;
         g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 128;
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
+        g->tune.async_steps = g->cfg.async_steps ? 1 : 0;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
         HIPCHK(coop_occupancy(0, &bpc_m));

@@ -86,6 +86,9 @@ struct Ctl {
     int32_t vd_tail;              // gathered edges
     int32_t vd_bad;               // smallest invalid id index
     int32_t vd_count;             // valid ids
+    int32_t aq_tail[2];           // asynchronous queues: slots handed out
+    int32_t aq_head[2];           //   slots taken by consumers
+    int32_t aq_pend[2];           //   items pushed and not finished
     int32_t sv_decision;          // serving: decision of the waiting thread
     ProgBatch sv_batch;           // serving: descriptor of the current batch
 };
@@ -173,6 +176,8 @@ struct DevQueues {
     int32_t *chg;
     int64_t *chh;
     int32_t *touched;
+    int32_t acap;                 // capacity of the asynchronous work queues
+    unsigned long long *aq[2];    // asynchronous steps: 0 expansion, 1 eviction / peel
 };
 
 struct Tune {
@@ -183,7 +188,7 @@ struct Tune {
     int32_t local_edges; // partition / apply steps up to this many edges run in one workgroup
     int32_t local_items; // frontier steps up to this many items run in one workgroup
     int32_t local_work;  // ... and only if their lists hold at most this many entries
-    int32_t pad;
+    int32_t async_steps; // cascades as work-queue steps
 };
 
 constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels

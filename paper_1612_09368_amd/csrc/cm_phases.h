@@ -301,6 +301,134 @@ __device__ __forceinline__ bool matched_before(uint32_t m, int32_t ep, int round
     return m >= lo && m <= hi;
 }
 
+// ===========================================================================
+// Asynchronous traversal steps.
+//
+// The expansion, eviction and peel cascades are closures: every vertex is
+// claimed, evicted or peeled exactly once through an atomic (stamp exchange,
+// counter crossing), so their result does not depend on the order in which
+// vertices are processed.  Instead of one grid barrier per frontier round,
+// an asynchronous step runs a whole cascade through one work queue: waves
+// take slots from the queue head, wait for the producer to fill them, process
+// the items and push the items they create.  A counter of items pushed but
+// not finished (incremented before an item becomes visible, decremented after
+// its children were pushed) reaching zero ends the step for every wave.
+// State that waves exchange inside the step goes through agent-scope
+// atomics, or through stores that complete (wave drain) before the item
+// that announces them is published.  Queue 0 carries expansion items, queue
+// 1 eviction / peel items (seeded by the step before).
+// ===========================================================================
+constexpr unsigned long long AQ_EMPTY = ~0ull;
+enum AqType : int { AQ_V = 0, AQ_CNT = 1, AQ_EXP = 2, AQ_CH = 3 };
+
+__device__ __forceinline__ unsigned long long aq_item(int type, int32_t v, int32_t c) {
+    return ((unsigned long long)type << 62) | ((unsigned long long)((uint32_t)c & 0x3FFFFFFFu) << 32) |
+           (unsigned long long)(uint32_t)v;
+}
+__device__ __forceinline__ int aq_type(unsigned long long it) { return (int)(it >> 62); }
+__device__ __forceinline__ int32_t aq_v(unsigned long long it) { return (int32_t)(uint32_t)it; }
+__device__ __forceinline__ int32_t aq_c(unsigned long long it) { return (int32_t)((it >> 32) & 0x3FFFFFFFu); }
+
+// Wave-aggregated push of one item per lane with pred into queue qi.
+__device__ __forceinline__ void apush(const KArgs &a, int qi, unsigned long long item, bool pred) {
+    Ctl *c = a.ctl;
+    wave_drain();  // stores this item announces (counter resets) are complete first
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    const int leader = __ffsll((long long)m) - 1;
+    const int cnt = __popcll(m);
+    const int rank = __popcll(m & ((1ull << lane()) - 1ull));
+    int32_t base = 0;
+    if (lane() == leader) {
+        atomicAdd(&c->aq_pend[qi], cnt);
+        base = atomicAdd(&c->aq_tail[qi], cnt);
+        wave_drain();  // the pending count is raised before any of the items is visible
+    }
+    base = __shfl(base, leader);
+    if (pred) {
+        const int32_t pos = base + rank;
+        if (pos < a.q.acap) __hip_atomic_store(&a.q.aq[qi][pos], item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else atomicOr(&c->overflow, 4);
+    }
+}
+
+// Per-lane push of the nch chunk items of v (lanes with pred; any lanes).
+__device__ __forceinline__ void apush_chunks(const KArgs &a, int qi, int type, int32_t v, int32_t nch, bool pred) {
+    Ctl *c = a.ctl;
+    wave_drain();
+    int32_t base = 0;
+    if (pred) {
+        atomicAdd(&c->aq_pend[qi], nch);
+        base = atomicAdd(&c->aq_tail[qi], nch);
+    }
+    wave_drain();
+    if (pred) {
+        for (int32_t q = 0; q < nch; ++q) {
+            const int32_t pos = base + q;
+            if (pos < a.q.acap)
+                __hip_atomic_store(&a.q.aq[qi][pos], aq_item(type, v, q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else atomicOr(&c->overflow, 4);
+        }
+    }
+}
+
+// Route a vertex to queue qi: as one item, or as chunk items of `ctype` when
+// its list is longer than large_deg.
+__device__ __forceinline__ void apush_vertex(const KArgs &a, int qi, int ctype, int32_t w, bool pred) {
+    const int32_t L = pred ? a.g.len[w] : 0;
+    const bool big = pred && L > a.t.large_deg;
+    apush(a, qi, aq_item(AQ_V, w, 0), pred && !big);
+    if (__ballot(big)) apush_chunks(a, qi, ctype, w, nchunks(L, a.t.chunk), big);
+}
+
+// Run queue qi to exhaustion; proc(item, fresh) is called by the whole wave
+// with the lanes holding a new item marked fresh.
+template <class P>
+__device__ __forceinline__ void aq_run(const KArgs &a, int qi, P &&proc) {
+    Ctl *c = a.ctl;
+    unsigned long long *Q = a.q.aq[qi];
+    const int32_t cap = a.q.acap;
+    constexpr int G = 16;
+    unsigned polls = 0;
+    for (;;) {
+        int32_t base = 0;
+        if (lane() == 0) base = atomicAdd(&c->aq_head[qi], G);
+        base = __shfl(base, 0);
+        const int32_t idx = base + lane();
+        bool waiting = lane() < G && idx < cap;
+        bool done = false;
+        while (__ballot(waiting) != 0ull || base >= cap) {
+            unsigned long long item = AQ_EMPTY;
+            bool fresh = false;
+            if (waiting) {
+                item = __hip_atomic_load(&Q[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (item != AQ_EMPTY) {
+                    fresh = true;
+                    waiting = false;
+                    __hip_atomic_store(&Q[idx], AQ_EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            const unsigned long long fm = __ballot(fresh);
+            if (fm) {
+                proc(item, fresh);
+                wave_drain();  // children pushed (pending raised) before this item counts as done
+                if (lane() == 0) atomicSub(&c->aq_pend[qi], __popcll(fm));
+                polls = 0;
+                continue;
+            }
+            if (ld_rlx(&c->aq_pend[qi]) == 0 || bar_aborted(a.bar)) { done = true; break; }
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1u << 24)) {  // bounded: a lost item is a bug, not a hang
+                if (lane() == 0) __hip_atomic_store(&a.bar->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                done = true;
+                break;
+            }
+        }
+        if (done) break;
+        if (ld_rlx(&c->aq_pend[qi]) == 0) break;
+    }
+}
+
 // Selection of a superior edge set from the remaining edges (Algorithms 1-2
 // and 5; Definition of the k-superior edge set).  An edge <u,v> has core
 // number k = min(core u, core v); the endpoints with core k are its
@@ -321,6 +449,7 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
         c->touched_count = 0; c->changed_count = 0;
+        for (int j = 0; j < 2; ++j) { c->aq_tail[j] = 0; c->aq_head[j] = 0; c->aq_pend[j] = 0; }
         c->st_iters += 1;
         c->st_remaining += (unsigned long long)it.n_r;
     }
@@ -403,8 +532,13 @@ __device__ __forceinline__ void apply_insert(const KArgs &a, const Iter &it, con
         // may still be appending to the same list in this step, so a chunk
         // count taken now could be stale.  The first expansion round splits
         // long root lists into chunks once lengths are final.
-        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
-        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv, &c->overflow);
+        if (a.t.async_steps) {
+            apush(a, 0, aq_item(AQ_V, u, 0), ru);
+            apush(a, 0, aq_item(AQ_V, v, 0), rv);
+        } else {
+            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
+            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv, &c->overflow);
+        }
     }
 }
 
@@ -431,8 +565,13 @@ __device__ __forceinline__ void apply_delete(const KArgs &a, const Iter &it, con
             int32_t m = atomicSub(&a.g.mcd[v], 1) - 1;
             if (m < k) { a.g.stamp[v] = it.ep; pv = true; }
         }
-        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], u, pu);
-        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, pv);
+        if (a.t.async_steps) {
+            apush_vertex(a, 1, AQ_CH, u, pu);
+            apush_vertex(a, 1, AQ_CH, v, pv);
+        } else {
+            push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], u, pu);
+            push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, pv);
+        }
         push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, u, pu);
         push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, pv);
     }
@@ -548,6 +687,7 @@ __device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
         c->touched_count = 0; c->changed_count = 0;
+        for (int j = 0; j < 2; ++j) { c->aq_tail[j] = 0; c->aq_head[j] = 0; c->aq_pend[j] = 0; }
         c->st_iters += 1;
         c->st_remaining += (unsigned long long)it.n_r;
     }
@@ -665,7 +805,8 @@ __device__ __forceinline__ void star_apply_insert(const KArgs &a, const Iter &it
                     if (m > cw) { g.stamp[w] = it.ep; g.cd[w] = 0; root = true; }
                 }
             }
-            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], w, root, &c->overflow);
+            if (a.t.async_steps) apush(a, 0, aq_item(AQ_V, w, 0), root);
+            else push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], w, root, &c->overflow);
         }
         sd = wave_sum(sd);
         ne = wave_sum(ne);
@@ -677,7 +818,8 @@ __device__ __forceinline__ void star_apply_insert(const KArgs &a, const Iter &it
             if (rv) { g.stamp[v] = it.ep; g.cd[v] = 0; }
             atomicAdd(&c->st_selected, (unsigned long long)ne);
         }
-        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv && lane() == 0, &c->overflow);
+        if (a.t.async_steps) apush(a, 0, aq_item(AQ_V, v, 0), rv && lane() == 0);
+        else push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv && lane() == 0, &c->overflow);
     }
 }
 
@@ -721,7 +863,8 @@ __device__ __forceinline__ void star_apply_delete(const KArgs &a, const Iter &it
                 }
             }
         }
-        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], q, pq);
+        if (a.t.async_steps) apush_vertex(a, 1, AQ_CH, q, pq);
+        else push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], q, pq);
         push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, q, pq);
     }
     ne = wave_sum(ne);
@@ -737,6 +880,225 @@ __device__ __forceinline__ void star_kill(const KArgs &a, const Iter &it, const 
         a.g.mcd[x] = 0;
         a.g.len[x] = 0;
     }
+}
+
+// Asynchronous expansion (Algorithm 3 closure) of the roots pushed into
+// queue 0 by the apply step; evictions go to queue 1.
+__device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, long long &scanned) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    const int32_t ep = it.ep;
+    if (gtid() == 0) c->st_rounds += 1;
+    auto claim = [&](int32_t w, int32_t k) -> bool {
+        if (w < 0) return false;
+        if (g.core[w] != k || g.mcd[w] <= k) return false;
+        if (ld_rlx(&g.stamp[w]) == ep) return false;
+        if (atomicExch(&g.stamp[w], ep) == ep) return false;
+        __hip_atomic_store(&g.cd[w], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    };
+    auto expand_list = [&](int32_t v, int32_t lo, int32_t hi, int32_t k) {  // whole wave
+        wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { apush_vertex(a, 0, AQ_CNT, w, claim(w, k)); });
+    };
+    aq_run(a, 0, [&](unsigned long long item, bool fresh) {
+        const int type = aq_type(item);
+        const int32_t v = aq_v(item);
+        const int32_t L = fresh && type == AQ_V ? g.len[v] : 0;
+        // short lists: one lane each
+        const bool lanev = fresh && type == AQ_V && L <= a.t.small_deg;
+        int32_t k = lanev ? g.core[v] : 0;
+        int32_t pcd = 0;
+        if (lanev) {
+            const int32_t *p = g.nbr + g.off[v];
+            for (int32_t s = 0; s < L; ++s) {
+                int32_t w = p[s];
+                if (w >= 0 && is_support(g, w, k)) ++pcd;
+            }
+            __hip_atomic_store(&g.cd[v], pcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            scanned += L;
+        }
+        push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, lanev, &c->overflow);
+        apush(a, 1, aq_item(AQ_V, v, 0), lanev && pcd <= k && L <= a.t.large_deg);
+        if (__ballot(lanev && pcd <= k && L > a.t.large_deg))
+            apush_chunks(a, 1, AQ_CH, v, nchunks(L, a.t.chunk), lanev && pcd <= k && L > a.t.large_deg);
+        if (__ballot(lanev && pcd > k)) {
+            // short lists that expand: each lane pushes its claimed neighbours
+            int32_t s = 0;
+            const int32_t *p = lanev ? g.nbr + g.off[v] : nullptr;
+            while (__ballot(lanev && pcd > k && s < L)) {
+                const bool act = lanev && pcd > k && s < L;
+                const int32_t w = act ? p[s] : -1;
+                apush_vertex(a, 0, AQ_CNT, w, act && claim(w, k));
+                ++s;
+            }
+            if (lanev && pcd > k) scanned += L;
+        }
+        // everything else: one wave per item
+        unsigned long long m = __ballot(fresh && !lanev);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const unsigned long long itw = __shfl(item, src);
+            const int tw = aq_type(itw);
+            const int32_t x = aq_v(itw);
+            const int32_t cx = aq_c(itw);
+            const int32_t Lx = g.len[x];
+            const int32_t kx = g.core[x];
+            if (tw == AQ_V) {
+                if (Lx > a.t.large_deg) {
+                    // a long root list: its CSD is counted chunk by chunk
+                    apush_chunks(a, 0, AQ_CNT, x, nchunks(Lx, a.t.chunk), lane() == 0);
+                    continue;
+                }
+                int32_t part = 0;
+                wave_walk(g, x, 0, Lx, [&](int32_t w, int32_t) {
+                    if (w >= 0 && is_support(g, w, kx)) ++part;
+                });
+                part = wave_sum(part);
+                if (lane() == 0) {
+                    __hip_atomic_store(&g.cd[x], part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    scanned += Lx;
+                }
+                push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, x, lane() == 0, &c->overflow);
+                if (part > kx) {
+                    if (lane() == 0) scanned += Lx;
+                    expand_list(x, 0, Lx, kx);
+                } else {
+                    apush(a, 1, aq_item(AQ_V, x, 0), lane() == 0);
+                }
+            } else if (tw == AQ_CNT) {
+                const int32_t lo = cx * a.t.chunk, hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
+                const int32_t nch = nchunks(Lx, a.t.chunk);
+                int32_t part = 0;
+                wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) {
+                    if (w >= 0 && is_support(g, w, kx)) ++part;
+                });
+                part = wave_sum(part);
+                int last = 0;
+                if (lane() == 0) {
+                    scanned += hi - lo;
+                    atomicAdd(&g.cd[x], part);
+                    wave_drain();  // the partial sum lands before this chunk counts as done
+                    last = atomicAdd(&g.done[x], 1) == nch - 1;
+                }
+                last = __shfl(last, 0);
+                if (last) {
+                    int32_t tot = 0;
+                    if (lane() == 0) {
+                        __hip_atomic_store(&g.done[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        tot = __hip_atomic_load(&g.cd[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    tot = __shfl(tot, 0);
+                    push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, x, lane() == 0, &c->overflow);
+                    if (tot > kx) apush_chunks(a, 0, AQ_EXP, x, nch, lane() == 0);
+                    else apush_chunks(a, 1, AQ_CH, x, nch, lane() == 0);
+                }
+            } else {  // AQ_EXP: claim the neighbours in one chunk
+                const int32_t lo = cx * a.t.chunk, hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
+                if (lane() == 0) scanned += hi - lo;
+                expand_list(x, lo, hi, kx);
+            }
+        }
+    });
+}
+
+// Asynchronous eviction (Algorithm 4 cascade) of the vertices in queue 1.
+__device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, long long &scanned) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    const int32_t ep = it.ep;
+    if (gtid() == 0) c->st_rounds += 1;
+    auto hit = [&](int32_t w, int32_t k) -> bool {
+        if (w < 0 || g.core[w] != k || ld_rlx(&g.stamp[w]) != ep) return false;
+        return atomicSub(&g.cd[w], 1) == k + 1;
+    };
+    aq_run(a, 1, [&](unsigned long long item, bool fresh) {
+        const int type = aq_type(item);
+        const int32_t x = aq_v(item);
+        const int32_t L = fresh && type == AQ_V ? g.len[x] : 0;
+        const bool lanev = fresh && type == AQ_V && L <= a.t.small_deg;
+        const int32_t k = lanev ? g.core[x] : 0;
+        {
+            int32_t s = 0;
+            const int32_t *p = lanev ? g.nbr + g.off[x] : nullptr;
+            while (__ballot(lanev && s < L)) {
+                const bool act = lanev && s < L;
+                const int32_t w = act ? p[s] : -1;
+                apush_vertex(a, 1, AQ_CH, w, act && hit(w, k));
+                ++s;
+            }
+            if (lanev) scanned += L;
+        }
+        unsigned long long m = __ballot(fresh && !lanev);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const unsigned long long itw = __shfl(item, src);
+            const int32_t xv = aq_v(itw);
+            const int32_t Lx = g.len[xv];
+            const int32_t kx = g.core[xv];
+            int32_t lo = 0, hi = Lx;
+            if (aq_type(itw) == AQ_CH) {
+                lo = aq_c(itw) * a.t.chunk;
+                hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
+            }
+            if (lane() == 0) scanned += hi - lo;
+            wave_walk(g, xv, lo, hi, [&](int32_t w, int32_t) { apush_vertex(a, 1, AQ_CH, w, hit(w, kx)); });
+        }
+    });
+}
+
+// Asynchronous peel (Algorithms 6-7 cascade) of the roots in queue 1.
+__device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, long long &scanned) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    const int32_t ep = it.ep;
+    if (gtid() == 0) c->st_rounds += 1;
+    auto body = [&](int32_t w, int32_t k) {
+        bool first = false, fire = false;
+        if (w >= 0 && g.core[w] == k && ld_rlx(&g.stamp[w]) != ep) {
+            int32_t old = atomicAdd(&g.dec[w], 1);
+            first = old == 0;
+            fire = g.mcd[w] - old - 1 == k - 1;
+            if (fire) atomicExch(&g.stamp[w], ep);
+        }
+        push_agg<int32_t>(a.q.touched, a.q.vcap, &c->touched_count, w, first, &c->overflow);
+        push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
+        apush_vertex(a, 1, AQ_CH, w, fire);
+    };
+    aq_run(a, 1, [&](unsigned long long item, bool fresh) {
+        const int type = aq_type(item);
+        const int32_t x = aq_v(item);
+        const int32_t L = fresh && type == AQ_V ? g.len[x] : 0;
+        const bool lanev = fresh && type == AQ_V && L <= a.t.small_deg;
+        const int32_t k = lanev ? g.core[x] : 0;
+        {
+            int32_t s = 0;
+            const int32_t *p = lanev ? g.nbr + g.off[x] : nullptr;
+            while (__ballot(lanev && s < L)) {
+                const bool act = lanev && s < L;
+                body(act ? p[s] : -1, k);
+                ++s;
+            }
+            if (lanev) scanned += L;
+        }
+        unsigned long long m = __ballot(fresh && !lanev);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const unsigned long long itw = __shfl(item, src);
+            const int32_t xv = aq_v(itw);
+            const int32_t Lx = g.len[xv];
+            const int32_t kx = g.core[xv];
+            int32_t lo = 0, hi = Lx;
+            if (aq_type(itw) == AQ_CH) {
+                lo = aq_c(itw) * a.t.chunk;
+                hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
+            }
+            if (lane() == 0) scanned += hi - lo;
+            wave_walk(g, xv, lo, hi, [&](int32_t w, int32_t) { body(w, kx); });
+        }
+    });
 }
 
 __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
@@ -1131,6 +1493,7 @@ __device__ __forceinline__ int64_t step_work(const KArgs &a, const Iter &it, con
 
 __device__ __forceinline__ bool step_is_local(const KArgs &a, const Iter &it, const PC &pc, int64_t work) {
     if (it.sc.mode && (pc.step <= S_APPLY || pc.step == S_CORE)) return false;
+    if (a.t.async_steps && (pc.step == S_EXPAND || pc.step == S_EVICT || pc.step == S_PEEL)) return false;
     if (pc.step <= S_APPLY) return work <= a.t.local_edges;
     return work <= a.t.local_items;
 }
@@ -1152,16 +1515,26 @@ __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &
         if (it.sc.mode) return PC{S_APPLY, 0};
         return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
     case S_APPLY:
+        if (a.t.async_steps) {
+            if (it.ins && ld_rlx(&a.ctl->aq_tail[0]) > 0) return PC{S_EXPAND, 0};
+            if (ld_rlx(&a.ctl->aq_tail[1]) == 0) return PC{S_CORE, 0};
+            return it.ins ? PC{S_EVICT, 0} : PC{S_PEEL, 0};
+        }
         if (it.ins) {
             if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
             return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
         }
         return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
     case S_EXPAND:
+        if (a.t.async_steps) return ld_rlx(&a.ctl->aq_tail[1]) > 0 ? PC{S_EVICT, 0} : PC{S_CORE, 0};
         if (!slot_empty_f(a, (pc.r + 1) % 3)) return PC{S_EXPAND, pc.r + 1};
         return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
-    case S_EVICT: return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_EVICT, pc.r + 1};
-    case S_PEEL: return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_PEEL, pc.r + 1};
+    case S_EVICT:
+        if (a.t.async_steps) return PC{S_CORE, 0};
+        return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_EVICT, pc.r + 1};
+    case S_PEEL:
+        if (a.t.async_steps) return PC{S_CORE, 0};
+        return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_PEEL, pc.r + 1};
     case S_CORE: return PC{S_MCD, 0};
     default: return PC{S_DONE, 0};
     }
@@ -1184,9 +1557,18 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
         else if (it.ins) apply_insert(a, it, T);
         else apply_delete(a, it, T);
         break;
-    case S_EXPAND: expand_round(a, it, pc.r, T, scanned); break;
-    case S_EVICT: evict_round(a, it, pc.r, T, scanned); break;
-    case S_PEEL: peel_round(a, it, pc.r, T, scanned); break;
+    case S_EXPAND:
+        if (a.t.async_steps) expand_async(a, it, scanned);
+        else expand_round(a, it, pc.r, T, scanned);
+        break;
+    case S_EVICT:
+        if (a.t.async_steps) evict_async(a, it, scanned);
+        else evict_round(a, it, pc.r, T, scanned);
+        break;
+    case S_PEEL:
+        if (a.t.async_steps) peel_async(a, it, scanned);
+        else peel_round(a, it, pc.r, T, scanned);
+        break;
     case S_CORE:
         apply_core(a, it, T);
         if (it.sc.mode == 2) star_kill(a, it, T);

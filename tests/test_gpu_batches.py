@@ -43,7 +43,7 @@ def _sequence(rng, n, s, d, nbatches, lo, hi):
     return np.asarray(kinds, np.int32), offs, np.concatenate(xs), np.concatenate(ys)
 
 
-@pytest.mark.parametrize("form", ["plain", "persistent", "graph"])
+@pytest.mark.parametrize("form", ["plain", "persistent", "graph", "async"])
 def test_sequence_matches_oracle(cm, oracle_mod, form):
     rng = graphgen.rng_for("seq-" + form)
     n = 20_000
@@ -55,7 +55,7 @@ def test_sequence_matches_oracle(cm, oracle_mod, form):
         st = fn(xs[offs[j]:offs[j + 1]], ys[offs[j]:offs[j + 1]])
         assert st[0] == 0
     mode = cm.MODE_PLAIN if form == "plain" else cm.MODE_PERSISTENT
-    with cm.Graph(mode=mode, use_graph=form == "graph") as g:
+    with cm.Graph(mode=mode, use_graph=form == "graph", async_steps=form == "async") as g:
         g.load(n, _dev(s), _dev(d))
         g.decompose()
         res, _ = g.run_batches(kinds, offs, _dev(xs), _dev(ys))

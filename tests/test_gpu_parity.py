@@ -57,7 +57,21 @@ def check_state(g, ref, tag=""):
     assert g.num_edges() == ref.num_edges(), tag
 
 
+ASYNC = False
+
+
+@pytest.fixture(autouse=True, params=[False, True], ids=["rounds", "async"])
+def _cascade_form(request):
+    """Every parity test runs with round-synchronous cascades and with
+    asynchronous (work-queue) cascades."""
+    global ASYNC
+    ASYNC = request.param
+    yield
+    ASYNC = False
+
+
 def new_graph(cm, n, s, d, dev, **kw):
+    kw.setdefault("async_steps", ASYNC)
     g = cm.Graph(**kw)
     g.load(n, _t(s, dev), _t(d, dev))
     g.decompose()

@@ -50,9 +50,9 @@ def _stream(scale, nreq, max_size, tag, spoil=()):
     return n, s, d, reqs
 
 
-def _run_served(cm, n, s, d, reqs, one_at_a_time, **scfg):
+def _run_served(cm, n, s, d, reqs, one_at_a_time, async_steps=False, **scfg):
     from paper_1612_09368_amd import serve
-    g = cm.Graph(mode=cm.MODE_PERSISTENT)
+    g = cm.Graph(mode=cm.MODE_PERSISTENT, async_steps=async_steps)
     g.load(n, s, d)
     g.decompose()
     cfg = {"ring_items": 1 << 18, "max_items": 1 << 16}
@@ -91,12 +91,13 @@ def test_serve_each_request_matches_oracle(cm, oracle_mod):
     g.close()
 
 
-def test_serve_mix_equals_alone(cm, oracle_mod):
+@pytest.mark.parametrize("async_steps", [False, True])
+def test_serve_mix_equals_alone(cm, oracle_mod, async_steps):
     n, s, d, reqs = _stream(12, 240, 600, "serve-mix", spoil=(5, 77, 150))
     ref = oracle_mod.DynamicGraph(n, s, d)
     want = [_oracle(ref, r) for r in reqs]
-    alone, c_alone, m_alone = _run_served(cm, n, s, d, reqs, True)
-    mix, c_mix, m_mix = _run_served(cm, n, s, d, reqs, False)
+    alone, c_alone, m_alone = _run_served(cm, n, s, d, reqs, True, async_steps=async_steps)
+    mix, c_mix, m_mix = _run_served(cm, n, s, d, reqs, False, async_steps=async_steps)
     assert [a[0] for a in alone] == want
     assert alone == mix
     assert np.array_equal(c_alone, ref.cores()) and np.array_equal(c_mix, ref.cores())
