@@ -554,13 +554,88 @@ def bench_serve(args, cm, torch):
     return out
 
 
+# ---------------------------------------------------------------------------
+# paper-sweep
+# ---------------------------------------------------------------------------
+SWEEP_UPDATES = 10_000
+SWEEP_SEQ_UPDATES = 1_000
+
+
+def bench_sweep(args, cm, torch):
+    """The paper's scalability experiment on synthetic graphs: ER, BA and
+    R-MAT with n = 2^15 .. 2^21 and m/n = 8; 10,000 random edge insertions,
+    then 10,000 random deletions, timed per edge; beside it the sequential
+    regime (one edge per iteration) on 1,000 of them, with iteration counts."""
+    import graphgen
+    sizes = [int(x) for x in args.sweep_scales.split(",")]
+    rows = []
+    for kind in ("er", "ba", "rmat"):
+        for sc in sizes:
+            rng = graphgen.rng_for(f"sweep-{kind}-{sc}")
+            n = 1 << sc
+            t0 = time.time()
+            if kind == "er":
+                s, d = graphgen.er_graph(n, 8 * n, rng)
+            elif kind == "ba":
+                s, d = graphgen.ba_graph_blocks(n, 8, rng)
+            else:
+                n, s, d = graphgen.rmat_graph(sc, 8, rng, workers=WORKERS)
+            es = graphgen.EdgeSet(s, d)
+            ia, ib = graphgen.uniform_non_edges(n, SWEEP_UPDATES, es, rng)
+            es.insert(ia, ib)
+            da, db = graphgen.existing_edges(SWEEP_UPDATES, es, rng)
+            dev = [to_dev(torch, z) for z in (s, d, ia, ib, da, db)]
+            row = {"graph": kind, "n": n, "m": int(s.size), "gen_s": round(time.time() - t0, 1)}
+            for regime, cnt in (("superior", SWEEP_UPDATES), ("sequential", SWEEP_SEQ_UPDATES)):
+                g = cm.Graph(mode=cm.MODE_PERSISTENT, single_edge=regime == "sequential")
+                g.load(n, dev[0], dev[1])
+                g.decompose()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                si = g.insert_edges(dev[2][:cnt], dev[3][:cnt])
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                # deletions of edges that exist in this regime's graph
+                if cnt == SWEEP_UPDATES:
+                    xa, xb = dev[4], dev[5]
+                else:
+                    keep = np.isin(graphgen.keys_of(da, db), graphgen.keys_of(s, d)) | \
+                        np.isin(graphgen.keys_of(da, db), graphgen.keys_of(ia[:cnt], ib[:cnt]))
+                    xa, xb = to_dev(torch, da[keep][:cnt]), to_dev(torch, db[keep][:cnt])
+                t3 = time.perf_counter()
+                sd = g.delete_edges(xa, xb)
+                torch.cuda.synchronize()
+                t4 = time.perf_counter()
+                g.close()
+                row[regime] = {"insert_us_per_edge": 1e6 * (t2 - t1) / cnt,
+                               "delete_us_per_edge": 1e6 * (t4 - t3) / max(int(xa.numel()), 1),
+                               "insert_iterations": si.iterations, "delete_iterations": sd.iterations,
+                               "edges": cnt}
+            rows.append(row)
+            log(f"{kind} n=2^{sc}: superior {row['superior']['insert_us_per_edge']:.3f}/"
+                f"{row['superior']['delete_us_per_edge']:.3f} us/edge ({row['superior']['insert_iterations']}/"
+                f"{row['superior']['delete_iterations']} it), sequential "
+                f"{row['sequential']['insert_us_per_edge']:.1f}/{row['sequential']['delete_us_per_edge']:.1f} us/edge")
+    big = [r for r in rows if r["graph"] == "rmat"][-1]
+    per_edge_us = (big["superior"]["insert_us_per_edge"] + big["superior"]["delete_us_per_edge"]) / 2
+    out = contract(f"paper scalability sweep: ER / BA / R-MAT, n = 2^{sizes[0]}..2^{sizes[-1]}, m/n = 8; "
+                   f"{SWEEP_UPDATES} random insertions then {SWEEP_UPDATES} random deletions per graph "
+                   f"(value: R-MAT n=2^{sizes[-1]}, superior edge sets)",
+                   1e6 / per_edge_us, 1, 0, per_edge_us * 2 * SWEEP_UPDATES / 1e3, 2 * SWEEP_UPDATES,
+                   "persistent (one launch per batch), superior edge sets vs one edge per iteration")
+    out["sweep"] = rows
+    out["roofline"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu-1m",
-                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve"])
+                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "paper-sweep"])
+    ap.add_argument("--sweep-scales", default="15,16,17,18,19,20,21", help="paper-sweep: log2 n values")
     ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
     ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -590,7 +665,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     fn = {"chunglu-1m": bench_cl1m, "rmat22-stream": bench_rmat22, "chunglu-pool512": bench_pool512,
-          "rmat-serve": bench_serve}
+          "rmat-serve": bench_serve, "paper-sweep": bench_sweep}
     out = fn[args.workload](args, cm, torch)
     print(json.dumps(out), flush=True)
 

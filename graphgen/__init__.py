@@ -25,7 +25,7 @@ __all__ = [
     "rng_for", "keys_of", "split_keys", "er_graph", "chung_lu_graph",
     "rmat_graph", "ba_graph", "uniform_non_edges", "weighted_non_edges",
     "rmat_non_edges", "existing_edges", "log_uniform_sizes", "EdgeSet", "DynamicEdgeSet",
-    "vertex_insert_payload", "power_law_degrees", "rmat_stream", "chung_lu_pool", "StreamEdgeSet", "serve_stream",
+    "vertex_insert_payload", "power_law_degrees", "rmat_stream", "chung_lu_pool", "StreamEdgeSet", "serve_stream", "ba_graph_blocks",
 ]
 
 
@@ -690,3 +690,40 @@ def serve_stream(scale, nreq, rng, edge_factor=16, max_size=100_000, mix=(0.4, 0
         if progress and (j + 1) % 1000 == 0:
             progress(f"requests: {j + 1}/{nreq}")
     return n, s, d, reqs
+
+
+def ba_graph_blocks(n: int, k: int, rng, block: int = 4096):
+    """Preferential attachment (Barabasi-Albert) for large n, drawn in blocks:
+    every vertex of a block attaches up to k edges to distinct earlier
+    vertices, each chosen with probability proportional to its degree in the
+    graph as it stood before the block (a block is never larger than the
+    graph before it; the seed is a (k+1)-clique).  A vertex whose 3k degree-
+    weighted draws hold fewer than k distinct targets keeps fewer edges."""
+    k0 = k + 1
+    cs, cd = np.triu_indices(k0, 1)
+    ends = np.empty(2 * (cs.size + k * max(n - k0, 0)), dtype=np.int64)
+    ends[: 2 * cs.size] = np.concatenate([cs, cd])
+    ne = 2 * cs.size
+    srcs, dsts = [cs.astype(np.int64)], [cd.astype(np.int64)]
+    v0 = k0
+    while v0 < n:
+        b = min(block, n - v0, v0)
+        cand = ends[rng.integers(0, ne, (b, 3 * k))]
+        cand.sort(axis=1)
+        dup = np.zeros_like(cand, dtype=bool)
+        dup[:, 1:] = cand[:, 1:] == cand[:, :-1]
+        # first k distinct targets per row, in a random order of the row
+        keyed = np.where(dup, np.iinfo(np.int64).max, rng.integers(0, 1 << 40, cand.shape))
+        order = np.argsort(keyed, axis=1)[:, :k]
+        pick = np.take_along_axis(cand, order, axis=1)
+        ok = ~np.take_along_axis(dup, order, axis=1)
+        own = np.repeat(np.arange(v0, v0 + b, dtype=np.int64), k).reshape(b, k)
+        s_new, d_new = pick[ok], own[ok]
+        srcs.append(s_new)
+        dsts.append(d_new)
+        cnt = s_new.size
+        ends[ne:ne + cnt] = s_new
+        ends[ne + cnt:ne + 2 * cnt] = d_new
+        ne += 2 * cnt
+        v0 += b
+    return split_keys(np.unique(keys_of(np.concatenate(srcs), np.concatenate(dsts))))

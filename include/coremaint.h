@@ -91,6 +91,8 @@ typedef struct cm_config {
                                    instantiated hipGraph (rebuilt when buffers move) */
     int32_t async_steps;        /* 1 = each expansion / eviction / peel cascade runs as one
                                    work-queue step instead of one grid-wide step per round */
+    int32_t single_edge;        /* 1 = one edge per iteration (the sequential regime the
+                                   paper compares against) instead of a superior edge set */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 

@@ -53,6 +53,7 @@ class Config(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("async_steps", ctypes.c_int32),
+        ("single_edge", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -186,7 +187,7 @@ class Graph:
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
                  local_edges=0, local_items=0, local_work=0, timing=False, use_graph=False, async_steps=False,
-                 stream=None):
+                 single_edge=False, stream=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -205,6 +206,7 @@ class Graph:
         cfg.timing = 1 if timing else 0
         cfg.use_graph = 1 if use_graph else 0
         cfg.async_steps = 1 if async_steps else 0
+        cfg.single_edge = 1 if single_edge else 0
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()
         st = lib.cm_create(ctypes.byref(cfg), ctypes.byref(h))

@@ -868,6 +868,8 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 128;
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         g->tune.async_steps = g->cfg.async_steps ? 1 : 0;
+        g->tune.single_edge = g->cfg.single_edge ? 1 : 0;
+        if (g->tune.single_edge) g->tune.rounds = 1;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
         HIPCHK(coop_occupancy(0, &bpc_m));

@@ -89,6 +89,7 @@ struct Ctl {
     int32_t aq_tail[2];           // asynchronous queues: slots handed out
     int32_t aq_head[2];           //   slots taken by consumers
     int32_t aq_pend[2];           //   items pushed and not finished
+    unsigned long long one_key;   // single-edge regime: largest complemented claim key of the iteration
     int32_t sv_decision;          // serving: decision of the waiting thread
     ProgBatch sv_batch;           // serving: descriptor of the current batch
 };
@@ -189,6 +190,8 @@ struct Tune {
     int32_t local_items; // frontier steps up to this many items run in one workgroup
     int32_t local_work;  // ... and only if their lists hold at most this many entries
     int32_t async_steps; // cascades as work-queue steps
+    int32_t single_edge; // one edge per iteration (the sequential regime) instead of a superior edge set
+    int32_t pad;
 };
 
 constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
@@ -313,6 +316,9 @@ __device__ __forceinline__ void ph_stop(Ctl *c, int slot, unsigned long long t0)
 // ordering with the data it guards comes from the grid / workgroup barrier
 // the readers passed; the load itself reads the device-coherent value.
 __device__ __forceinline__ int32_t ld_rlx(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_rlx64(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -467,6 +467,11 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
                       (fv && matched_before(a.g.matched[v], it.ep, a.t.rounds, r))))
             continue;
         unsigned long long key = hi | mix32((uint32_t)i);
+        if (a.t.single_edge) {
+            // keys fall with the iteration, so the complemented maximum needs no reset
+            atomicMax(&a.ctl->one_key, ~key);
+            continue;
+        }
         if (fu) atomicMin(&a.g.claim[u], key);
         if (fv) atomicMin(&a.g.claim[v], key);
     }
@@ -489,7 +494,8 @@ __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int 
         bool part = !(r > 0 && ((fu && matched_before(a.g.matched[u], it.ep, a.t.rounds, r)) ||
                                 (fv && matched_before(a.g.matched[v], it.ep, a.t.rounds, r))));
         unsigned long long key = hi | mix32((uint32_t)i);
-        bool win = part && (!fu || a.g.claim[u] == key) && (!fv || a.g.claim[v] == key);
+        bool win = a.t.single_edge ? ld_rlx64(&a.ctl->one_key) == ~key
+                                   : part && (!fu || a.g.claim[u] == key) && (!fv || a.g.claim[v] == key);
         if (win) {
             a.b.esel[i] = it.ep;
             if (fu) a.g.matched[u] = mstamp;

@@ -98,3 +98,12 @@ def test_serve_stream_requests_are_valid_in_order():
         else:
             st = ref.delete_vertices(r[1])[0]
         assert st == 0, r[0]
+
+
+def test_ba_blocks_shape():
+    n, k = 20_000, 4
+    s, d = graphgen.ba_graph_blocks(n, k, graphgen.rng_for("ba"), block=512)
+    _simple(n, s, d)
+    assert 0.95 * k * n < s.size <= k * n + k * (k + 1) // 2
+    deg = np.bincount(np.concatenate([s, d]), minlength=n)
+    assert deg.min() >= 1 and deg.max() > 20 * 2 * k   # preferential attachment: heavy tail

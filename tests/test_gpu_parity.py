@@ -434,3 +434,20 @@ def test_vertex_ops_dense(cm, dev, oracle_mod, mode):
             hit = np.isin(lo, top) | np.isin(hi, top)
             es = graphgen.EdgeSet(*graphgen.split_keys(ks[~hit]))
             check_state(g, ref, f"dense vertex delete {step}")
+
+
+def test_single_edge_regime(cm, dev, oracle_mod):
+    """One edge per iteration (the sequential regime the paper compares
+    against): same cores, and exactly one iteration per valid edge."""
+    rng = graphgen.rng_for("single-edge")
+    n = 1500
+    s, d = graphgen.chung_lu_graph(n, 6000, 2.2, 200.0, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev, mode=1, single_edge=True) as g:
+        for kind, a, b in _batches(ref, rng, n, 4, 150):
+            if a.size == 0:
+                continue
+            st = (g.insert_edges if kind == "insert" else g.delete_edges)(_t(a, dev), _t(b, dev))
+            (ref.insert_edges if kind == "insert" else ref.delete_edges)(a, b)
+            assert st.iterations == a.size, (kind, st.iterations, a.size)
+            check_state(g, ref, f"single-edge {kind}")
