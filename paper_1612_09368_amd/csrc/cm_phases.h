@@ -1136,54 +1136,36 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, p);
     };
 
-    for_vertices(
-        T, a.q.fq[bc], nq, g, a.t.small_deg,
-        [&](int32_t v, int32_t L) {
-            int32_t k = g.core[v];
-            const int32_t *p = g.nbr + g.off[v];
-            int32_t pcd = 0;
-            for (int32_t s = 0; s < L; ++s) {
-                int32_t w = p[s];
-                if (w >= 0 && is_support(g, w, k)) ++pcd;
+    // Lists of up to `large` slots: CSD and expansion as flattened walks of
+    // the wave's batch; longer root lists have their CSD counted chunk by
+    // chunk next round.
+    for_batches(T, a.q.fq[bc], nq, [&](int32_t v) {
+        const int32_t L = v >= 0 ? g.len[v] : 0;
+        const int32_t k = v >= 0 ? g.core[v] : 0;
+        const bool big = L > a.t.large_deg;
+        if (big) {
+            const int nch = nchunks(L, a.t.chunk);
+            const int base = atomicAdd(&c->fh_tail[sn], nch);
+            for (int q = 0; q < nch; ++q) {
+                if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
+                else atomicOr(&c->overflow, 1);
             }
-            g.cd[v] = pcd;
-            scanned += L;
-            push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, true, &c->overflow);
-            if (pcd > k) {
-                scanned += L;
-                for (int32_t s = 0; s < L; ++s) push_next(p[s], claim(p[s], k));
-            } else {
-                push_evict(v, true);
-            }
-        },
-        [&](int32_t v, int32_t L) {
-            if (L > a.t.large_deg) {
-                // a long root list: count its CSD chunk by chunk next round
-                if (lane() == 0) {
-                    int nch = nchunks(L, a.t.chunk);
-                    int base = atomicAdd(&c->fh_tail[sn], nch);
-                    for (int q = 0; q < nch; ++q) {
-                        if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
-                        else atomicOr(&c->overflow, 1);
-                    }
-                }
-                return;
-            }
-            int32_t k = g.core[v];
-            int32_t pcd = 0;
-            wave_walk(g, v, 0, L, [&](int32_t w, int32_t) {
-                if (w >= 0 && is_support(g, w, k)) ++pcd;
-            });
-            pcd = wave_sum(pcd);
-            if (lane() == 0) { g.cd[v] = pcd; scanned += L; }
-            push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, lane() == 0, &c->overflow);
-            if (pcd > k) {
-                if (lane() == 0) scanned += L;
-                wave_walk(g, v, 0, L, [&](int32_t w, int32_t) { push_next(w, claim(w, k)); });
-            } else {
-                push_evict(v, lane() == 0);
-            }
+        }
+        const bool live = v >= 0 && !big;
+        int32_t pcd = 0;
+        flat_walk(g, v, live ? L : 0, [&](int32_t j, int32_t w, unsigned long long own) {
+            const int32_t kj = __shfl(k, j < 0 ? 0 : j);
+            pcd += __popcll(__ballot(w >= 0 && is_support(g, w, kj)) & own);
         });
+        if (live) { g.cd[v] = pcd; scanned += L; }
+        push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, live, &c->overflow);
+        const bool grow = live && pcd > k;
+        if (grow) scanned += L;
+        push_evict(v, live && !grow);
+        flat_walk(g, v, grow ? L : 0, [&](int32_t j, int32_t w, unsigned long long) {
+            push_next(w, claim(w, __shfl(k, j < 0 ? 0 : j)));
+        });
+    });
 
     // CSD of long lists, chunk by chunk; the last chunk to finish decides.
     for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
@@ -1253,22 +1235,8 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     auto push_next = [&](int32_t w, bool p) {
         push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
-    for_vertices(
-        T, a.q.eq[bc], nq, g, a.t.small_deg,
-        [&](int32_t x, int32_t L) {
-            int32_t k = g.core[x];
-            const int32_t *p = g.nbr + g.off[x];
-            scanned += L;
-            for (int32_t s = 0; s < L; ++s) {
-                int32_t w = p[s];
-                push_next(w, hit(w, k));
-            }
-        },
-        [&](int32_t x, int32_t L) {
-            int32_t k = g.core[x];
-            if (lane() == 0) scanned += L;
-            wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
-        });
+    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
+                                [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
         if (lane() == 0) scanned += hi - lo;
@@ -1305,19 +1273,7 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, fire);
         push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
-    for_vertices(
-        T, a.q.eq[bc], nq, g, a.t.small_deg,
-        [&](int32_t x, int32_t L) {
-            int32_t k = g.core[x];
-            const int32_t *p = g.nbr + g.off[x];
-            scanned += L;
-            for (int32_t s = 0; s < L; ++s) body(p[s], k);
-        },
-        [&](int32_t x, int32_t L) {
-            int32_t k = g.core[x];
-            if (lane() == 0) scanned += L;
-            wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { body(w, k); });
-        });
+    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
         if (lane() == 0) scanned += hi - lo;
@@ -1397,23 +1353,28 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         return cw >= cv ? 1 : 0;
     };
     const int32_t n = qlen(&c->chg_count, a.q.vcap);
-    for_vertices(
-        T, a.q.chg, n, g, a.t.small_deg,
-        [&](int32_t v, int32_t L) {
-            int32_t cv = g.core[v];
-            const int32_t *p = g.nbr + g.off[v];
-            int32_t cnt = 0;
-            for (int32_t s = 0; s < L; ++s) cnt += nb(p[s], cv);
-            g.mcd[v] = cnt;
-            scanned += L;
-        },
-        [&](int32_t v, int32_t L) {
-            int32_t cv = g.core[v];
-            int32_t cnt = 0;
-            wave_walk(g, v, 0, L, [&](int32_t w, int32_t) { cnt += nb(w, cv); });
-            cnt = wave_sum(cnt);
-            if (lane() == 0) { g.mcd[v] = cnt; scanned += L; }
+    for_batches(T, a.q.chg, n, [&](int32_t v) {
+        const int32_t L = v >= 0 ? g.len[v] : 0;
+        const int32_t cv = v >= 0 ? g.core[v] : 0;
+        const bool big = L > a.t.large_deg;
+        int32_t cnt = 0;
+        flat_walk(g, v, big ? 0 : L, [&](int32_t j, int32_t w, unsigned long long own) {
+            cnt += __popcll(__ballot(nb(w, __shfl(cv, j < 0 ? 0 : j)) != 0) & own);
         });
+        if (v >= 0 && !big) { g.mcd[v] = cnt; scanned += L; }
+        unsigned long long m = __ballot(big);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const int32_t vv = __shfl(v, src);
+            const int32_t cvv = __shfl(cv, src);
+            const int32_t LL = __shfl(L, src);
+            int32_t tot = 0;
+            wave_walk(g, vv, 0, LL, [&](int32_t w, int32_t) { tot += nb(w, cvv); });
+            tot = wave_sum(tot);
+            if (lane() == 0) { g.mcd[vv] = tot; scanned += LL; }
+        }
+    });
     const int32_t nh = qlen(&c->chh_count, a.q.hcap);
     for_chunks(T, a.q.chh, nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
         int32_t cv = g.core[v];
@@ -2198,17 +2159,8 @@ __device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, cons
     auto push_next = [&](int32_t w, bool p) {
         push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
-    for_vertices(
-        T, a.q.eq[bc], nq, g, a.t.small_deg,
-        [&](int32_t x, int32_t L) {
-            const int32_t *p = g.nbr + g.off[x];
-            scanned += L;
-            for (int32_t s = 0; s < L; ++s) push_next(p[s], body(p[s]));
-        },
-        [&](int32_t x, int32_t L) {
-            if (lane() == 0) scanned += L;
-            wave_walk(g, x, 0, L, [&](int32_t w, int32_t) { push_next(w, body(w)); });
-        });
+    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
+                                [&](int32_t w, int32_t) { push_next(w, body(w)); });
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, body(w)); });

@@ -117,4 +117,91 @@ __device__ __forceinline__ void lane_walk(const DevGraph &g, int32_t v, int32_t 
     }
 }
 
+
+// Team-stride over a vertex queue in batches of up to 64 entries per wave
+// (fewer when the queue is short, as in for_vertices): fb(v) runs on the
+// whole wave with lane j holding entry j of the batch (v < 0 past the end).
+template <class FB>
+__device__ __forceinline__ void for_batches(const Team &T, const int32_t *q, int32_t n, FB &&fb) {
+    const int nw = T.nwaves();
+    int per = (int)(((int64_t)n + nw - 1) / nw);
+    per = per < 1 ? 1 : (per > WAVE ? WAVE : per);
+    const int step = nw * per;
+    for (int32_t base = T.wave() * per; base < n; base += step) {
+        const int32_t i = base + lane();
+        fb((lane() < per && i < n) ? q[i] : -1);
+    }
+}
+
+// Flattened walk over the lists of a wave's batch: lane j holds vertex v_j
+// and the number L_j of leading slots of its list to walk (0 for none).
+// The lists are laid end to end and every lane takes one slot per step, so
+// a batch of short and medium lists keeps all 64 lanes busy with 64 loads
+// in flight instead of walking the lists one after another.  f(j, w, own)
+// runs on every lane each step (it may use wave votes): j = the lane whose
+// list holds the slot this lane reads (-1 when it reads none), w = the slot's
+// entry (< 0 for a tombstone or none), own = the lanes that read a slot of
+// THIS lane's list in this step, so that popcount(ballot(p) & own) counts p
+// over this lane's slots.
+template <class F>
+__device__ __forceinline__ void flat_walk(const DevGraph &g, int32_t v, int32_t L, F &&f) {
+    int32_t incl = L;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o);
+        if (lane() >= o) incl += t;
+    }
+    const int32_t total = __shfl(incl, WAVE - 1);
+    const int32_t excl = incl - L;
+    const int64_t off = (v >= 0 && L > 0) ? g.off[v] : 0;
+    for (int32_t base = 0; base < total; base += WAVE) {
+        const int32_t e = base + lane();
+        // owner of slot e: the last lane whose list starts at or before e
+        int32_t j = 0;
+        for (int s = WAVE / 2; s > 0; s >>= 1) {
+            const int32_t xc = __shfl(excl, j + s);
+            if (xc <= e) j += s;
+        }
+        const int32_t xj = __shfl(excl, j);
+        const int64_t oj = __shfl(off, j);
+        const bool has = e < total;
+        const int32_t w = has ? g.nbr[oj + (e - xj)] : -1;
+        int32_t lo = excl - base, hi = incl - base;
+        lo = lo < 0 ? 0 : (lo > WAVE ? WAVE : lo);
+        hi = hi < 0 ? 0 : (hi > WAVE ? WAVE : hi);
+        const unsigned long long own =
+            hi > lo ? ((hi - lo == WAVE ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo) : 0ull;
+        f(has ? j : -1, w, own);
+    }
+}
+
+// Team-stride over a vertex queue visiting every slot of every list:
+// fs(w, k) runs on every lane per step, k = core number of the list's
+// owner (w < 0: no slot or a tombstone).  Lists of up to `large` slots are
+// walked flattened, batch by batch; a longer one (possible only for queue
+// entries not routed through push_vertex) is walked by the wave alone.
+// Returns the slots visited by this lane's owned lists (for statistics).
+template <class FS>
+__device__ __forceinline__ long long for_vertex_slots(const Team &T, const int32_t *q, int32_t n,
+                                                      const DevGraph &g, int32_t large, FS &&fs) {
+    long long seen = 0;
+    for_batches(T, q, n, [&](int32_t v) {
+        const int32_t L = v >= 0 ? g.len[v] : 0;
+        const int32_t k = v >= 0 ? g.core[v] : 0;
+        const bool big = L > large;
+        seen += L;
+        flat_walk(g, v, big ? 0 : L, [&](int32_t j, int32_t w, unsigned long long) {
+            fs(w, __shfl(k, j < 0 ? 0 : j));
+        });
+        unsigned long long m = __ballot(big);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const int32_t vv = __shfl(v, src);
+            const int32_t kk = __shfl(k, src);
+            wave_walk(g, vv, 0, __shfl(L, src), [&](int32_t w, int32_t) { fs(w, kk); });
+        }
+    });
+    return seen;
+}
+
 }  // namespace cm
