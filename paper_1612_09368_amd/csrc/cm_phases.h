@@ -1016,6 +1016,8 @@ __device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, long
     if (gtid() == 0) c->st_rounds += 1;
     auto hit = [&](int32_t w, int32_t k) -> bool {
         if (w < 0 || g.core[w] != k || ld_rlx(&g.stamp[w]) != ep) return false;
+        // a counter already at or below k has crossed once: w is evicted
+        if (ld_rlx(&g.cd[w]) <= k) return false;
         return atomicSub(&g.cd[w], 1) == k + 1;
     };
     aq_run(a, 1, [&](unsigned long long item, bool fresh) {
@@ -1129,11 +1131,15 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         g.cd[w] = 0;
         return true;
     };
+    WaveBuf bq = wave_buf(0), be = wave_buf(1), bcand = wave_buf(2);
     auto push_next = [&](int32_t w, bool p) {
-        push_vertex(a, a.q.fq[bn], &c->fq_tail[sn], a.q.fh[bn], &c->fh_tail[sn], w, p);
+        push_vertex_wb(a, bq, a.q.fq[bn], &c->fq_tail[sn], a.q.fh[bn], &c->fh_tail[sn], w, p);
     };
     auto push_evict = [&](int32_t v, bool p) {
-        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, p);
+        push_vertex_wb(a, be, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, p);
+    };
+    auto push_cand = [&](int32_t v, bool p) {
+        wb_push(bcand, a.q.cand, a.q.vcap, &c->cand_count, v, p, &c->overflow);
     };
 
     // Lists of up to `large` slots: CSD and expansion as flattened walks of
@@ -1158,7 +1164,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             pcd += __popcll(__ballot(w >= 0 && is_support(g, w, kj)) & own);
         });
         if (live) { g.cd[v] = pcd; scanned += L; }
-        push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, live, &c->overflow);
+        push_cand(v, live);
         const bool grow = live && pcd > k;
         if (grow) scanned += L;
         push_evict(v, live && !grow);
@@ -1190,7 +1196,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
                 tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             tot = __shfl(tot, 0);
-            push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, lane() == 0, &c->overflow);
+            push_cand(v, lane() == 0);
             if (tot > k) {
                 if (lane() == 0) {
                     int base = atomicAdd(&c->fx_tail[sn], nch);
@@ -1211,6 +1217,9 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { push_next(w, claim(w, k)); });
     });
+    wb_flush(bq, a.q.fq[bn], a.q.vcap, &c->fq_tail[sn], &c->overflow);
+    wb_flush(be, a.q.eq[0], a.q.vcap, &c->eq_tail[0], &c->overflow);
+    wb_flush(bcand, a.q.cand, a.q.vcap, &c->cand_count, &c->overflow);
 }
 
 // Negative traversal (Algorithm 4) as rounds: an evicted candidate lowers the
@@ -1230,10 +1239,13 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     const int32_t ep = it.ep;
     auto hit = [&](int32_t w, int32_t k) -> bool {
         if (w < 0 || g.core[w] != k || g.stamp[w] != ep) return false;
+        // a counter already at or below k has crossed once: w is evicted
+        if (ld_rlx(&g.cd[w]) <= k) return false;
         return atomicSub(&g.cd[w], 1) == k + 1;
     };
+    WaveBuf bq = wave_buf(0);
     auto push_next = [&](int32_t w, bool p) {
-        push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
+        push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
     scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
                                 [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
@@ -1242,6 +1254,7 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
     });
+    wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
 }
 
 // Peel cascade of the deletion (Algorithms 6-7) as rounds.  A peeled vertex
@@ -1261,6 +1274,7 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         c->st_rounds += 1;
     }
     const int32_t ep = it.ep;
+    WaveBuf bq = wave_buf(0), bt = wave_buf(1), bchg = wave_buf(2);
     auto body = [&](int32_t w, int32_t k) {
         bool first = false, fire = false;
         if (w >= 0 && g.core[w] == k && g.stamp[w] != ep) {
@@ -1269,9 +1283,9 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
             fire = g.mcd[w] - old - 1 == k - 1;
             if (fire) g.stamp[w] = ep;
         }
-        push_agg<int32_t>(a.q.touched, a.q.vcap, &c->touched_count, w, first, &c->overflow);
-        push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, fire);
-        push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
+        wb_push(bt, a.q.touched, a.q.vcap, &c->touched_count, w, first, &c->overflow);
+        push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, fire);
+        push_vertex_wb(a, bchg, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
     scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
@@ -1279,6 +1293,9 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
     });
+    wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
+    wb_flush(bt, a.q.touched, a.q.vcap, &c->touched_count, &c->overflow);
+    wb_flush(bchg, a.q.chg, a.q.vcap, &c->chg_count, &c->overflow);
 }
 
 // Core update (Algorithm 1: +1 for every surviving candidate; Algorithm 5:
@@ -2156,8 +2173,9 @@ __device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, cons
         g.core[w] = k;
         return true;
     };
+    WaveBuf bq = wave_buf(0);
     auto push_next = [&](int32_t w, bool p) {
-        push_vertex(a, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
+        push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
     scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
                                 [&](int32_t w, int32_t) { push_next(w, body(w)); });
@@ -2165,6 +2183,7 @@ __device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, cons
         if (lane() == 0) scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, body(w)); });
     });
+    wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
 }
 
 __device__ __forceinline__ bool dec_block_local_ok(const KArgs &a, const DState &st, const Team &T) {

@@ -30,6 +30,62 @@ __device__ __forceinline__ void push_vertex(const KArgs &a, int32_t *vq, int32_t
     }
 }
 
+// Per-wave push buffers in LDS.  A queue tail is one word that every wave
+// appends to, and returning atomics on one address serialise (about 11 ns
+// each on gfx950), so a traversal step that pushed with one atomic per wave
+// per step was bound by that word.  A wave instead collects its pushes in
+// LDS and appends them with one atomic per 64 or more entries; a round
+// flushes its buffers before its barrier.  wb_push / push_vertex_wb must be
+// called by every lane of the wave (pred selects the pushing lanes).
+constexpr int PUSH_SLOTS = 3;
+struct WaveBuf {
+    int32_t *buf;  // 2 * WAVE entries of this wave's slot
+    int32_t n;     // entries held (uniform over the wave)
+};
+__device__ __forceinline__ WaveBuf wave_buf(int slot) {
+    __shared__ int32_t lds_push[PUSH_SLOTS][COOP_THREADS / WAVE][2 * WAVE];
+    return WaveBuf{lds_push[slot][threadIdx.x / WAVE], 0};
+}
+__device__ __forceinline__ void wb_flush(WaveBuf &b, int32_t *q, int32_t qcap, int32_t *tail, int32_t *overflow) {
+    if (b.n == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // other lanes' LDS writes come first
+    int base = 0;
+    if (lane() == 0) base = atomicAdd(tail, b.n);
+    base = __shfl(base, 0);
+    for (int i = lane(); i < b.n; i += WAVE) {
+        const int pos = base + i;
+        if (pos < qcap) q[pos] = b.buf[i];
+        else atomicOr(overflow, 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // reads done before the slots are reused
+    b.n = 0;
+}
+__device__ __forceinline__ void wb_push(WaveBuf &b, int32_t *q, int32_t qcap, int32_t *tail, int32_t val,
+                                        bool pred, int32_t *overflow) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    if (pred) b.buf[b.n + __popcll(m & ((1ull << lane()) - 1ull))] = val;
+    b.n += __popcll(m);
+    if (b.n >= WAVE) wb_flush(b, q, qcap, tail, overflow);
+}
+// push_vertex through a wave buffer (long lists still go straight to the
+// chunk queue, one atomic per list).
+__device__ __forceinline__ void push_vertex_wb(const KArgs &a, WaveBuf &b, int32_t *vq, int32_t *vtail,
+                                               int64_t *hq, int32_t *htail, int32_t w, bool pred) {
+    const int32_t L = pred ? a.g.len[w] : 0;
+    const bool big = pred && L > a.t.large_deg;
+    wb_push(b, vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
+    if (big) {
+        const int nch = nchunks(L, a.t.chunk);
+        const int base = atomicAdd(htail, nch);
+        for (int c = 0; c < nch; ++c) {
+            const int pos = base + c;
+            if (pos < a.q.hcap) hq[pos] = chunk_item(w, c);
+            else atomicOr(&a.ctl->overflow, 1);
+        }
+    }
+}
+
 // Team-stride over a vertex queue.  fl(v, L) runs on the owning lane for
 // short lists; fw(v, L) runs on the whole wave (uniform) for the others.
 // A wave takes `per` consecutive entries, per = ceil(n / waves) capped at
