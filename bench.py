@@ -590,6 +590,11 @@ def bench_sweep(args, cm, torch):
                 g = cm.Graph(mode=cm.MODE_PERSISTENT, single_edge=regime == "sequential")
                 g.load(n, dev[0], dev[1])
                 g.decompose()
+                if regime == "superior":
+                    # generator sanity: the paper reports BA all at core 8, ER with max core ~10
+                    c0 = g.cores()
+                    row["kmax"] = int(c0.max())
+                    row["top_level_share"] = round(float((c0 == c0.max()).mean()), 4)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 si = g.insert_edges(dev[2][:cnt], dev[3][:cnt])
@@ -628,13 +633,78 @@ def bench_sweep(args, cm, torch):
     return out
 
 
+# ---------------------------------------------------------------------------
+# core-levels
+# ---------------------------------------------------------------------------
+LV_LEVELS, LV_FRAC = 5, 0.2
+
+
+def bench_levels(args, cm, torch):
+    """Per-edge time against the core number of the updated edges (the
+    paper's experiment on the core distribution of the updates): on the
+    R-MAT scale-22 graph, five typical edge core numbers K1 < ... < K5 (the
+    edge core distribution's quantiles 0.1, 0.3, ..., 0.9); for each, 20% of
+    the edges of that core number, chosen at random, are deleted as one
+    batch and then inserted back as one batch (the graph, and so every core
+    number, is back to the start afterwards).  Persistent form."""
+    import graphgen
+    t = time.time()
+    rng = graphgen.rng_for("bench-levels")
+    n, s, d = graphgen.rmat_graph(RM_SCALE, 16, rng, workers=WORKERS)
+    log(f"r-mat scale {RM_SCALE}: {s.size} edges ({time.time() - t:.0f}s)")
+    ds, dd = to_dev(torch, s), to_dev(torch, d)
+    params, tuning = tuned_params(args, n, s.size, [LV_FRAC * s.size / 50], None)
+    g = cm.Graph(mode=cm.MODE_PERSISTENT, timing=True, **params)
+    g.load(n, ds, dd)
+    g.decompose()
+    cores0 = g.cores()
+    levels = graphgen.typical_levels(s, d, cores0, LV_LEVELS)
+    ec = graphgen.edge_levels(s, d, cores0)
+    rows, tot_edges, tot_s = [], 0, 0.0
+    for k in levels:
+        a, b = graphgen.edges_at_level(s, d, cores0, k, LV_FRAC, rng)
+        xa, xb = to_dev(torch, a), to_dev(torch, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sd = g.delete_edges(xa, xb)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        si = g.insert_edges(xa, xb)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        assert sd.status == 0 and si.status == 0, (sd.status, si.status)
+        back = bool(np.array_equal(g.cores(), cores0))
+        assert back, f"level {k}: core numbers differ after deleting and re-inserting the same edges"
+        rows.append({"level": k, "level_edges": int((ec == k).sum()), "edges": int(a.size),
+                     "delete_us_per_edge": 1e6 * (t1 - t0) / a.size,
+                     "insert_us_per_edge": 1e6 * (t2 - t1) / a.size,
+                     "delete_iterations": sd.iterations, "insert_iterations": si.iterations,
+                     "delete_changed": sd.changed, "insert_changed": si.changed})
+        tot_edges += 2 * int(a.size)
+        tot_s += t2 - t0
+        r = rows[-1]
+        log(f"level {k}: {a.size} of {r['level_edges']} edges; delete {r['delete_us_per_edge']:.3f} us/edge "
+            f"({sd.iterations} it), insert {r['insert_us_per_edge']:.3f} us/edge ({si.iterations} it)")
+    g.close()
+    out = contract(f"r-mat scale {RM_SCALE} (edge factor 16, {s.size} edges); per typical edge core number "
+                   f"(quantiles 0.1..0.9 of the edge core distribution), {int(LV_FRAC * 100)}% of that "
+                   f"level's edges deleted as one batch then inserted back as one batch",
+                   tot_edges / tot_s, len(rows), 0, 1e3 * tot_s / max(len(rows), 1),
+                   tot_edges // max(len(rows), 1), "persistent (one launch per batch)")
+    out["levels"] = rows
+    out["tuning"] = tuning
+    out["roofline"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chunglu-1m",
-                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "paper-sweep"])
+                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "paper-sweep",
+                             "core-levels"])
     ap.add_argument("--sweep-scales", default="15,16,17,18,19,20,21", help="paper-sweep: log2 n values")
     ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
     ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
@@ -665,7 +735,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     fn = {"chunglu-1m": bench_cl1m, "rmat22-stream": bench_rmat22, "chunglu-pool512": bench_pool512,
-          "rmat-serve": bench_serve, "paper-sweep": bench_sweep}
+          "rmat-serve": bench_serve, "paper-sweep": bench_sweep, "core-levels": bench_levels}
     out = fn[args.workload](args, cm, torch)
     print(json.dumps(out), flush=True)
 

@@ -361,6 +361,35 @@ def existing_edges(count: int, es: EdgeSet, rng):
     return np.where(flip, d, s).astype(np.int32), np.where(flip, s, d).astype(np.int32)
 
 
+def edge_levels(s, d, cores):
+    """Core number of each edge: the smaller core number of its endpoints
+    (`cores` is an input here, computed by whoever calls)."""
+    cores = np.asarray(cores)
+    return np.minimum(cores[s], cores[d])
+
+
+def typical_levels(s, d, cores, count=5):
+    """Up to `count` distinct edge core numbers in increasing order, taken
+    at the quantiles (i + 1/2) / count of the edge core distribution, so
+    that each stands for an equal share of the edges."""
+    ec = edge_levels(s, d, cores)
+    if ec.size == 0:
+        return []
+    q = (np.arange(count) + 0.5) / count
+    return sorted({int(x) for x in np.quantile(ec, q, method="lower")})
+
+
+def edges_at_level(s, d, cores, level, frac, rng):
+    """A uniform random share `frac` (rounded, at least one when any exist)
+    of the edges whose core number equals `level`, without replacement."""
+    idx = np.flatnonzero(edge_levels(s, d, cores) == level)
+    if idx.size == 0:
+        return s[:0].copy(), d[:0].copy()
+    cnt = max(1, int(round(frac * idx.size)))
+    pick = np.sort(rng.choice(idx, cnt, replace=False))
+    return s[pick].astype(np.int32), d[pick].astype(np.int32)
+
+
 def log_uniform_sizes(count: int, lo: float, hi: float, rng):
     """Sizes round(exp(U[ln lo, ln hi]))."""
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)

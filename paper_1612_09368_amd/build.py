@@ -20,22 +20,28 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every source (in parallel: one hipcc process each) and link."""
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                        if "packed-fp32-ops" not in l and l.strip())
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{msg}")
-        if verbose and msg:
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                text=True)))
+    objs, failed = [], []
+    for src, obj, proc in jobs:
+        out, _ = proc.communicate()
+        msg = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l and l.strip())
+        if proc.returncode != 0:
+            failed.append(f"hipcc failed for {src}:\n{msg}")
+        elif verbose and msg:
             print(msg, flush=True)
         objs.append(obj)
+    if failed:
+        raise RuntimeError("\n".join(failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.check_call(cmd)

@@ -1,11 +1,12 @@
 // Load-balanced walks over frontier queues (gfx950, wave64).
 //
 // A frontier is a list of vertices plus a list of chunk items for long
-// adjacency lists.  Each wave takes up to 64 queue entries: a vertex whose
-// list is short (len <= small) is walked by its own lane; longer lists are
-// walked by the whole wave, one vertex after another (coalesced reads);
-// lists longer than `large` never enter the vertex list -- the pusher splits
-// them into chunk items that separate waves walk.
+// adjacency lists.  Each wave takes a batch of up to 64 queue entries and
+// walks their lists laid end to end, one slot per lane per step, so short
+// and medium lists keep every lane busy; lists longer than `large` never
+// enter the vertex list -- the pusher splits them into chunk items that
+// separate waves walk.  Pushes go through per-wave LDS buffers so that a
+// queue tail takes one atomic per 64 or more entries.
 #pragma once
 #include "cm_internal.h"
 
@@ -86,37 +87,9 @@ __device__ __forceinline__ void push_vertex_wb(const KArgs &a, WaveBuf &b, int32
     }
 }
 
-// Team-stride over a vertex queue.  fl(v, L) runs on the owning lane for
-// short lists; fw(v, L) runs on the whole wave (uniform) for the others.
-// A wave takes `per` consecutive entries, per = ceil(n / waves) capped at
-// 64: a queue shorter than 64 entries per wave is spread over every wave
-// instead of leaving most waves idle while a few walk up to 64 lists each.
-// n must be the same in every thread of the team.
-template <class FL, class FW>
-__device__ __forceinline__ void for_vertices(const Team &T, const int32_t *q, int32_t n, const DevGraph &g,
-                                             int32_t small, FL &&fl, FW &&fw) {
-    const int nw = T.nwaves();
-    int per = (int)(((int64_t)n + nw - 1) / nw);
-    per = per < 1 ? 1 : (per > WAVE ? WAVE : per);
-    const int step = nw * per;
-    for (int32_t base = T.wave() * per; base < n; base += step) {
-        int32_t i = base + lane();
-        int32_t v = (lane() < per && i < n) ? q[i] : -1;
-        int32_t L = (v >= 0) ? g.len[v] : 0;
-        if (v >= 0 && L <= small) fl(v, L);
-        unsigned long long m = __ballot(v >= 0 && L > small);
-        while (m) {
-            int src = __ffsll((long long)m) - 1;
-            m &= m - 1ull;
-            int32_t vv = __shfl(v, src);
-            int32_t LL = __shfl(L, src);
-            fw(vv, LL);
-        }
-    }
-}
-
-// Same for an implicit identity list 0..n-1 (whole-graph passes); lists of
-// any length are accepted (long ones are walked by one wave).
+// Team-stride over the implicit identity list 0..n-1 (whole-graph passes).
+// fl(v, L) runs on the owning lane for lists of length <= small; fw(v, L)
+// runs on the whole wave (uniform) for the others, of any length.
 template <class FL, class FW>
 __device__ __forceinline__ void for_all_vertices(const Team &T, int32_t n, const DevGraph &g, int32_t small,
                                                  FL &&fl, FW &&fw) {
@@ -174,9 +147,12 @@ __device__ __forceinline__ void lane_walk(const DevGraph &g, int32_t v, int32_t 
 }
 
 
-// Team-stride over a vertex queue in batches of up to 64 entries per wave
-// (fewer when the queue is short, as in for_vertices): fb(v) runs on the
-// whole wave with lane j holding entry j of the batch (v < 0 past the end).
+// Team-stride over a vertex queue in batches of up to 64 entries per wave:
+// a wave takes `per` consecutive entries, per = ceil(n / waves) capped at
+// 64, so a queue shorter than 64 entries per wave is spread over every wave
+// instead of leaving most waves idle.  fb(v) runs on the whole wave with
+// lane j holding entry j of the batch (v < 0 past the end).  n must be the
+// same in every thread of the team.
 template <class FB>
 __device__ __forceinline__ void for_batches(const Team &T, const int32_t *q, int32_t n, FB &&fb) {
     const int nw = T.nwaves();
@@ -208,7 +184,7 @@ __device__ __forceinline__ void flat_walk(const DevGraph &g, int32_t v, int32_t 
     }
     const int32_t total = __shfl(incl, WAVE - 1);
     const int32_t excl = incl - L;
-    const int64_t off = (v >= 0 && L > 0) ? g.off[v] : 0;
+    const int64_t off = v >= 0 ? g.off[v] : 0;  // independent of L: issues with the length load
     for (int32_t base = 0; base < total; base += WAVE) {
         const int32_t e = base + lane();
         // owner of slot e: the last lane whose list starts at or before e

@@ -107,3 +107,21 @@ def test_ba_blocks_shape():
     assert 0.95 * k * n < s.size <= k * n + k * (k + 1) // 2
     deg = np.bincount(np.concatenate([s, d]), minlength=n)
     assert deg.min() >= 1 and deg.max() > 20 * 2 * k   # preferential attachment: heavy tail
+
+
+def test_level_selection():
+    import oracle
+    n, s, d = graphgen.rmat_graph(10, 8, graphgen.rng_for("lv"))
+    cores = oracle.bz_cores(n, s, d)
+    levels = graphgen.typical_levels(s, d, cores, 5)
+    assert levels == sorted(set(levels)) and 1 <= len(levels) <= 5
+    ec = np.minimum(cores[s], cores[d])
+    for k in levels:
+        a, b = graphgen.edges_at_level(s, d, cores, k, 0.2, graphgen.rng_for(f"lv{k}"))
+        assert (np.minimum(cores[a], cores[b]) == k).all()
+        assert a.size == max(1, round(0.2 * (ec == k).sum()))
+        kk = graphgen.keys_of(a, b)
+        assert np.unique(kk).size == kk.size and np.isin(kk, graphgen.keys_of(s, d)).all()
+    # the chosen levels split the edges into roughly equal shares
+    share = np.array([(ec <= k).mean() for k in levels])
+    assert share[0] >= 0.1 and share[-1] >= 0.9 - 1e-12

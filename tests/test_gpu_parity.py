@@ -451,3 +451,26 @@ def test_single_edge_regime(cm, dev, oracle_mod):
             (ref.insert_edges if kind == "insert" else ref.delete_edges)(a, b)
             assert st.iterations == a.size, (kind, st.iterations, a.size)
             check_state(g, ref, f"single-edge {kind}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_core_targeted_updates(cm, dev, oracle_mod, mode):
+    """Updates concentrated on one core level (the paper's experiment on the
+    core distribution of the updates): 20% of the edges of each typical edge
+    core number, deleted as one batch then inserted back as one batch."""
+    rng = graphgen.rng_for("core-levels")
+    n, s, d = graphgen.rmat_graph(12, 16, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    cores0 = ref.cores()
+    levels = graphgen.typical_levels(s, d, cores0, 5)
+    assert len(levels) >= 3
+    with new_graph(cm, n, s, d, dev, mode=mode) as g:
+        for k in levels:
+            a, b = graphgen.edges_at_level(s, d, cores0, k, 0.2, rng)
+            st = g.delete_edges(_t(a, dev), _t(b, dev))
+            assert ref.delete_edges(a, b)[0] == 0 and st.status == 0
+            check_state(g, ref, f"level {k} delete")
+            st = g.insert_edges(_t(a, dev), _t(b, dev))
+            assert ref.insert_edges(a, b)[0] == 0 and st.status == 0
+            check_state(g, ref, f"level {k} insert")
+        assert np.array_equal(g.cores(), cores0)
