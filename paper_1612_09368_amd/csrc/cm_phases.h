@@ -71,38 +71,38 @@ __device__ __forceinline__ void val_canon(const KArgs &a, const BatchCtx &bc, co
     }
 }
 
+// Queue the lists of x (one per lane, x < 0 for none) for the locate scan,
+// once per batch: the first lane to stamp x adds its chunk items.  Called
+// by every lane of the wave; one tail atomic per wave.
 __device__ __forceinline__ void mark_scan(const KArgs &a, const BatchCtx &bc, int32_t x) {
-    if (atomicExch(&a.g.bmark[x], bc.bstamp) != bc.bstamp) {
-        int32_t L = a.g.len[x];
-        int nch = nchunks(L, a.t.chunk);
-        if (nch > 0) {
-            int base = atomicAdd(&a.ctl->scan_tail, nch);
-            for (int c = 0; c < nch; ++c) {
-                if (base + c < a.b.scap) a.b.scanq[base + c] = chunk_item(x, c);
-                else atomicOr(&a.ctl->overflow, 1);
-            }
-        }
+    int nch = 0;
+    if (x >= 0 && atomicExch(&a.g.bmark[x], bc.bstamp) != bc.bstamp) nch = nchunks(a.g.len[x], a.t.chunk);
+    const int base = reserve_agg(&a.ctl->scan_tail, nch);
+    for (int c = 0; c < nch; ++c) {
+        if (base + c < a.b.scap) a.b.scanq[base + c] = chunk_item(x, c);
+        else atomicOr(&a.ctl->overflow, 1);
     }
 }
 
 // V2: duplicates inside the batch; choose the lists the locate scan reads
 // (insertion: the shorter endpoint list is enough to test existence;
-// deletion: both lists, to find both slots).
+// deletion: both lists, to find both slots).  Waves stride the batch
+// together so that mark_scan is called by whole waves.
 __device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc, const Team &T) {
-    for (int32_t i = T.rank; i < bc.s; i += T.size) {
-        int32_t e = a.b.err[i];
-        if (e != 0) continue;
-        if (a.b.hval[a.b.hslot[i]] != i) {
-            a.b.err[i] = ST_DUP;
-            continue;
+    for (int32_t w0 = T.rank - lane(); w0 < bc.s; w0 += T.size) {
+        const int32_t i = w0 + lane();
+        int32_t x = -1, y = -1;
+        if (i < bc.s && a.b.err[i] == 0) {
+            if (a.b.hval[a.b.hslot[i]] != i) {
+                a.b.err[i] = ST_DUP;
+            } else {
+                const int32_t u = a.b.eu[i], v = a.b.ev[i];
+                if (bc.inserting) x = a.g.len[u] <= a.g.len[v] ? u : v;
+                else { x = u; y = v; }
+            }
         }
-        int32_t u = a.b.eu[i], v = a.b.ev[i];
-        if (bc.inserting) {
-            mark_scan(a, bc, a.g.len[u] <= a.g.len[v] ? u : v);
-        } else {
-            mark_scan(a, bc, u);
-            mark_scan(a, bc, v);
-        }
+        mark_scan(a, bc, x);
+        if (!bc.inserting) mark_scan(a, bc, y);
     }
 }
 
@@ -1768,19 +1768,6 @@ __device__ __forceinline__ void prog_finish(const KArgs &a, bool inserting, long
     gbar(a.bar);
 }
 
-// One edge batch described by bc (validation through compaction).  Returns
-// 1 on a pool failure (nothing applied), else 0.
-__device__ __forceinline__ int prog_edge_batch(const KArgs &a, const BatchCtx &bc, int32_t &ep, long long &scanned,
-                                               int &pubs, int32_t &status, int32_t &fb, int32_t &valid,
-                                               int32_t &iters) {
-    iters = 0;
-    if (prog_prepare(a, bc, status, fb, valid)) return 1;
-    if (status != 0 || valid == 0) return 0;
-    iters = run_iterations(a, bc.inserting, 0x7fffffff, ep, scanned, pubs);
-    prog_finish(a, bc.inserting, scanned);
-    return 0;
-}
-
 // Replace the remaining list of the next iteration (read by the iteration
 // with stamp ep + 1) by the entries fill(i) accepts, i in [0, n).
 template <class F>
@@ -1896,9 +1883,18 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
     bc.n_ids = n_ids;
     prog_clear_stats(a, G);
     int32_t status = 0, fb = -1, valid = 0, iters = 0, vdone = 0;
+    // Each kind sets up below the edge batch to validate (vb), then runs up
+    // to two iteration passes and the compaction / statistics step.  One
+    // call site each keeps a single inlined copy of the validation and of
+    // the iteration machinery in the kernel.
+    enum { P_EDGES = 1, P_STARS_IN, P_NEWNEW, P_STARS_OUT };
+    BatchCtx vb = bc;
+    bool validate = B.s > 0;
+    int32_t vbad = 0x7fffffff;  // vertex deletion: smallest bad id index
+    const int32_t *ids = pd->src + B.off;
+    StarCtx sc{};
     if (B.kind == 3) {
         // vertex deletion
-        const int32_t *ids = pd->src + B.off;
         if (B.s > a.b.cap) {
             if (gtid() == 0) prog_record(a, out, -9, -1, 0, 0, 0);
             gbar(a.bar);
@@ -1924,41 +1920,21 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
         gbar(a.bar);
         const int32_t ng = ld_rlx(&c->vd_tail);
         vdone = ld_rlx(&c->vd_count);
-        const int32_t vbad = bad;
-        {
-            // the gathered edges are validated (slot location) and counted
-            // for compaction; then the ids leave as stars
-            BatchCtx eb = bc;
-            eb.src = pd->gsrc;
-            eb.dst = pd->gdst;
-            eb.sub = nullptr;
-            eb.s = ng;
-            eb.inserting = 0;
-            eb.hcap = hash_slots(ng);
-            eb.strict = 1;
-            int32_t efb = -1;
-            if (ng > 0) prog_prepare(a, eb, status, efb, valid);
-            if (status == 0) {
-                prog_refill(a, ep, B.s, [&](int32_t i, int32_t &x) {
-                    x = ids[i];
-                    return x >= 0 && x < n_ids && pd->firstidx[x] == i;
-                });
-                StarCtx sc{};
-                sc.mode = 2;
-                sc.ng = ng;
-                sc.firstidx = pd->firstidx;
-                iters = run_iterations(a, 0, 0x7fffffff, ep, scanned, pubs, sc);
-                if (ng > 0) prog_finish(a, false, scanned);
-            }
-        }
-        // a deletion needs no reservation, so status can only be 0 here
-        vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
-        gbar(a.bar);
-        if (gtid() == 0) prog_record(a, out, status, vbad == 0x7fffffff ? -1 : vbad, valid, iters, vdone);
-        gbar(a.bar);
-        return 0;
-    }
-    if (B.kind == 2) {
+        vbad = bad;
+        // the gathered edges are validated (slot location) and counted for
+        // compaction; then the ids leave as stars
+        vb.src = pd->gsrc;
+        vb.dst = pd->gdst;
+        vb.sub = nullptr;
+        vb.s = ng;
+        vb.inserting = 0;
+        vb.hcap = hash_slots(ng);
+        vb.strict = 1;
+        validate = ng > 0;
+        sc.mode = 2;
+        sc.ng = ng;
+        sc.firstidx = pd->firstidx;
+    } else if (B.kind == 2) {
         // vertex insertion: the new ids exist (core 0, empty list) before validation
         for (int32_t i = G.rank; i < B.nv; i += G.size) {
             int32_t v = B.v0 + i;
@@ -1969,27 +1945,41 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
             a.g.off[v] = 0;
         }
         gbar(a.bar);
-    }
-    if (B.kind == 2 && B.s > 0) {
-        if (pd->gsrc && B.s <= pd->gcap) {
+        if (B.s > 0 && pd->gsrc && B.s <= pd->gcap) {
             // device copy of the items: the star passes read them repeatedly
             for (int32_t i = G.rank; i < B.s; i += G.size) {
                 pd->gsrc[i] = bc.src[i];
                 pd->gdst[i] = bc.dst[i];
             }
             gbar(a.bar);
-            bc.src = pd->gsrc;
-            bc.dst = pd->gdst;
+            vb.src = pd->gsrc;
+            vb.dst = pd->gdst;
         }
-        if (prog_prepare(a, bc, status, fb, valid)) return 1;
-        if (status == 0 && valid > 0) {
-            StarCtx sc{};
-            sc.mode = 1;
-            sc.v0 = B.v0;
-            sc.nv = B.nv;
-            sc.s = B.s;
-            sc.src = bc.src;
-            sc.dst = bc.dst;
+        sc.mode = 1;
+        sc.v0 = B.v0;
+        sc.nv = B.nv;
+        sc.s = B.s;
+        sc.src = vb.src;
+        sc.dst = vb.dst;
+    }
+    int32_t vfb = -1;
+    if (validate && prog_prepare(a, vb, status, vfb, valid)) return 1;
+    int pass0 = 0, pass1 = 0;  // the iteration passes, 0 = none
+    if (B.kind == 3) {
+        // a deletion needs no reservation, so status can only be 0 here
+        if (status == 0) pass0 = P_STARS_OUT;
+    } else if (status == 0 && valid > 0) {
+        if (B.kind == 2) {
+            pass0 = P_STARS_IN;
+            pass1 = P_NEWNEW;
+        } else {
+            pass0 = P_EDGES;  // the valid items are already the remaining list
+        }
+    }
+    for (int p = 0; p < 2; ++p) {
+        const int kind = p == 0 ? pass0 : pass1;
+        if (kind == 0) break;
+        if (kind == P_STARS_IN) {
             // stars: the new vertices with at least one item
             prog_refill(a, ep, B.nv, [&](int32_t i, int32_t &x) {
                 int32_t lo, hi;
@@ -1997,19 +1987,31 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
                 x = i;
                 return hi > lo;
             });
-            iters = run_iterations(a, 1, 0x7fffffff, ep, scanned, pubs, sc);
+        } else if (kind == P_NEWNEW) {
             // edges between two new vertices: ordinary iterations
             prog_refill(a, ep, B.s, [&](int32_t j, int32_t &x) {
-                const int32_t u = bc.src[j], w = bc.dst[j];
+                const int32_t u = vb.src[j], w = vb.dst[j];
                 x = j;
                 return a.b.err[j] == 0 && u >= B.v0 && u < B.v0 + B.nv && w >= B.v0 && w < B.v0 + B.nv;
             });
-            iters += run_iterations(a, 1, 0x7fffffff, ep, scanned, pubs);
-            prog_finish(a, true, scanned);
+        } else if (kind == P_STARS_OUT) {
+            prog_refill(a, ep, B.s, [&](int32_t i, int32_t &x) {
+                x = ids[i];
+                return x >= 0 && x < n_ids && pd->firstidx[x] == i;
+            });
         }
-    } else if (B.s > 0) {
-        if (prog_edge_batch(a, bc, ep, scanned, pubs, status, fb, valid, iters)) return 1;
+        const bool star = kind == P_STARS_IN || kind == P_STARS_OUT;
+        iters += run_iterations(a, vb.inserting, 0x7fffffff, ep, scanned, pubs, star ? sc : StarCtx{});
     }
+    if (pass0 != 0 && validate) prog_finish(a, vb.inserting, scanned);
+    if (B.kind == 3) {
+        vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
+        gbar(a.bar);
+        if (gtid() == 0) prog_record(a, out, status, vbad == 0x7fffffff ? -1 : vbad, valid, iters, vdone);
+        gbar(a.bar);
+        return 0;
+    }
+    fb = vfb;
     if (B.kind == 2) {
         vdone = status == 0 ? B.nv : 0;
         if (status != 0) {
