@@ -1126,7 +1126,9 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     auto claim = [&](int32_t w, int32_t k) -> bool {
         if (w < 0) return false;
         if (g.core[w] != k || g.mcd[w] <= k) return false;
-        if (ld_rlx(&g.stamp[w]) == ep) return false;  // already claimed: skip the atomic
+        // already claimed: skip the atomic.  A plain load may return an
+        // older stamp (then the atomic decides), never a later one.
+        if (g.stamp[w] == ep) return false;
         if (atomicExch(&g.stamp[w], ep) == ep) return false;
         g.cd[w] = 0;
         return true;
@@ -1239,8 +1241,10 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     const int32_t ep = it.ep;
     auto hit = [&](int32_t w, int32_t k) -> bool {
         if (w < 0 || g.core[w] != k || g.stamp[w] != ep) return false;
-        // a counter already at or below k has crossed once: w is evicted
-        if (ld_rlx(&g.cd[w]) <= k) return false;
+        // a counter already at or below k has crossed once: w is evicted.
+        // Counters only fall during eviction, so a plain load, which may
+        // return an older value, never skips a live counter.
+        if (g.cd[w] <= k) return false;
         return atomicSub(&g.cd[w], 1) == k + 1;
     };
     WaveBuf bq = wave_buf(0);
