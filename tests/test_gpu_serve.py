@@ -146,3 +146,45 @@ def test_serve_refuses_other_calls(cm):
     srv.stop()
     assert g.cores().size == 500
     g.close()
+
+
+def test_serve_stream_replica_scale18(cm, oracle_mod):
+    """The serving workload's stream on a scale-18 R-MAT replica (200
+    requests, sizes log-uniform in [1, 10^5], 40% edge insert, 40% edge
+    delete, 10% vertex insert, 10% vertex delete), served in 20 chunks, each
+    chunk continuously batched: every request's status (and the applied count
+    of edge requests) equals the oracle's, and the core numbers equal the
+    oracle's at the end of every chunk (20 checkpoints, the last one the final
+    state)."""
+    from paper_1612_09368_amd import serve
+    n, s, d, reqs = graphgen.serve_stream(18, 200, graphgen.rng_for("serve-c5-replica"))
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    new_ids = sum(len(r[1]) - 1 for r in reqs if r[0] == "vins")
+    g = cm.Graph(mode=cm.MODE_PERSISTENT)
+    g.load(n, s, d)
+    g.decompose()
+    assert np.array_equal(g.cores(), ref.cores())
+    nchunk = 20
+    bounds = np.linspace(0, len(reqs), nchunk + 1).astype(int)
+    for c in range(nchunk):
+        chunk = reqs[bounds[c]:bounds[c + 1]]
+        srv = serve.Server(g, ring_requests=256, ring_items=1 << 24, max_items=1 << 23,
+                           vertex_headroom=new_ids + 1024, idle_ms=20)
+        res = serve.run_stream(srv, chunk)
+        srv.stop()
+        for j, (r, x) in enumerate(zip(chunk, res["stats"])):
+            if r[0] == "ins":
+                want = ref.insert_edges(r[1], r[2])
+            elif r[0] == "del":
+                want = ref.delete_edges(r[1], r[2])
+            elif r[0] == "vins":
+                want = ref.insert_vertices(r[1], r[2], keep_failed_ids=True)
+            else:
+                want = ref.delete_vertices(r[1])
+            tag = (c, j, r[0])
+            assert x.status == want[0], tag
+            if r[0] in ("ins", "del"):
+                assert x.applied == want[2], tag
+        assert np.array_equal(g.cores(), ref.cores()), f"checkpoint {c}"
+    assert g.num_edges() == ref.num_edges()
+    g.close()
