@@ -52,6 +52,11 @@ struct cm_graph {
     unsigned long long *hu64 = nullptr;  // pinned host scratch
     int32_t *firstidx = nullptr;      // [n_cap] vertex-deletion duplicate check
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // plain form: outcomes of the maintenance launches in flight (pinned) and
+    // their start / end events
+    static constexpr int LSLOTS = 4;
+    LaunchOut *lout = nullptr;
+    hipEvent_t lev[LSLOTS][2] = {};
     int coop_prog = 0;        // cooperative grid of the batch program kernel
     // batch programs (cm_run_batches)
     ProgDesc *d_prog = nullptr;
@@ -498,6 +503,68 @@ void reserve(cm_graph *g, int cur) {
     throw Fail{CM_E_NOMEM};
 }
 
+// Plain form: one cooperative launch per superior edge set.  The next
+// launch is queued before the host reads the outcome of the current one
+// (from its pinned LaunchOut slot, after its end event), so the device does
+// not idle while the host decides; a launch that finds no edges left runs no
+// iteration and changes nothing, so the last queued launch of a batch is an
+// empty one.
+void run_plain(cm_graph *g, KArgs a, double &kms, int &launches) {
+    hipStream_t st = g->stream;
+    constexpr int depth = 2;  // launches in flight
+    int64_t issued = 0, consumed = 0;
+    auto issue = [&]() {
+        const int s = (int)(issued % cm_graph::LSLOTS);
+        a.lout = &g->lout[s];
+        HIPCHK(hipEventRecord(g->lev[s][0], st));
+        HIPCHK(maintain_coop(a, g->coop_maint, st));
+        HIPCHK(hipEventRecord(g->lev[s][1], st));
+        ++issued;
+    };
+    // wait for launch `consumed`, account for it and return its outcome
+    auto take = [&]() {
+        const int s = (int)(consumed % cm_graph::LSLOTS);
+        HIPCHK(hipEventSynchronize(g->lev[s][1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g->lev[s][0], g->lev[s][1]));
+        kms += ms;
+        ++launches;
+        ++consumed;
+        const LaunchOut o = g->lout[s];
+        if (o.aborted) {
+            g->poisoned = true;
+            g->err = "internal: grid barrier wait gave up";
+            throw Fail{CM_E_INTERNAL};
+        }
+        if (o.overflow) {
+            g->poisoned = true;
+            g->err = "internal queue overflow (code " + std::to_string(o.overflow) + ")";
+            throw Fail{CM_E_INTERNAL};
+        }
+        return o;
+    };
+    issue();
+    for (;;) {
+        if (issued - consumed < depth) issue();
+        const LaunchOut o = take();
+        if (o.rem_next == 0) break;
+        if (o.iters == 0) {
+            g->poisoned = true;
+            g->err = "maintenance launch made no progress";
+            throw Fail{CM_E_INTERNAL};
+        }
+    }
+    while (consumed < issued) {
+        const LaunchOut o = take();
+        if (o.iters != 0) {  // a launch queued after the last set found edges
+            g->poisoned = true;
+            g->err = "internal: a queued maintenance launch ran after the batch ended";
+            throw Fail{CM_E_INTERNAL};
+        }
+    }
+    sync_ctl(g);
+}
+
 // Run the iterations of a validated batch (list `cur`) to completion.
 void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
     hipStream_t st = g->stream;
@@ -506,26 +573,31 @@ void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
     a.max_iters = g->cfg.mode == CM_MODE_PERSISTENT ? INT_MAX : 1;
     double kms = 0.0;
     int launches = 0;
-    for (;;) {
-        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
-        HIPCHK(maintain_coop(a, g->coop_maint, st));
-        if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
-        ++launches;
-        sync_ctl(g);
-        check_abort(g);
-        check_overflow(g);
-        if (g->cfg.timing) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-            kms += ms;
-        }
+    if (g->cfg.mode != CM_MODE_PERSISTENT) {
+        run_plain(g, a, kms, launches);
         g->epoch = g->hctl->epoch;
-        int nxt = (g->epoch + 1) & 1;
-        if (g->hctl->rem_count[nxt] == 0) break;
-        if (g->hctl->iters_done == 0) {
-            g->poisoned = true;
-            g->err = "maintenance launch made no progress";
-            throw Fail{CM_E_INTERNAL};
+    } else {
+        for (;;) {
+            if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev0, st));
+            HIPCHK(maintain_coop(a, g->coop_maint, st));
+            if (g->cfg.timing) HIPCHK(hipEventRecord(g->ev1, st));
+            ++launches;
+            sync_ctl(g);
+            check_abort(g);
+            check_overflow(g);
+            if (g->cfg.timing) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+                kms += ms;
+            }
+            g->epoch = g->hctl->epoch;
+            int nxt = (g->epoch + 1) & 1;
+            if (g->hctl->rem_count[nxt] == 0) break;
+            if (g->hctl->iters_done == 0) {
+                g->poisoned = true;
+                g->err = "maintenance launch made no progress";
+                throw Fail{CM_E_INTERNAL};
+            }
         }
     }
     if (stats) {
@@ -895,6 +967,10 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         dev_alloc(g, &g->u64_scratch, 4);
         HIPCHK(hipEventCreate(&g->ev0));
         HIPCHK(hipEventCreate(&g->ev1));
+        HIPCHK(hipHostMalloc((void **)&g->lout, sizeof(LaunchOut) * cm_graph::LSLOTS, hipHostMallocDefault));
+        std::memset(g->lout, 0, sizeof(LaunchOut) * cm_graph::LSLOTS);
+        for (auto &pr : g->lev)
+            for (auto &e : pr) HIPCHK(hipEventCreate(&e));
         HIPCHK(hipStreamSynchronize(g->stream));
     } catch (const Fail &f) {
         cm_destroy(g);
@@ -920,6 +996,10 @@ void cm_destroy(cm_graph *g) {
     if (g->hu64) (void)hipHostFree(g->hu64);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
+    for (auto &pr : g->lev)
+        for (auto &e : pr)
+            if (e) (void)hipEventDestroy(e);
+    if (g->lout) (void)hipHostFree(g->lout);
     delete g;
 }
 

@@ -198,6 +198,18 @@ constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
 
 struct ProgDesc;
 
+// Outcome of one maintenance launch, written at its end by global thread 0
+// into pinned host memory (one slot per launch in flight), so that the host
+// can read it while the next launch already runs.
+struct LaunchOut {
+    int32_t epoch;     // last iteration stamp used
+    int32_t iters;     // iterations run
+    int32_t rem_next;  // edges left for the next iteration
+    int32_t overflow;  // queue overflow code (0 = none)
+    int32_t aborted;   // a grid barrier wait gave up
+    int32_t pad[3];
+};
+
 struct KArgs {
     DevGraph g;
     DevBatch b;
@@ -212,6 +224,7 @@ struct KArgs {
     int32_t bstamp;      // batch stamp (bmark values bstamp, bstamp + 1)
     int32_t cur;         // remaining list that receives the validated batch
     int32_t strict;      // packed sub-batches: drop a sub-batch with an invalid item
+    LaunchOut *lout;     // maintenance launch outcome (pinned host) or null
 };
 
 // Per-batch parameters of the validation / reservation steps.

@@ -373,6 +373,14 @@ __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
     if (gtid() == 0) {
         a.ctl->epoch = ep;
         a.ctl->iters_done = n;
+        if (a.lout) {
+            // every step ended at a grid barrier, so the counters are final
+            a.lout->epoch = ep;
+            a.lout->iters = n;
+            a.lout->rem_next = ld_rlx(&a.ctl->rem_count[(ep + 1) & 1]);
+            a.lout->overflow = ld_rlx(&a.ctl->overflow);
+            a.lout->aborted = bar_aborted(a.bar) ? 1 : 0;
+        }
     }
 }
 
