@@ -78,8 +78,10 @@ typedef struct cm_config {
     int32_t mode;               /* CM_MODE_PLAIN or CM_MODE_PERSISTENT */
     int32_t partition_rounds;   /* selection rounds per superior edge set (1..8; 0 = default) */
     int32_t blocks_per_cu;      /* cooperative grid occupancy (0 = default) */
-    int32_t small_degree;       /* lists up to this length are walked by one lane (0 = default) */
-    int32_t large_degree;       /* lists above this length are split into chunks (0 = default) */
+    int32_t small_degree;       /* whole-graph passes and the asynchronous cascade form walk lists up to
+                                   this length with one lane, longer ones with a wave (0 = default) */
+    int32_t large_degree;       /* lists above this length are split into chunks; shorter ones are walked
+                                   flattened, up to 64 lists per wave (0 = default) */
     int32_t chunk;              /* chunk length for long lists (0 = default) */
     int32_t local_edges;        /* selection / apply steps up to this many edges run in one
                                    workgroup instead of the whole grid (0 = default) */

@@ -2,10 +2,13 @@
 
 The parameters are the ones of ``cm_config`` that change speed but never
 results: workgroups per compute unit of the cooperative grid, the list
-lengths that separate per-lane walks, per-wave walks and chunked lists
-(``small_degree``, ``large_degree``, ``chunk``), the claim rounds of the
-partition, and the sizes up to which a step runs inside one workgroup
-(``local_edges``, ``local_items``, ``local_work``).
+length above which a list is split into chunks and the chunk length
+(``large_degree``, ``chunk``; shorter lists are walked flattened, up to 64
+per wave), the list length walked by one lane in whole-graph passes and in
+the asynchronous cascade form (``small_degree``), the cascade form itself
+(``async_steps``), the claim rounds of the partition, and the sizes up to
+which a step runs inside one workgroup (``local_edges``, ``local_items``,
+``local_work``).
 
 Search: coordinate descent from the library defaults.  For each parameter in
 turn every candidate value is tried with the others held at the best values

@@ -182,7 +182,7 @@ struct DevQueues {
 };
 
 struct Tune {
-    int32_t small_deg;   // list length walked by one lane
+    int32_t small_deg;   // list length walked by one lane (whole-graph passes, asynchronous cascades)
     int32_t large_deg;   // longer lists are chunked
     int32_t chunk;       // chunk length
     int32_t rounds;      // selection rounds per iteration
