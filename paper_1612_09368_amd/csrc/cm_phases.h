@@ -84,10 +84,25 @@ __device__ __forceinline__ void mark_scan(const KArgs &a, const BatchCtx &bc, in
     }
 }
 
-// V2: duplicates inside the batch; choose the lists the locate scan reads
-// (insertion: the shorter endpoint list is enough to test existence;
-// deletion: both lists, to find both slots).  Waves stride the batch
-// together so that mark_scan is called by whole waves.
+// Lists up to this length are searched by the item itself (one or two
+// cache lines); longer ones are read once by the locate scan, every entry
+// probing the batch hash.
+constexpr int32_t VAL_SHORT = 32;
+
+// Absolute slot of `target` in x's list, or -1.
+__device__ __forceinline__ int64_t find_in_list(const DevGraph &g, int32_t x, int32_t target) {
+    const int64_t o = g.off[x];
+    const int32_t L = g.len[x];
+    for (int32_t s = 0; s < L; ++s)
+        if (g.nbr[o + s] == target) return o + s;
+    return -1;
+}
+
+// V2: duplicates inside the batch; locate the valid items (insertion: the
+// shorter endpoint list is enough to test existence; deletion: both lists,
+// to find both slots).  A short list is searched by the item; a long one is
+// queued for the locate scan.  Waves stride the batch together so that
+// mark_scan is called by whole waves.
 __device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc, const Team &T) {
     for (int32_t w0 = T.rank - lane(); w0 < bc.s; w0 += T.size) {
         const int32_t i = w0 + lane();
@@ -97,8 +112,20 @@ __device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc,
                 a.b.err[i] = ST_DUP;
             } else {
                 const int32_t u = a.b.eu[i], v = a.b.ev[i];
-                if (bc.inserting) x = a.g.len[u] <= a.g.len[v] ? u : v;
-                else { x = u; y = v; }
+                const int32_t lu = a.g.len[u], lv = a.g.len[v];
+                if (bc.inserting) {
+                    const int32_t p = lu <= lv ? u : v, q = lu <= lv ? v : u;
+                    if ((lu <= lv ? lu : lv) <= VAL_SHORT) {
+                        if (find_in_list(a.g, p, q) >= 0) a.b.err[i] = ST_EXISTS;
+                    } else {
+                        x = p;
+                    }
+                } else {
+                    if (lu <= VAL_SHORT) a.b.su[i] = find_in_list(a.g, u, v);
+                    else x = u;
+                    if (lv <= VAL_SHORT) a.b.sv[i] = find_in_list(a.g, v, u);
+                    else y = v;
+                }
             }
         }
         mark_scan(a, bc, x);
