@@ -474,3 +474,72 @@ def test_core_targeted_updates(cm, dev, oracle_mod, mode):
             assert ref.insert_edges(a, b)[0] == 0 and st.status == 0
             check_state(g, ref, f"level {k} insert")
         assert np.array_equal(g.cores(), cores0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_empty_and_degenerate_batches(cm, dev, oracle_mod, mode):
+    """Empty graph and empty batches; a clique built in one batch (every
+    vertex is the constrained endpoint of all its edges: one level, the
+    largest conflict) and torn down in one batch; an all-invalid batch in
+    filter mode; a graph of one vertex."""
+    n = 50
+    e = np.zeros(0, dtype=np.int32)
+    with new_graph(cm, n, e, e, dev, mode=mode) as g:
+        assert (g.cores() == 0).all() and g.num_edges() == 0
+        st = g.insert_edges(_t(e, dev), _t(e, dev))
+        assert st.applied == 0 and st.iterations == 0
+        st = g.delete_edges(_t(e, dev), _t(e, dev))
+        assert st.applied == 0 and st.iterations == 0
+        pairs = np.array(list(itertools.combinations(range(3, 13), 2)), dtype=np.int32)
+        a, b = pairs[:, 0].copy(), pairs[:, 1].copy()
+        ref = oracle_mod.DynamicGraph(n, e, e)
+        st = g.insert_edges(_t(a, dev), _t(b, dev))
+        ref.insert_edges(a, b)
+        assert st.applied == a.size
+        check_state(g, ref, "clique insert")
+        want = np.zeros(n, np.int32)
+        want[3:13] = 9
+        assert np.array_equal(g.cores(), want)   # closed form: K_10 has core 9
+        st = g.delete_edges(_t(b, dev), _t(a, dev))
+        ref.delete_edges(b, a)
+        assert st.applied == a.size
+        check_state(g, ref, "clique delete")
+        assert (g.cores() == 0).all() and g.num_edges() == 0
+    with new_graph(cm, n, e, e, dev, mode=mode, strict=False) as g:
+        bad_a = np.array([0, 7, 60, -1, 4], dtype=np.int32)
+        bad_b = np.array([0, 7, 1, 2, 4], dtype=np.int32)
+        st = g.insert_edges(_t(bad_a, dev), _t(bad_b, dev))
+        assert st.applied == 0 and st.dropped == bad_a.size and st.first_bad == 0
+        st = g.delete_edges(_t(np.array([1, 2], np.int32), dev), _t(np.array([2, 3], np.int32), dev))
+        assert st.applied == 0 and st.dropped == 2
+        assert (g.cores() == 0).all() and g.num_edges() == 0
+    one = np.zeros(0, dtype=np.int32)
+    with new_graph(cm, 1, one, one, dev, mode=mode) as g:
+        assert np.array_equal(g.cores(), np.zeros(1, np.int32))
+        st, stats = g.insert_edges(_t(np.zeros(1, np.int32), dev), _t(np.zeros(1, np.int32), dev), check=False)
+        assert st == cm.E_SELF_LOOP and stats.first_bad == 0
+
+
+@pytest.mark.slow
+def test_chung_lu_full_size_batched(cm, dev, oracle_mod):
+    """The benchmark's Chung-Lu configuration (n = 1,000,000, m = 10,000,000)
+    in the batched form: one insertion batch of 100,000 degree-weighted
+    non-edges and one deletion batch of 100,000 existing edges in one
+    persistent launch replayed from a hipGraph; the final core numbers and
+    SD against the oracle."""
+    rng = graphgen.rng_for("cl-1m-batched")
+    n = 1_000_000
+    s, d = graphgen.chung_lu_graph(n, 10_000_000, 2.1, 50_000.0, rng)
+    es = graphgen.EdgeSet(s, d)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    a, b = graphgen.weighted_non_edges(100_000, es, rng)
+    es.insert(a, b)
+    x, y = graphgen.existing_edges(100_000, es, rng)
+    ref.insert_edges(a, b)
+    ref.delete_edges(x, y)
+    xs, ys = np.concatenate([a, x]), np.concatenate([b, y])
+    with new_graph(cm, n, s, d, dev, mode=1, use_graph=True) as g:
+        res, _ = g.run_batches([cm.BATCH_INSERT, cm.BATCH_DELETE], [0, a.size, a.size + x.size],
+                               _t(xs, dev), _t(ys, dev))
+        assert [r.status for r in res] == [0, 0] and [r.applied for r in res] == [a.size, x.size]
+        check_state(g, ref, "cl full batched")
