@@ -504,6 +504,79 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
     }
 }
 
+// Apply one selected edge i (Algorithm 1 / 5, the set's insertion or
+// deletion): list append or tombstones, SD of its constrained endpoints,
+// roots.  A constrained endpoint keeps at most one selected edge, so its SD
+// and root status depend on this edge alone.  Every lane may call it (sel
+// selects the applying lanes; pushes are wave-aggregated).
+__device__ __forceinline__ void apply_edge_insert(const KArgs &a, const Iter &it, int32_t i, bool sel) {
+    Ctl *c = a.ctl;
+    bool ru = false, rv = false;
+    int32_t u = -1, v = -1;
+    if (sel) {
+        u = a.b.eu[i];
+        v = a.b.ev[i];
+        int32_t cu = a.g.core[u], cv = a.g.core[v];
+        int32_t k = cu < cv ? cu : cv;
+        int32_t pu = atomicAdd(&a.g.len[u], 1);
+        if (pu < a.g.cap[u]) a.g.nbr[a.g.off[u] + pu] = v;
+        else atomicOr(&c->overflow, 2);
+        int32_t pv = atomicAdd(&a.g.len[v], 1);
+        if (pv < a.g.cap[v]) a.g.nbr[a.g.off[v] + pv] = u;
+        else atomicOr(&c->overflow, 2);
+        if (cu == k) {
+            int32_t m = atomicAdd(&a.g.mcd[u], 1) + 1;
+            if (m > k) { a.g.stamp[u] = it.ep; a.g.cd[u] = 0; ru = true; }
+        }
+        if (cv == k) {
+            int32_t m = atomicAdd(&a.g.mcd[v], 1) + 1;
+            if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; rv = true; }
+        }
+    }
+    // Roots enter the vertex queue whatever their length: other threads may
+    // still be appending to the same list in this step, so a chunk count
+    // taken now could be stale.  The first expansion round splits long root
+    // lists into chunks once lengths are final.
+    if (a.t.async_steps) {
+        apush(a, 0, aq_item(AQ_V, u, 0), ru);
+        apush(a, 0, aq_item(AQ_V, v, 0), rv);
+    } else {
+        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
+        push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv, &c->overflow);
+    }
+}
+
+__device__ __forceinline__ void apply_edge_delete(const KArgs &a, const Iter &it, int32_t i, bool sel) {
+    Ctl *c = a.ctl;
+    bool pu = false, pv = false;
+    int32_t u = -1, v = -1;
+    if (sel) {
+        u = a.b.eu[i];
+        v = a.b.ev[i];
+        int32_t cu = a.g.core[u], cv = a.g.core[v];
+        int32_t k = cu < cv ? cu : cv;
+        a.g.nbr[a.b.su[i]] = TOMB;
+        a.g.nbr[a.b.sv[i]] = TOMB;
+        if (cu == k) {
+            int32_t m = atomicSub(&a.g.mcd[u], 1) - 1;
+            if (m < k) { a.g.stamp[u] = it.ep; pu = true; }
+        }
+        if (cv == k) {
+            int32_t m = atomicSub(&a.g.mcd[v], 1) - 1;
+            if (m < k) { a.g.stamp[v] = it.ep; pv = true; }
+        }
+    }
+    if (a.t.async_steps) {
+        apush_vertex(a, 1, AQ_CH, u, pu);
+        apush_vertex(a, 1, AQ_CH, v, pv);
+    } else {
+        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], u, pu);
+        push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, pv);
+    }
+    push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, u, pu);
+    push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, pv);
+}
+
 __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int r, const Team &T) {
     Ctl *c = a.ctl;
     const bool last = r == a.t.rounds - 1;
@@ -528,7 +601,12 @@ __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int 
             if (fu) a.g.matched[u] = mstamp;
             if (fv) a.g.matched[v] = mstamp;
         }
-        push_agg<int32_t>(a.b.sel, a.b.cap, &c->sel_count, i, win, &c->overflow);
+        // a winner applies itself in this step (no separate apply step)
+        if (it.ins) apply_edge_insert(a, it, i, win);
+        else apply_edge_delete(a, it, i, win);
+        const unsigned long long wm = __ballot(win);
+        if (wm && lane() == __ffsll((long long)__ballot(1)) - 1)
+            atomicAdd(&c->st_selected, (unsigned long long)__popcll(wm));
         push_agg<int32_t>(a.b.rem[it.cur ^ 1], a.b.cap, &c->rem_count[it.cur ^ 1], i, last && !win,
                           &c->overflow);
     }
@@ -541,73 +619,14 @@ __device__ __forceinline__ void apply_insert(const KArgs &a, const Iter &it, con
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
     if (T.lead()) c->st_selected += (unsigned long long)n;
-    for (int32_t idx = T.rank; idx < n; idx += T.size) {
-        int32_t i = a.b.sel[idx];
-        int32_t u = a.b.eu[i], v = a.b.ev[i];
-        int32_t cu = a.g.core[u], cv = a.g.core[v];
-        int32_t k = cu < cv ? cu : cv;
-        int32_t pu = atomicAdd(&a.g.len[u], 1);
-        if (pu < a.g.cap[u]) a.g.nbr[a.g.off[u] + pu] = v;
-        else atomicOr(&c->overflow, 2);
-        int32_t pv = atomicAdd(&a.g.len[v], 1);
-        if (pv < a.g.cap[v]) a.g.nbr[a.g.off[v] + pv] = u;
-        else atomicOr(&c->overflow, 2);
-        bool ru = false, rv = false;
-        if (cu == k) {
-            int32_t m = atomicAdd(&a.g.mcd[u], 1) + 1;
-            if (m > k) { a.g.stamp[u] = it.ep; a.g.cd[u] = 0; ru = true; }
-        }
-        if (cv == k) {
-            int32_t m = atomicAdd(&a.g.mcd[v], 1) + 1;
-            if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; rv = true; }
-        }
-        // Roots enter the vertex queue whatever their length: other threads
-        // may still be appending to the same list in this step, so a chunk
-        // count taken now could be stale.  The first expansion round splits
-        // long root lists into chunks once lengths are final.
-        if (a.t.async_steps) {
-            apush(a, 0, aq_item(AQ_V, u, 0), ru);
-            apush(a, 0, aq_item(AQ_V, v, 0), rv);
-        } else {
-            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], u, ru, &c->overflow);
-            push_agg<int32_t>(a.q.fq[0], a.q.vcap, &c->fq_tail[0], v, rv, &c->overflow);
-        }
-    }
+    for (int32_t idx = T.rank; idx < n; idx += T.size) apply_edge_insert(a, it, a.b.sel[idx], true);
 }
 
-// Delete the selected set from G (Algorithm 5) and update SD of the
-// constrained endpoints; a root whose SD on G minus the set falls below its
-// core is peeled at once (Algorithm 6, test cd < k).
 __device__ __forceinline__ void apply_delete(const KArgs &a, const Iter &it, const Team &T) {
     Ctl *c = a.ctl;
     const int32_t n = qlen(&c->sel_count, a.b.cap);
     if (T.lead()) c->st_selected += (unsigned long long)n;
-    for (int32_t idx = T.rank; idx < n; idx += T.size) {
-        int32_t i = a.b.sel[idx];
-        int32_t u = a.b.eu[i], v = a.b.ev[i];
-        int32_t cu = a.g.core[u], cv = a.g.core[v];
-        int32_t k = cu < cv ? cu : cv;
-        a.g.nbr[a.b.su[i]] = TOMB;
-        a.g.nbr[a.b.sv[i]] = TOMB;
-        bool pu = false, pv = false;
-        if (cu == k) {
-            int32_t m = atomicSub(&a.g.mcd[u], 1) - 1;
-            if (m < k) { a.g.stamp[u] = it.ep; pu = true; }
-        }
-        if (cv == k) {
-            int32_t m = atomicSub(&a.g.mcd[v], 1) - 1;
-            if (m < k) { a.g.stamp[v] = it.ep; pv = true; }
-        }
-        if (a.t.async_steps) {
-            apush_vertex(a, 1, AQ_CH, u, pu);
-            apush_vertex(a, 1, AQ_CH, v, pv);
-        } else {
-            push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], u, pu);
-            push_vertex(a, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, pv);
-        }
-        push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, u, pu);
-        push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, pv);
-    }
+    for (int32_t idx = T.rank; idx < n; idx += T.size) apply_edge_delete(a, it, a.b.sel[idx], true);
 }
 
 // Positive traversal (Algorithm 3) as level-synchronous rounds over all
@@ -1523,23 +1542,28 @@ __device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
 }
 
 // Step that follows pc (reads the counters pc's step published).
+// First cascade step once the set is applied (roots queued).
+__device__ __forceinline__ PC after_apply(const KArgs &a, const Iter &it) {
+    if (a.t.async_steps) {
+        if (it.ins && ld_rlx(&a.ctl->aq_tail[0]) > 0) return PC{S_EXPAND, 0};
+        if (ld_rlx(&a.ctl->aq_tail[1]) == 0) return PC{S_CORE, 0};
+        return it.ins ? PC{S_EVICT, 0} : PC{S_PEEL, 0};
+    }
+    if (it.ins) {
+        if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
+        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
+    }
+    return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
+}
+
 __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &pc) {
     switch (pc.step) {
     case S_CLAIM: return PC{S_SELECT, pc.r};
     case S_SELECT:
         if (it.sc.mode) return PC{S_APPLY, 0};
-        return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : PC{S_APPLY, 0};
-    case S_APPLY:
-        if (a.t.async_steps) {
-            if (it.ins && ld_rlx(&a.ctl->aq_tail[0]) > 0) return PC{S_EXPAND, 0};
-            if (ld_rlx(&a.ctl->aq_tail[1]) == 0) return PC{S_CORE, 0};
-            return it.ins ? PC{S_EVICT, 0} : PC{S_PEEL, 0};
-        }
-        if (it.ins) {
-            if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
-            return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
-        }
-        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
+        // edge sets: the select steps applied their winners
+        return pc.r + 1 < a.t.rounds ? PC{S_CLAIM, pc.r + 1} : after_apply(a, it);
+    case S_APPLY: return after_apply(a, it);
     case S_EXPAND:
         if (a.t.async_steps) return ld_rlx(&a.ctl->aq_tail[1]) > 0 ? PC{S_EVICT, 0} : PC{S_CORE, 0};
         if (!slot_empty_f(a, (pc.r + 1) % 3)) return PC{S_EXPAND, pc.r + 1};
