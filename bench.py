@@ -256,6 +256,10 @@ def bench_cl1m(args, cm, torch):
     if kernel_sources_sha256() == TRAFFIC["sources_sha256"]:
         out["roofline"]["traffic"] = TRAFFIC["bytes_per_launch"]
         out["roofline"]["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        # measured HBM rate: counted bytes per launch over this run's average launch time
+        tgbs = TRAFFIC["bytes_per_launch"] / (out["roofline"]["avg_launch_us"] * 1e-6) / 1e9
+        out["roofline"]["traffic_gbs"] = tgbs
+        out["roofline"]["traffic_frac"] = tgbs / HBM_PEAK_GBS
     out["latency_ms"] = {"p50": pct(plain["lat"], 50), "p99": pct(plain["lat"], 99),
                          "per": "batch of 100000 edges"}
     out["tuning"] = tuning
