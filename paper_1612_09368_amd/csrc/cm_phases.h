@@ -1162,21 +1162,32 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     const int bc = r & 1, bn = bc ^ 1;
     const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
     const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
-    const int32_t nx = qlen(&c->fx_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->fq_tail[sx] = 0; c->fh_tail[sx] = 0; c->fx_tail[sx] = 0;
         c->st_rounds += 1;
     }
     const int32_t ep = it.ep;
 
-    auto claim = [&](int32_t w, int32_t k) -> bool {
+    // One pass per list: count CSD and claim every level-k neighbour w with
+    // SD(w) > k on the way, before the vertex knows whether it expands.  The
+    // visited set only grows, so it still holds every vertex that rises; a
+    // vertex that does not expand (CSD <= k) is evicted at once, so the
+    // neighbours it counted without visiting never matter; and an expanding
+    // vertex has visited every level-k neighbour its CSD counted.  Peeling
+    // the visited set therefore still leaves exactly the risers.
+    // Returns whether w supports a level-k vertex; *cl = w newly claimed.
+    auto csd_claim = [&](int32_t w, int32_t k, bool &cl) -> bool {
+        cl = false;
         if (w < 0) return false;
-        if (g.core[w] != k || g.mcd[w] <= k) return false;
+        const int32_t cw = g.core[w];
+        if (cw > k) return true;
+        if (cw != k || g.mcd[w] <= k) return false;
         // already claimed: skip the atomic.  A plain load may return an
         // older stamp (then the atomic decides), never a later one.
-        if (g.stamp[w] == ep) return false;
-        if (atomicExch(&g.stamp[w], ep) == ep) return false;
-        g.cd[w] = 0;
+        if (g.stamp[w] != ep && atomicExch(&g.stamp[w], ep) != ep) {
+            g.cd[w] = 0;
+            cl = true;
+        }
         return true;
     };
     WaveBuf bq = wave_buf(0), be = wave_buf(1), bcand = wave_buf(2);
@@ -1190,9 +1201,8 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         wb_push(bcand, a.q.cand, a.q.vcap, &c->cand_count, v, p, &c->overflow);
     };
 
-    // Lists of up to `large` slots: CSD and expansion as flattened walks of
-    // the wave's batch; longer root lists have their CSD counted chunk by
-    // chunk next round.
+    // Lists of up to `large` slots: flattened walks of the wave's batch;
+    // longer root lists are counted chunk by chunk next round.
     for_batches(T, a.q.fq[bc], nq, [&](int32_t v) {
         const int32_t L = v >= 0 ? g.len[v] : 0;
         const int32_t k = v >= 0 ? g.core[v] : 0;
@@ -1208,25 +1218,24 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         const bool live = v >= 0 && !big;
         int32_t pcd = 0;
         flat_walk(g, v, live ? L : 0, [&](int32_t j, int32_t w, unsigned long long own) {
-            const int32_t kj = __shfl(k, j < 0 ? 0 : j);
-            pcd += __popcll(__ballot(w >= 0 && is_support(g, w, kj)) & own);
+            bool cl;
+            const bool sup = csd_claim(j >= 0 ? w : -1, __shfl(k, j < 0 ? 0 : j), cl);
+            pcd += __popcll(__ballot(sup) & own);
+            push_next(w, cl);
         });
         if (live) { g.cd[v] = pcd; scanned += L; }
         push_cand(v, live);
-        const bool grow = live && pcd > k;
-        if (grow) scanned += L;
-        push_evict(v, live && !grow);
-        flat_walk(g, v, grow ? L : 0, [&](int32_t j, int32_t w, unsigned long long) {
-            push_next(w, claim(w, __shfl(k, j < 0 ? 0 : j)));
-        });
+        push_evict(v, live && pcd <= k);
     });
 
-    // CSD of long lists, chunk by chunk; the last chunk to finish decides.
+    // Long lists, chunk by chunk; the last chunk to finish has the CSD.
     for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
         int32_t k = g.core[v];
         int32_t part = 0;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) {
-            if (w >= 0 && is_support(g, w, k)) ++part;
+            bool cl;
+            if (csd_claim(w, k, cl)) ++part;
+            push_next(w, cl);
         });
         part = wave_sum(part);
         int last = 0;
@@ -1245,25 +1254,8 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             }
             tot = __shfl(tot, 0);
             push_cand(v, lane() == 0);
-            if (tot > k) {
-                if (lane() == 0) {
-                    int base = atomicAdd(&c->fx_tail[sn], nch);
-                    for (int q = 0; q < nch; ++q) {
-                        if (base + q < a.q.hcap) a.q.fx[bn][base + q] = chunk_item(v, q);
-                        else atomicOr(&c->overflow, 1);
-                    }
-                }
-            } else {
-                push_evict(v, lane() == 0);
-            }
+            push_evict(v, lane() == 0 && tot <= k);
         }
-    });
-
-    // Expansion of long lists whose CSD exceeded k (decided last round).
-    for_chunks(T, a.q.fx[bc], nx, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
-        int32_t k = g.core[v];
-        if (lane() == 0) scanned += hi - lo;
-        wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { push_next(w, claim(w, k)); });
     });
     wb_flush(bq, a.q.fq[bn], a.q.vcap, &c->fq_tail[sn], &c->overflow);
     wb_flush(be, a.q.eq[0], a.q.vcap, &c->eq_tail[0], &c->overflow);
