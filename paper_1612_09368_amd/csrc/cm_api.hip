@@ -169,7 +169,7 @@ KArgs make_args(cm_graph *g) {
                          d.done, d.matched, d.claim, d.bmark, d.gain},
                      "graph arrays");
         const DevQueues &q = g->q;
-        require_ptrs(g, {q.fq[0], q.fq[1], q.fh[0], q.fh[1], q.fx[0], q.fx[1], q.eq[0], q.eq[1],
+        require_ptrs(g, {q.fq[0], q.fq[1], q.fh[0], q.fh[1], q.eq[0], q.eq[1],
                          q.eh[0], q.eh[1], q.cand, q.chg, q.chh, q.touched, g->b.vlist, g->b.reloc,
                          g->b.reloc_off, g->b.reloc_cap, g->scan_tmp, g->firstidx},
                      "queues");
@@ -286,9 +286,8 @@ void alloc_chunk_queues(cm_graph *g) {
     if (h > INT_MAX) h = INT_MAX;
     if (h > g->q.hcap) {
         for (int i = 0; i < 2; ++i) {
-            dev_free(g->q.fh[i]); dev_free(g->q.fx[i]); dev_free(g->q.eh[i]);
+            dev_free(g->q.fh[i]); dev_free(g->q.eh[i]);
             dev_alloc(g, &g->q.fh[i], h);
-            dev_alloc(g, &g->q.fx[i], h);
             dev_alloc(g, &g->q.eh[i], h);
         }
         dev_free(g->q.chh);
@@ -856,7 +855,7 @@ void release_all(cm_graph *g) {
     dev_free(b.reloc_off); dev_free(b.reloc_cap);
     DevQueues &q = g->q;
     for (int i = 0; i < 2; ++i) {
-        dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.fx[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
+        dev_free(q.fq[i]); dev_free(q.fh[i]); dev_free(q.eq[i]); dev_free(q.eh[i]);
     }
     dev_free(q.cand); dev_free(q.chg); dev_free(q.chh); dev_free(q.touched);
     dev_free(q.aq[0]); dev_free(q.aq[1]);

@@ -39,8 +39,7 @@ struct Ctl {
     int32_t rem_count[2];    // remaining-edge lists, ping-pong by epoch parity
     int32_t sel_count;       // selected edges of the current iteration
     int32_t fq_tail[3];      // expansion: normal vertices
-    int32_t fh_tail[3];      // expansion: chunks of long lists (count pass)
-    int32_t fx_tail[3];      // expansion: chunks of long lists (expand pass)
+    int32_t fh_tail[3];      // expansion: chunks of long lists
     int32_t eq_tail[3];      // eviction / peel / decomposition: normal vertices
     int32_t eh_tail[3];      // eviction / peel / decomposition: chunks of long lists
     int32_t cand_count;      // candidates of the iteration (insert)
@@ -170,7 +169,6 @@ struct DevQueues {
     int32_t hcap;        // capacity of chunk queues
     int32_t *fq[2];
     int64_t *fh[2];
-    int64_t *fx[2];
     int32_t *eq[2];
     int64_t *eh[2];
     int32_t *cand;

@@ -31,7 +31,7 @@ __global__ void k_ctl_batch_reset(Ctl *c, int cur) {
         c->rem_count[1] = 0;
         c->sel_count = 0;
         for (int j = 0; j < 3; ++j) {
-            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0;
             c->eq_tail[j] = 0; c->eh_tail[j] = 0;
             c->rm_count[j] = 0; c->min_deg[j] = 0x7fffffff;
         }

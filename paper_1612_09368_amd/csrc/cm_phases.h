@@ -471,7 +471,7 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
         c->sel_count = 0;
         c->rem_count[it.cur ^ 1] = 0;
         for (int j = 0; j < 3; ++j) {
-            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0;
             c->eq_tail[j] = 0; c->eh_tail[j] = 0;
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
@@ -734,7 +734,7 @@ __device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const
         c->sel_count = 0;
         c->rem_count[it.cur ^ 1] = 0;
         for (int j = 0; j < 3; ++j) {
-            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0;
             c->eq_tail[j] = 0; c->eh_tail[j] = 0;
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
@@ -1163,7 +1163,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
     const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
     if (T.lead()) {
-        c->fq_tail[sx] = 0; c->fh_tail[sx] = 0; c->fx_tail[sx] = 0;
+        c->fq_tail[sx] = 0; c->fh_tail[sx] = 0;
         c->st_rounds += 1;
     }
     const int32_t ep = it.ep;
@@ -1484,8 +1484,7 @@ __device__ __forceinline__ bool block_local_ok(const KArgs &a, const Iter &it, c
     long long w = 0;
     switch (pc.step) {
     case S_EXPAND:
-        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap),
-                       qlen(&c->fh_tail[s], a.q.hcap) + qlen(&c->fx_tail[s], a.q.hcap), 2);
+        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap), 1);
         break;
     case S_EVICT:
     case S_PEEL:
@@ -1507,8 +1506,7 @@ __device__ __forceinline__ int64_t step_work(const KArgs &a, const Iter &it, con
     case S_SELECT: return it.n_r;
     case S_APPLY: return qlen(&c->sel_count, a.b.cap);
     case S_EXPAND:
-        return frontier_work(a, qlen(&c->fq_tail[s], a.q.vcap),
-                             qlen(&c->fh_tail[s], a.q.hcap) + qlen(&c->fx_tail[s], a.q.hcap));
+        return frontier_work(a, qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap));
     case S_EVICT:
     case S_PEEL: return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
     case S_CORE: return it.ins ? qlen(&c->cand_count, a.q.vcap) : qlen(&c->chg_count, a.q.vcap);
@@ -1526,7 +1524,7 @@ __device__ __forceinline__ bool step_is_local(const KArgs &a, const Iter &it, co
 
 __device__ __forceinline__ bool slot_empty_f(const KArgs &a, int s) {
     Ctl *c = a.ctl;
-    return ld_rlx(&c->fq_tail[s]) + ld_rlx(&c->fh_tail[s]) + ld_rlx(&c->fx_tail[s]) == 0;
+    return ld_rlx(&c->fq_tail[s]) + ld_rlx(&c->fh_tail[s]) == 0;
 }
 __device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
     Ctl *c = a.ctl;
@@ -1704,7 +1702,7 @@ __device__ __forceinline__ void prog_reset_ctl(const KArgs &a, const BatchCtx &b
         c->rem_count[1] = 0;
         c->sel_count = 0;
         for (int j = 0; j < 3; ++j) {
-            c->fq_tail[j] = 0; c->fh_tail[j] = 0; c->fx_tail[j] = 0;
+            c->fq_tail[j] = 0; c->fh_tail[j] = 0;
             c->eq_tail[j] = 0; c->eh_tail[j] = 0;
         }
         c->cand_count = 0; c->chg_count = 0; c->chh_count = 0;
