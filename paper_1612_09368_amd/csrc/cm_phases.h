@@ -505,8 +505,8 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
 }
 
 // Apply one selected edge i (Algorithm 1 / 5, the set's insertion or
-// deletion): list append or tombstones, SD of its constrained endpoints,
-// roots.  A constrained endpoint keeps at most one selected edge, so its SD
+// deletion), called by the select step for its winners: list append or
+// tombstones, SD of its constrained endpoints, roots.  A constrained endpoint keeps at most one selected edge, so its SD
 // and root status depend on this edge alone.  Every lane may call it (sel
 // selects the applying lanes; pushes are wave-aggregated).
 __device__ __forceinline__ void apply_edge_insert(const KArgs &a, const Iter &it, int32_t i, bool sel) {
@@ -615,20 +615,6 @@ __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int 
 // Insert the selected set into G (Algorithm 1) and update SD of the
 // constrained endpoints; a constrained endpoint whose new SD exceeds its core
 // is a root of the traversal (a vertex with SD <= k cannot rise).
-__device__ __forceinline__ void apply_insert(const KArgs &a, const Iter &it, const Team &T) {
-    Ctl *c = a.ctl;
-    const int32_t n = qlen(&c->sel_count, a.b.cap);
-    if (T.lead()) c->st_selected += (unsigned long long)n;
-    for (int32_t idx = T.rank; idx < n; idx += T.size) apply_edge_insert(a, it, a.b.sel[idx], true);
-}
-
-__device__ __forceinline__ void apply_delete(const KArgs &a, const Iter &it, const Team &T) {
-    Ctl *c = a.ctl;
-    const int32_t n = qlen(&c->sel_count, a.b.cap);
-    if (T.lead()) c->st_selected += (unsigned long long)n;
-    for (int32_t idx = T.rank; idx < n; idx += T.size) apply_edge_delete(a, it, a.b.sel[idx], true);
-}
-
 // Positive traversal (Algorithm 3) as level-synchronous rounds over all
 // levels at once.  A visited vertex v gets cd[v] = CSD(v); if CSD(v) > k it
 // visits its core-k neighbours w with SD(w) > k, otherwise it is queued for
@@ -1580,11 +1566,9 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
         if (it.sc.mode) star_select(a, it, T);
         else part_select(a, it, pc.r, T);
         break;
-    case S_APPLY:
+    case S_APPLY:  // vertex stars only: edge sets apply inside the select step
         if (it.sc.mode == 1) star_apply_insert(a, it, T);
-        else if (it.sc.mode == 2) star_apply_delete(a, it, T);
-        else if (it.ins) apply_insert(a, it, T);
-        else apply_delete(a, it, T);
+        else star_apply_delete(a, it, T);
         break;
     case S_EXPAND:
         if (a.t.async_steps) expand_async(a, it, scanned);
