@@ -430,10 +430,13 @@ __device__ __forceinline__ void gbar(Bar *b) {
         const unsigned members = nb / NGRP + (grp < nb % NGRP ? 1u : 0u);
         const unsigned ngroups = nb < (unsigned)NGRP ? nb : (unsigned)NGRP;
         const unsigned g0 = __hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned a = __hip_atomic_fetch_add(&b->grp[grp * 32], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // arrival releases this workgroup's stores; the one acquire comes
+        // after the wait (an acquire on arrival would only add a cache
+        // invalidation per workgroup)
+        unsigned a = __hip_atomic_fetch_add(&b->grp[grp * 32], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (a == members - 1u) {
             __hip_atomic_store(&b->grp[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned t = __hip_atomic_fetch_add(&b->top[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned t = __hip_atomic_fetch_add(&b->top[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (t == ngroups - 1u) {
                 __hip_atomic_store(&b->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&b->gen[0], g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
