@@ -105,11 +105,13 @@ constexpr int PH_SLOTS = 16;
 // dispatch), one counter for the groups, one generation word; each on its
 // own 128-byte line.
 constexpr int NGRP = 8;
+constexpr int XSLOTS = 16;  // XCC ids a workgroup can report
 struct Bar {
-    unsigned int grp[NGRP * 32];
+    unsigned int grp[XSLOTS * 32];  // arrival counters (per group, 128-byte apart)
     unsigned int top[32];
     unsigned int gen[32];
     unsigned int abort[32];   // set when a wait gives up; later barriers return at once
+    unsigned long long xreg[XSLOTS * 16];  // per XCC: (launch epoch << 32) | workgroups on it
 };
 
 // Per-vertex device arrays plus the adjacency pool.
@@ -416,12 +418,42 @@ struct Team {
 __device__ __forceinline__ Team grid_team() { return Team{gtid(), gthreads()}; }
 __device__ __forceinline__ Team block_team() { return Team{(int)threadIdx.x, (int)blockDim.x}; }
 
-// Grid-wide barrier of a cooperative launch (all workgroups co-resident).
-// Thread 0 of each workgroup arrives on its group counter; the last arrival
-// of a group arrives on the top counter; the last group bumps the generation
-// word that everyone waits on.  Device-scope release on arrival and acquire
-// on departure make plain stores before the barrier visible after it.
-__device__ __forceinline__ void gbar(Bar *b) {
+// Per-workgroup barrier state in LDS: XCC id, workgroups on that XCC,
+// XCCs in use (set by gbar_setup at the start of every cooperative kernel).
+__device__ __forceinline__ unsigned *bar_info() {
+    __shared__ unsigned info[4];
+    return info;
+}
+
+// Hardware id of the XCC (accelerator complex die) running this workgroup.
+__device__ __forceinline__ unsigned xcc_id() {
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (XSLOTS - 1);  // HW_REG_XCC_ID[3:0]
+}
+
+// Wait (bounded, about a second) until the generation word moves past g0;
+// a workgroup that never arrives is a bug: the barrier then trips the abort
+// word instead of hanging, and the drivers stop at their next check.
+__device__ __forceinline__ void bar_wait(Bar *b, unsigned g0) {
+    unsigned polls = 0;
+    while (__hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        if (__hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++polls > (1u << 25)) {
+            __hip_atomic_store(&b->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+    // one acquire for the whole workgroup after the wait (polls stay relaxed)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Grid-wide barrier of a cooperative launch (all workgroups co-resident),
+// correct for any placement of workgroups: thread 0 of each workgroup
+// arrives on the counter of group blockIdx % NGRP with a release (its own
+// stores become visible device-wide); the last arrival of a group arrives on
+// the top counter; the last group bumps the generation word that everyone
+// waits on.
+__device__ __forceinline__ void gbar_any(Bar *b) {
     wave_drain();  // this wave's stores and atomics have reached the cache hierarchy
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -430,9 +462,6 @@ __device__ __forceinline__ void gbar(Bar *b) {
         const unsigned members = nb / NGRP + (grp < nb % NGRP ? 1u : 0u);
         const unsigned ngroups = nb < (unsigned)NGRP ? nb : (unsigned)NGRP;
         const unsigned g0 = __hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // arrival releases this workgroup's stores; the one acquire comes
-        // after the wait (an acquire on arrival would only add a cache
-        // invalidation per workgroup)
         unsigned a = __hip_atomic_fetch_add(&b->grp[grp * 32], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (a == members - 1u) {
             __hip_atomic_store(&b->grp[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -442,20 +471,72 @@ __device__ __forceinline__ void gbar(Bar *b) {
                 __hip_atomic_store(&b->gen[0], g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // Bounded wait (about a second): a workgroup that never arrives is a
-        // bug; the barrier then trips the abort word instead of hanging, and
-        // the drivers stop at their next check.
-        unsigned polls = 0;
-        while (__hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-            if (__hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(2);
-            if (++polls > (1u << 25)) {
-                __hip_atomic_store(&b->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
+        bar_wait(b, g0);
+    }
+    __syncthreads();
+}
+
+// Start of a cooperative kernel: every workgroup registers the XCC it runs
+// on (counted under this launch's epoch, the generation word at the start,
+// so nothing needs clearing between launches or graph replays), then one
+// gbar_any; afterwards each workgroup knows how many workgroups share its
+// XCC and how many XCCs are in use.
+__device__ __forceinline__ void gbar_setup(Bar *b) {
+    unsigned *info = bar_info();
+    unsigned long long ep = 0;
+    unsigned x = 0;
+    if (threadIdx.x == 0) {
+        x = xcc_id();
+        ep = __hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long *r = &b->xreg[x * 16];
+        unsigned long long old = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+            const unsigned long long want = (old >> 32) == ep ? old + 1ull : ((ep << 32) | 1ull);
+            const unsigned long long prev = atomicCAS(r, old, want);
+            if (prev == old) break;
+            old = prev;
+        }
+    }
+    gbar_any(b);
+    if (threadIdx.x == 0) {
+        // XCCs with workgroups of this launch (a slot never used reads 0 in
+        // both halves, so the epoch alone would not tell it apart at epoch 0)
+        unsigned ng = 0;
+        for (int y = 0; y < XSLOTS; ++y) {
+            const unsigned long long v =
+                __hip_atomic_load(&b->xreg[y * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((v >> 32) == ep && (v & 0xffffffffull) != 0) ++ng;
+        }
+        info[0] = x;
+        info[1] = (unsigned)(__hip_atomic_load(&b->xreg[x * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                             0xffffffffull);
+        info[2] = ng;
+    }
+    __syncthreads();
+}
+
+// The barrier of the step machines (after gbar_setup), grouped by XCC: the
+// workgroups of one XCC share its L2, so their arrivals need no release of
+// their own: the last arrival of the XCC releases once for all of them
+// (their stores had reached that L2 before they arrived), then arrives on
+// the top counter; the last XCC bumps the generation word.
+__device__ __forceinline__ void gbar(Bar *b) {
+    const unsigned *info = bar_info();
+    wave_drain();  // this wave's stores and atomics have reached the cache hierarchy
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned x = info[0], members = info[1], ngroups = info[2];
+        const unsigned g0 = __hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned a = __hip_atomic_fetch_add(&b->grp[x * 32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == members - 1u) {
+            __hip_atomic_store(&b->grp[x * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned t = __hip_atomic_fetch_add(&b->top[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1u) {
+                __hip_atomic_store(&b->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&b->gen[0], g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // one acquire for the whole workgroup after the wait (polls stay relaxed)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        bar_wait(b, g0);
     }
     __syncthreads();
 }

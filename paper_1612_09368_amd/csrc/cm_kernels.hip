@@ -322,6 +322,7 @@ __global__ void k_dec_prep(KArgs a) {
 }
 
 __global__ void __launch_bounds__(COOP_THREADS) k_decompose(KArgs a) {
+    gbar_setup(a.bar);
     long long scanned = 0;
     decompose(a, scanned);
     flush_stat(&a.ctl->st_scanned, scanned);
@@ -365,6 +366,7 @@ __global__ void k_res_alloc(KArgs a) { res_alloc(a, grid_team()); }
 __global__ void k_res_copy(KArgs a) { res_copy(a, grid_team()); }
 __global__ void k_del_compact(KArgs a) { del_compact(a, grid_team()); }
 __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
+    gbar_setup(a.bar);
     int32_t ep = ld_rlx(&a.ctl->epoch);
     long long scanned = 0;
     int pubs = 0;
@@ -384,8 +386,14 @@ __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(COOP_THREADS) k_program(KArgs a) { run_program(a); }
-__global__ void __launch_bounds__(COOP_THREADS) k_serve(KArgs a) { run_server(a); }
+__global__ void __launch_bounds__(COOP_THREADS) k_program(KArgs a) {
+    gbar_setup(a.bar);
+    run_program(a);
+}
+__global__ void __launch_bounds__(COOP_THREADS) k_serve(KArgs a) {
+    gbar_setup(a.bar);
+    run_server(a);
+}
 
 // ---------------------------------------------------------------------------
 // Vertex operations
