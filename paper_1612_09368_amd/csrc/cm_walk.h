@@ -136,17 +136,6 @@ __device__ __forceinline__ void wave_walk(const DevGraph &g, int32_t v, int32_t 
     }
 }
 
-// Lane walk of slots [0, L) of v, live entries only.
-template <class F>
-__device__ __forceinline__ void lane_walk(const DevGraph &g, int32_t v, int32_t L, F &&f) {
-    const int32_t *p = g.nbr + g.off[v];
-    for (int32_t i = 0; i < L; ++i) {
-        int32_t w = p[i];
-        if (w >= 0) f(w, i);
-    }
-}
-
-
 // Team-stride over a vertex queue in batches of up to 64 entries per wave:
 // a wave takes `per` consecutive entries, per = ceil(n / waves) capped at
 // 64, so a queue shorter than 64 entries per wave is spread over every wave
