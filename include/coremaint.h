@@ -113,9 +113,12 @@ typedef struct cm_batch_stats {
     int64_t rounds;         /* cascade rounds (expansion, eviction, peel) */
     int64_t grid_steps;     /* steps run by the whole grid (each ends in a grid barrier) */
     int64_t local_steps;    /* steps run inside one workgroup */
-    int32_t launches;       /* maintenance kernel launches */
+    int32_t launches;       /* maintenance kernel launches (plain mode: one per superior edge
+                               set plus the empty one that ends the batch, queued before the
+                               host knew no edges were left) */
     int32_t graph_launch;   /* 1 when the launch was replayed from a hipGraph */
-    double kernel_ms;       /* summed HIP-event time of those launches (timing = 1) */
+    double kernel_ms;       /* summed HIP-event time of those launches (timing = 1; the
+                               plain mode times every launch) */
     double ms_total;        /* wall time of the call */
 } cm_batch_stats;
 
