@@ -543,3 +543,32 @@ def test_chung_lu_full_size_batched(cm, dev, oracle_mod):
                                _t(xs, dev), _t(ys, dev))
         assert [r.status for r in res] == [0, 0] and [r.applied for r in res] == [a.size, x.size]
         check_state(g, ref, "cl full batched")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_two_workgroups_per_cu(cm, dev, oracle_mod, mode):
+    """The cooperative grid with two workgroups per compute unit (a launch
+    parameter the autotuner may pick): the grid barrier then groups 64
+    workgroups per XCC; decomposition and mixed batches against the oracle,
+    in the per-call form and in one batch program."""
+    rng = graphgen.rng_for("bpc2")
+    n = 20_000
+    s, d = graphgen.chung_lu_graph(n, 120_000, 2.2, 2000.0, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev, mode=mode, blocks_per_cu=2) as g:
+        check_state(g, ref, "decompose")
+        for kind, a, b in _batches(ref, rng, n, 4, 3000):
+            st = (g.insert_edges if kind == "insert" else g.delete_edges)(_t(a, dev), _t(b, dev))
+            (ref.insert_edges if kind == "insert" else ref.delete_edges)(a, b)
+            check_state(g, ref, f"bpc2 {kind}")
+        if mode == 1:
+            es = graphgen.EdgeSet(*ref.edges())
+            a, b = graphgen.weighted_non_edges(2000, es, rng)
+            es.insert(a, b)
+            x, y = graphgen.existing_edges(2000, es, rng)
+            res, _ = g.run_batches([cm.BATCH_INSERT, cm.BATCH_DELETE], [0, a.size, a.size + x.size],
+                                   _t(np.concatenate([a, x]), dev), _t(np.concatenate([b, y]), dev))
+            ref.insert_edges(a, b)
+            ref.delete_edges(x, y)
+            assert [r.status for r in res] == [0, 0]
+            check_state(g, ref, "bpc2 program")
