@@ -169,10 +169,16 @@ def keys_of(a, b):
 
 
 class DynamicGraph:
-    """Host model of the dynamic graph: a sorted array of canonical edge keys
-    plus an alive mask.  Each batch method validates the batch with the C
+    """Host model of the dynamic graph: the canonical edge keys plus an alive
+    mask of vertex ids.  Each batch method validates the batch with the C
     boundary's convention, applies it (or not, in strict mode) and the caller
     recomputes cores with ``cores()`` (BZ from scratch).
+
+    Storage: the keys of the initial graph stay in one sorted array with a
+    presence mask; keys inserted later live in a sorted side array.  A batch
+    therefore costs a search per item instead of a re-sort of the whole set,
+    which keeps streams of 10^7 updates on 6.4 x 10^7 edges checkable.  The
+    edge set it represents is the plain set union / difference of the batches.
 
     Validation convention (boundary rule, not from the paper): in a batch of
     edges, item i is invalid if an endpoint is out of [0, n_ids) (E_RANGE),
@@ -187,25 +193,65 @@ class DynamicGraph:
     def __init__(self, n: int, src, dst):
         self.n = int(n)
         self.alive = np.ones(self.n, dtype=np.uint8)
-        self.keys = np.unique(keys_of(src, dst))
+        self._base = np.unique(keys_of(src, dst))
+        self._present = np.ones(self._base.size, dtype=bool)
+        self._added = np.empty(0, dtype=np.int64)
+        self._m = int(self._base.size)
 
     # -- queries --------------------------------------------------------
+    @property
+    def keys(self) -> np.ndarray:
+        """Sorted canonical keys (min << 32 | max) of the current edges."""
+        return np.sort(np.concatenate([self._base[self._present], self._added]))
+
     def edges(self):
-        return (self.keys >> 32).astype(np.int32), (self.keys & 0xFFFFFFFF).astype(np.int32)
+        k = np.concatenate([self._base[self._present], self._added])
+        return (k >> 32).astype(np.int32), (k & 0xFFFFFFFF).astype(np.int32)
 
     def num_edges(self):
-        return int(self.keys.size)
+        return self._m
 
     def cores(self) -> np.ndarray:
         s, d = self.edges()
         return bz_cores(self.n, s, d, self.alive)
 
+    def _base_pos(self, keys):
+        if self._base.size == 0:
+            return np.zeros(keys.shape, dtype=np.int64), np.zeros(keys.shape, dtype=bool)
+        p = np.minimum(np.searchsorted(self._base, keys), self._base.size - 1)
+        return p, self._base[p] == keys
+
+    def _added_pos(self, keys):
+        if self._added.size == 0:
+            return np.zeros(keys.shape, dtype=np.int64), np.zeros(keys.shape, dtype=bool)
+        p = np.minimum(np.searchsorted(self._added, keys), self._added.size - 1)
+        return p, self._added[p] == keys
+
     def has(self, keys):
         keys = np.asarray(keys, dtype=np.int64)
-        if self.keys.size == 0:
-            return np.zeros(keys.shape, dtype=bool)
-        p = np.minimum(np.searchsorted(self.keys, keys), self.keys.size - 1)
-        return self.keys[p] == keys
+        p, hit = self._base_pos(keys)
+        out = hit & self._present[p] if self._base.size else hit
+        return out | self._added_pos(keys)[1]
+
+    def _add_keys(self, keys):
+        """Add distinct keys that are not edges."""
+        p, hit = self._base_pos(keys)
+        self._present[p[hit]] = True
+        new = np.sort(keys[~hit])
+        self._added = np.insert(self._added, np.searchsorted(self._added, new), new)
+        self._m += int(keys.size)
+
+    def _remove_keys(self, keys):
+        """Remove distinct keys that are edges."""
+        p, hit = self._base_pos(keys)
+        hit &= self._present[p] if self._base.size else hit
+        self._present[p[hit]] = False
+        rest = keys[~hit]
+        if rest.size:
+            q, ok = self._added_pos(rest)
+            assert ok.all()
+            self._added = np.delete(self._added, q)
+        self._m -= int(keys.size)
 
     # -- validation ----------------------------------------------------------
     def validate(self, src, dst, inserting: bool):
@@ -250,7 +296,7 @@ class DynamicGraph:
         if st != OK:
             return st, fb, 0
         ok = err == 0
-        self.keys = np.union1d(self.keys, keys_of(np.asarray(src)[ok], np.asarray(dst)[ok]))
+        self._add_keys(keys_of(np.asarray(src)[ok], np.asarray(dst)[ok]))
         return OK, fb, int(ok.sum())
 
     def delete_edges(self, src, dst, strict=True):
@@ -259,8 +305,7 @@ class DynamicGraph:
         if st != OK:
             return st, fb, 0
         ok = err == 0
-        self.keys = np.setdiff1d(self.keys, keys_of(np.asarray(src)[ok], np.asarray(dst)[ok]),
-                                 assume_unique=True)
+        self._remove_keys(keys_of(np.asarray(src)[ok], np.asarray(dst)[ok]))
         return OK, fb, int(ok.sum())
 
     def insert_vertices(self, off, nbrs, strict=True, keep_failed_ids=False):
@@ -307,10 +352,9 @@ class DynamicGraph:
             return st, fb
         dead = np.unique(ids[err == 0])
         if dead.size:
-            lo = self.keys >> 32
-            hi = self.keys & 0xFFFFFFFF
-            hit = np.isin(lo, dead) | np.isin(hi, dead)
-            self.keys = self.keys[~hit]
+            k = self.keys
+            hit = np.isin(k >> 32, dead) | np.isin(k & 0xFFFFFFFF, dead)
+            self._remove_keys(k[hit])
             self.alive[dead] = 0
         return OK, fb
 
