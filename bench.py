@@ -3,7 +3,7 @@
 Workloads (``--workload``; every graph and update stream is seeded and
 synthetic, and inputs are resident in device memory before the timed region):
 
-chunglu-1m (default)
+chunglu-1m
     Chung-Lu power-law graph, n = 1,000,000, m = 10,000,000, degree exponent
     2.1, largest weight 50,000.  One step inserts 100,000 degree-weighted
     non-edges and then deletes 100,000 uniformly drawn existing edges, with
@@ -11,7 +11,7 @@ chunglu-1m (default)
     cooperative launch per superior edge set, the host checks termination);
     the persistent form (one launch per batch) and the batched form (every
     timed batch in one launch) run beside it on the same batches.
-rmat22-stream
+rmat22-stream (default)
     R-MAT scale 22 (edge factor 16, a=0.57 b=0.19 c=0.19, dedup, no loops,
     random relabel) and 64 batches, sizes log-uniform in [1,000, 1,000,000],
     half R-MAT-sampled insertions, half uniform deletions, shuffled.  One step
@@ -44,12 +44,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per k_maintain launch on the default workload (plain form), from two rocprofv3 counter
-# passes (FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, both scaled by what they read for a 1 GiB
-# device copy); the summary and commands are in profiles/k_maintain_chunglu_1m_hbm_traffic.md.
-# It describes the kernel sources it was measured on: reported only while their hash matches.
-TRAFFIC = {"kernel": "k_maintain", "bytes_per_launch": 241.4e6,
-           "sources_sha256": "c3b52196483f2f022e46a810be9b8c997836b657ed8dc040615477977c54b50a"}
+# Measured HBM bytes per launch of the dominant kernel, per workload, from two rocprofv3 counter
+# passes (FETCH_SIZE, then WRITE_SIZE) scaled by calibration kernels of known footprint; each entry
+# names the kernel sources it was measured on and is reported only while their hash matches (the
+# summaries and commands are under profiles/).
+TRAFFIC = {}
 KERNEL_SOURCES = ["cm_internal.h", "cm_kernels.hip", "cm_phases.h", "cm_walk.h"]
 
 
@@ -91,18 +90,31 @@ def contract(workload, value, steps, warmup, ms_per_step, global_batch, form):
     }
 
 
-def roofline(kernel, stats, note):
-    """Algorithmic bytes of the launches over their HIP-event time."""
+def roofline(kernel, stats, note, traffic_key=None):
+    """Algorithmic bytes of the launches over their HIP-event time; the
+    measured HBM traffic per launch is attached when it was taken on the
+    current kernel sources."""
     kms = sum(x["kernel_ms"] for x in stats)
     launches = sum(x["launches"] for x in stats)
     abytes = sum(x["alg_bytes"] for x in stats)
     achieved = (abytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
-    return {
+    out = {
         "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
         "alg_bytes_per_launch": abytes / max(launches, 1),
         "avg_launch_us": kms * 1e3 / max(launches, 1), "launches": launches, "per_launch": note,
     }
+    tr = TRAFFIC.get(traffic_key)
+    if tr is not None and tr["kernel"] == kernel:
+        if tr["sources_sha256"] == kernel_sources_sha256():
+            out["traffic"] = tr["bytes_per_launch"]
+            out["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+            out["traffic_gbs"] = tr["bytes_per_launch"] / (out["avg_launch_us"] * 1e-6) / 1e9
+            out["traffic_frac"] = out["traffic_gbs"] / HBM_PEAK_GBS
+            out["traffic_over_alg"] = tr["bytes_per_launch"] / max(out["alg_bytes_per_launch"], 1.0)
+        else:
+            out["traffic_note"] = "kernel sources changed since the counters were taken"
+    return out
 
 
 def to_dev(torch, x):
@@ -264,14 +276,7 @@ def bench_cl1m(args, cm, torch):
                    plain["elapsed"] * 1e3 / args.steps, 2 * CL_BATCH,
                    "plain (one cooperative launch per superior edge set)")
     out["roofline"] = roofline("k_maintain", st, "one superior edge set (partition, apply, cascade, "
-                                                "core and SD update)")
-    if kernel_sources_sha256() == TRAFFIC["sources_sha256"]:
-        out["roofline"]["traffic"] = TRAFFIC["bytes_per_launch"]
-        out["roofline"]["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-        # measured HBM rate: counted bytes per launch over this run's average launch time
-        tgbs = TRAFFIC["bytes_per_launch"] / (out["roofline"]["avg_launch_us"] * 1e-6) / 1e9
-        out["roofline"]["traffic_gbs"] = tgbs
-        out["roofline"]["traffic_frac"] = tgbs / HBM_PEAK_GBS
+                                                "core and SD update)", traffic_key="chunglu-1m")
     out["latency_ms"] = {"p50": pct(plain["lat"], 50), "p99": pct(plain["lat"], 99),
                          "per": "batch of 100000 edges"}
     out["tuning"] = tuning
@@ -316,6 +321,20 @@ def bench_cl1m(args, cm, torch):
 RM_SCALE, RM_BATCHES, RM_LO, RM_HI = 22, 64, 1000, 1_000_000
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def bench_rmat22(args, cm, torch):
     import graphgen
     t = time.time()
@@ -332,67 +351,100 @@ def bench_rmat22(args, cm, torch):
         return n, ds, dd, kinds[:ns], offs[:ns + 1], dx[:offs[ns]], dy[:offs[ns]]
     params, tuning = tuned_params(args, n, s.size, np.diff(offs), sample)
 
-    def run(mode, use_graph, reps):
+    def run(mode, use_graph, reps, per_batch=False):
+        """reps passes over the stream from the freshly loaded graph: one
+        cm_run_batches call for the whole stream, or (per_batch) one call per
+        batch with its latency."""
         g = cm.Graph(mode=mode, timing=True, use_graph=use_graph, **params)
-        times, allstats, cores = [], [], None
-        for rep in range(reps):
-            g.load(n, ds, dd)
-            g.decompose()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res, _ = g.run_batches(kinds, offs, dx, dy)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            assert all(r.status == 0 for r in res), [r.status for r in res]
-            allstats.append([r.as_dict() for r in res])
+        times, allstats, lat = [], [], []
+        try:
+            for rep in range(reps):
+                g.load(n, ds, dd)
+                g.decompose()
+                g.phase_times(reset=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if per_batch:
+                    res, lat = [], []
+                    for j in range(RM_BATCHES):
+                        tb = time.perf_counter()
+                        r, _ = g.run_batches(kinds[j:j + 1], offs[j:j + 2] - offs[j],
+                                             dx[offs[j]:offs[j + 1]], dy[offs[j]:offs[j + 1]])
+                        lat.append((time.perf_counter() - tb) * 1e3)
+                        res += r
+                else:
+                    res, _ = g.run_batches(kinds, offs, dx, dy)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                assert all(r.status == 0 for r in res), [r.status for r in res]
+                allstats.append([r.as_dict() for r in res])
+                log(f"mode {mode}{' per batch' if per_batch else ''}: pass {rep} {times[-1]:.3f}s")
             phases = g.phase_times()
-            log(f"mode {mode}: pass {rep} {times[-1]:.3f}s")
-        cores = g.cores()
-        g.close()
-        return times, allstats, cores, phases
+            cores = g.cores()
+        finally:
+            g.close()
+        return times, allstats, cores, phases, lat
 
-    bt, bstats, bcores, bph = run(cm.MODE_PERSISTENT, True, args.warmup + args.steps)
+    bt, bstats, bcores, bph, _ = run(cm.MODE_PERSISTENT, True, args.warmup + args.steps)
     bt, bstats = bt[args.warmup:], bstats[args.warmup:]
-    pt, pstats, pcores, pph = run(cm.MODE_PLAIN, False, 1 + (args.steps > 1))
+    pt, pstats, pcores, pph, _ = run(cm.MODE_PLAIN, False, 1 + (args.steps > 1))
     assert np.array_equal(bcores, pcores), "plain and batched forms disagree"
     pt, pstats = pt[-1:], pstats[-1:]
+    qt, qstats, qcores, _, qlat = run(cm.MODE_PERSISTENT, False, 1, per_batch=True)
+    assert np.array_equal(bcores, qcores), "persistent and batched forms disagree"
     value = total * len(bt) / sum(bt)
     plain_value = total / pt[0]
-    out = contract(f"r-mat scale 22 edge factor 16 (m={s.size}); stream of 64 batches, sizes "
+    out = contract(f"r-mat scale 22 edge factor 16 (n={n} m={s.size}); stream of 64 batches, sizes "
                    "log-uniform [1000, 1000000], half r-mat non-edge inserts, half uniform deletes "
-                   f"({total} updates)", value, args.steps, args.warmup, sum(bt) * 1e3 / len(bt), total,
+                   f"({total} updates); one step = the whole stream from the freshly loaded graph",
+                   value, args.steps, args.warmup, sum(bt) * 1e3 / len(bt), total,
                    "batched (the whole stream in one persistent launch, hipGraph replay)")
     flat = [x for run_ in bstats for x in run_]
-    out["roofline"] = roofline("k_program", flat, "the whole 64-batch stream")
+    out["roofline"] = roofline("k_program", flat, "the whole 64-batch stream", traffic_key="rmat22-stream")
     plat = [x["ms_total"] for x in pstats[0]]
+    out["speedup_batched_vs_plain"] = value / plain_value
+    out["latency_ms"] = {"p50": pct(plat, 50), "p99": pct(plat, 99),
+                         "per": "batch, plain form (call to exact cores)"}
     out["plain"] = {
         "form": "plain (host loop, one cooperative launch per superior edge set)",
-        "value": plain_value, "ms_per_step": pt[0] * 1e3, "speedup_batched_vs_plain": value / plain_value,
+        "value": plain_value, "ms_per_step": pt[0] * 1e3,
         "latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "per": "batch"},
         "roofline": roofline("k_maintain", pstats[0], "one superior edge set"),
+    }
+    out["persistent"] = {
+        "form": "persistent (one cooperative launch per batch, one call per batch)",
+        "value": total / qt[0], "ms_per_step": qt[0] * 1e3,
+        "latency_ms": {"p50": pct(qlat, 50), "p99": pct(qlat, 99), "per": "batch"},
     }
     out["tuning"] = tuning
     out["phase_ms"] = {k: round(v[0], 3) for k, v in bph.items()}
     out["phase_count"] = {k: v[1] for k, v in bph.items()}
-    out["iterations_per_batch"] = [x["iterations"] for x in pstats[0]]
+    ps0 = pstats[0]
+    out["iterations_per_batch"] = [x["iterations"] for x in ps0]
+    out["steps_per_batch"] = [x["grid_steps"] + x["local_steps"] for x in bstats[-1]]
     out["batch_sizes"] = np.diff(offs).tolist()
-    out["per_batch"] = {k: [x[k] for x in pstats[0]] for k in
+    out["per_batch"] = {k: [x[k] for x in ps0] for k in
                         ("rounds", "candidates", "evicted", "changed", "scanned", "remaining_sum")}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
         ref = oracle.DynamicGraph(n, s, d)
         t0 = time.perf_counter()
-        done = 0
-        for j in range(2):
+        done, used = 0, 0
+        for j in range(RM_BATCHES):
             a, b = xs[offs[j]:offs[j + 1]], ys[offs[j]:offs[j + 1]]
             (ref.insert_edges if kinds[j] == 0 else ref.delete_edges)(a, b)
             ref.cores()
             done += a.size
+            used += 1
+            if time.perf_counter() - t0 >= args.cpu_budget:
+                break
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": done / el, "unit": "edge_updates/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first 2 batches of the stream ({done} updates, {el:.1f}s): "
-                                         "host edge-set apply + Batagelj-Zaversnik recompute per batch"}
+                               "host": host_cpu(),
+                               "sample": f"first {used} batches of the stream ({done} updates, {el:.1f}s): "
+                                         "host edge-set apply + Batagelj-Zaversnik recompute after each "
+                                         "batch, one thread"}
     return out
 
 
@@ -718,20 +770,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chunglu-1m",
+    ap.add_argument("--workload", default="rmat22-stream",
                     choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "paper-sweep",
                              "core-levels"])
     ap.add_argument("--sweep-scales", default="15,16,17,18,19,20,21", help="paper-sweep: log2 n values")
     ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
     ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch parameters on the workload's sample first and store them")
     ap.add_argument("--tune-budget", type=float, default=300.0, help="seconds for --tune")
     ap.add_argument("--no-persistent", action="store_true",
                     help="chunglu-1m: time the plain form only")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
+                    help="run the calibration kernels (1 GiB copy, random gather) first")
+    ap.add_argument("--calibration-only", action="store_true",
+                    help="run only the calibration kernels (references for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -743,17 +798,55 @@ def main():
     cm.library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0")
-        dst = torch.empty_like(src)
-        src.fill_(1)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    if args.copy_calibration or args.calibration_only:
+        cal = calibration(torch)
+        if args.calibration_only:
+            print(json.dumps({"calibration": cal}), flush=True)
+            teardown(torch)
+            return
     fn = {"chunglu-1m": bench_cl1m, "rmat22-stream": bench_rmat22, "chunglu-pool512": bench_pool512,
           "rmat-serve": bench_serve, "paper-sweep": bench_sweep, "core-levels": bench_levels}
     out = fn[args.workload](args, cm, torch)
     print(json.dumps(out), flush=True)
+    teardown(torch)
+
+
+def calibration(torch):
+    """Two kernels of known HBM footprint, the references for scaling the
+    rocprofv3 byte counters: a device copy of 1 GiB (reads 1 GiB, writes
+    1 GiB), and a gather of 2^21 random 4-byte values from a 1 GiB array
+    whose indices hit 2^21 distinct 128-byte lines, at most one value per
+    line, in random order -- the access pattern of the traversal kernels'
+    neighbour gathers, with no line reused.  It reads its 16 MiB of int64
+    indices plus one fetch unit per value, and writes 8 MiB."""
+    n = 1 << 28
+    src = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    rng = np.random.Generator(np.random.PCG64(11))
+    lines = rng.choice(n // 32, 1 << 21, replace=False).astype(np.int64)
+    idx = lines * 32 + rng.integers(0, 32, lines.size)
+    didx = torch.from_numpy(idx).to("cuda:0")
+    torch.cuda.synchronize()
+    got = torch.take(src, didx)
+    torch.cuda.synchronize()
+    del src, dst, didx, got
+    return {"copy": {"read_bytes": 4 * n, "write_bytes": 4 * n},
+            "gather": {"values": int(idx.size), "distinct_128b_lines": int(idx.size),
+                       "index_read_bytes": 8 * int(idx.size), "write_bytes": 4 * int(idx.size)}}
+
+
+def teardown(torch):
+    """Explicit end of the process's GPU work: every handle was closed by its
+    workload; wait for the device, release torch's cached blocks and flush
+    the output before the interpreter unwinds."""
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sys.stdout.flush()
+    sys.stderr.flush()
 
 
 if __name__ == "__main__":

@@ -146,3 +146,13 @@ def tune(n, src, dst, kinds, offs, xs, ys, sub=None, nsub=0, space=None, order=N
         if not improved:
             break
     return best, best_t, trials
+
+
+def params_for(n, m, batch_sizes, path=DEFAULT_FILE):
+    """(parameters, source) for a workload: the stored entry for its
+    signature when there is one, else the library defaults."""
+    key = signature(n, m, batch_sizes)
+    stored = load_tuning(key, path)
+    if stored is not None:
+        return stored, f"tuning.json[{key}]"
+    return dict(DEFAULTS), "library defaults"
