@@ -64,6 +64,7 @@ extern "C" {
 #define CM_E_DEVICE (-11)   /* HIP runtime error; the handle is poisoned */
 #define CM_E_INTERNAL (-12) /* internal invariant violated (queue overflow); handle poisoned */
 #define CM_E_BUSY (-13)     /* serving: the request must wait (ring, payload space or budget full) */
+#define CM_E_IO (-14)       /* snapshot file missing, unreadable, corrupt or inconsistent */
 
 /* Execution forms of the update path. */
 #define CM_MODE_PLAIN 0     /* host loop: one cooperative launch per superior edge set */
@@ -95,6 +96,13 @@ typedef struct cm_config {
                                    work-queue step instead of one grid-wide step per round */
     int32_t single_edge;        /* 1 = one edge per iteration (the sequential regime the
                                    paper compares against) instead of a superior edge set */
+    int32_t debug;              /* > 0 = keep the iteration log of the last update call
+                                   (cm_debug_log) with room for 2^20 entries of each kind,
+                                   or for `debug` entries when debug > 1 */
+    int32_t expand_mode;        /* insertion's subcore expansion (Algorithm 3): 1 = a candidate
+                                   visits its neighbours only once its CSD exceeds its core (the
+                                   algorithm's pruning); 2 = it claims them while counting its
+                                   CSD (one pass per list, a larger visited set); 0 = default (1) */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 
@@ -109,8 +117,15 @@ typedef struct cm_batch_stats {
     int64_t evicted;        /* sum of evicted (insert) / peeled (delete) vertices */
     int64_t changed;        /* sum of vertices whose core moved */
     int64_t scanned;        /* adjacency entries read by traversal phases */
-    int64_t alg_bytes;      /* algorithmic HBM bytes of the maintenance launches */
+    int64_t alg_bytes;      /* algorithmic HBM bytes of the method's own work on the batch:
+                               32 per remaining edge per iteration (partition), 40 per applied
+                               edge (validation and apply), per candidate and per evicted vertex
+                               16 + 12 per list entry (CSD count; counter decrements), per
+                               changed vertex 20 per list entry (SD recount, neighbour deltas) */
     int64_t rounds;         /* cascade rounds (expansion, eviction, peel) */
+    int64_t cand_degree;    /* sum of list lengths over the insertion candidates visited */
+    int64_t evicted_degree; /* sum of list lengths over the evicted / peeled vertices */
+    int64_t changed_degree; /* sum of list lengths over the vertices whose core moved */
     int64_t grid_steps;     /* steps run by the whole grid (each ends in a grid barrier) */
     int64_t local_steps;    /* steps run inside one workgroup */
     int32_t launches;       /* maintenance kernel launches (plain mode: one per superior edge
@@ -299,6 +314,36 @@ int cm_serve_result(cm_graph *g, int64_t ticket, cm_batch_stats *out);
 
 /* Finish every admitted request, end the launch and leave serving. */
 int cm_serve_stop(cm_graph *g);
+
+/* Checkpoint: write the graph's state to the file at path -- id count, live
+ * count, the core number of every id (-1 for dead ids), the maintained SD
+ * of every id, and the edge set -- so that cm_restore can continue the
+ * update stream exactly where it stopped (core numbers are a function of
+ * the graph, Section III, and SD of the cores, Section IV-B).  Needs a
+ * decomposed graph; the graph is not changed.  CM_E_IO when the file cannot
+ * be written. */
+int cm_snapshot(cm_graph *g, const char *path);
+
+/* Create a handle (cfg as for cm_create, may be NULL) holding the state
+ * written by cm_snapshot, without a new decomposition.  CM_E_IO when the
+ * file is missing, truncated, fails its checksum or is inconsistent (a
+ * core outside [-1, n_ids), an edge at a dead or out-of-range id, a live
+ * count that does not match).  *out is NULL on failure. */
+int cm_restore(const cm_config *cfg, const char *path, cm_graph **out);
+
+/* Iteration log of the last update call on a handle created with
+ * cfg.debug > 0 (Algorithms 1 and 5 step by step): sel receives sel_cap
+ * entries of 3 int32 (iteration stamp, u, v), one per edge of a selected
+ * superior edge set, u < v; chg receives chg_cap entries (iteration stamp,
+ * v, new core), one per core number moved by an edge iteration.  Stamps
+ * grow by one per iteration, so the entries of one stamp are one superior
+ * edge set and the core changes it caused.  *n_sel / *n_chg receive the
+ * counts recorded.  Vertex-star iterations (vertex operations in the
+ * persistent form and in batch programs) are not logged.  CM_E_STATE
+ * without debug mode; CM_E_CAPACITY when the log overflowed (entries past
+ * its capacity are lost; the counts still report the totals). */
+int cm_debug_log(cm_graph *g, int64_t *n_sel, int32_t *sel, int64_t sel_cap, int64_t *n_chg, int32_t *chg,
+                 int64_t chg_cap);
 
 /* Phase clock of the maintenance kernels, for profiling one persistent
  * launch from the inside: ms[i] (host, n <= 16 entries) receives the device

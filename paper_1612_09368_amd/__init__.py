@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libcoremaint.so")
 
 OK = 0
 E_ARG, E_RANGE, E_SELF_LOOP, E_DUP, E_EXISTS, E_MISSING, E_DEAD = -1, -2, -3, -4, -5, -6, -7
-E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL, E_BUSY = -8, -9, -10, -11, -12, -13
+E_NOMEM, E_CAPACITY, E_STATE, E_DEVICE, E_INTERNAL, E_BUSY, E_IO = -8, -9, -10, -11, -12, -13, -14
 MODE_PLAIN, MODE_PERSISTENT = 0, 1
 BATCH_INSERT, BATCH_DELETE = 0, 1
 
@@ -32,6 +32,7 @@ EXPORTED = [
     "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees", "cm_run_batches", "cm_phase_times",
     "cm_serve_config_default", "cm_serve_start", "cm_serve_submit_edges", "cm_serve_submit_insert_vertices",
     "cm_serve_submit_delete_vertices", "cm_serve_poll", "cm_serve_result", "cm_serve_stop",
+    "cm_snapshot", "cm_restore", "cm_debug_log",
 ]
 REQ_INSERT_EDGES, REQ_DELETE_EDGES, REQ_INSERT_VERTICES, REQ_DELETE_VERTICES = 0, 1, 2, 3
 
@@ -54,6 +55,8 @@ class Config(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("async_steps", ctypes.c_int32),
         ("single_edge", ctypes.c_int32),
+        ("debug", ctypes.c_int32),
+        ("expand_mode", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -84,6 +87,9 @@ class BatchStats(ctypes.Structure):
         ("scanned", ctypes.c_int64),
         ("alg_bytes", ctypes.c_int64),
         ("rounds", ctypes.c_int64),
+        ("cand_degree", ctypes.c_int64),
+        ("evicted_degree", ctypes.c_int64),
+        ("changed_degree", ctypes.c_int64),
         ("grid_steps", ctypes.c_int64),
         ("local_steps", ctypes.c_int64),
         ("launches", ctypes.c_int32),
@@ -141,6 +147,9 @@ def library():
         "cm_serve_poll": (ctypes.c_int, [P, P]),
         "cm_serve_result": (ctypes.c_int, [P, I64, P]),
         "cm_serve_stop": (ctypes.c_int, [P]),
+        "cm_snapshot": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "cm_restore": (ctypes.c_int, [P, ctypes.c_char_p, P]),
+        "cm_debug_log": (ctypes.c_int, [P, P, P, I64, P, P, I64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -187,7 +196,7 @@ class Graph:
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
                  local_edges=0, local_items=0, local_work=0, timing=False, use_graph=False, async_steps=False,
-                 single_edge=False, stream=None):
+                 single_edge=False, debug=0, expand_mode=0, stream=None, _restore_from=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -207,15 +216,45 @@ class Graph:
         cfg.use_graph = 1 if use_graph else 0
         cfg.async_steps = 1 if async_steps else 0
         cfg.single_edge = 1 if single_edge else 0
+        cfg.debug = int(debug)
+        cfg.expand_mode = int(expand_mode)
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()
-        st = lib.cm_create(ctypes.byref(cfg), ctypes.byref(h))
+        if _restore_from is None:
+            st = lib.cm_create(ctypes.byref(cfg), ctypes.byref(h))
+            what = "cm_create"
+        else:
+            st = lib.cm_restore(ctypes.byref(cfg), os.fsencode(_restore_from), ctypes.byref(h))
+            what = "cm_restore"
         if st != OK:
-            raise CoreMaintError(st, "cm_create: " + lib.cm_strerror(st).decode())
+            raise CoreMaintError(st, f"{what}: " + lib.cm_strerror(st).decode())
         self._lib = lib
         self._h = h
         self.config = cfg
         self.last_stats = None
+
+    @classmethod
+    def restore(cls, path, **cfg):
+        """A new handle holding the state cm_snapshot wrote to `path`."""
+        return cls(_restore_from=path, **cfg)
+
+    def snapshot(self, path):
+        """Write the graph's state (ids, cores, SD, edges) to `path`."""
+        self._check(self._lib.cm_snapshot(self._h, os.fsencode(path)), "cm_snapshot")
+
+    def debug_log(self):
+        """Iteration log of the last update call (debug mode): (sel, chg),
+        int32 arrays of shape (k, 3): (iteration stamp, u, v) per selected
+        edge and (iteration stamp, v, new core) per core change."""
+        ns, nc = ctypes.c_int64(), ctypes.c_int64()
+        st = self._lib.cm_debug_log(self._h, ctypes.byref(ns), None, 0, ctypes.byref(nc), None, 0)
+        self._check(st, "cm_debug_log")
+        sel = np.empty((max(ns.value, 1), 3), dtype=np.int32)
+        chg = np.empty((max(nc.value, 1), 3), dtype=np.int32)
+        st = self._lib.cm_debug_log(self._h, ctypes.byref(ns), ctypes.c_void_p(sel.ctypes.data), ns.value,
+                                    ctypes.byref(nc), ctypes.c_void_p(chg.ctypes.data), nc.value)
+        self._check(st, "cm_debug_log")
+        return sel[:ns.value], chg[:nc.value]
 
     def close(self):
         if getattr(self, "_h", None):

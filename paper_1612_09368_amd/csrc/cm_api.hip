@@ -68,6 +68,7 @@ struct cm_graph {
     int64_t items_cap = 0;
     unsigned long long *d_sub_bad = nullptr;
     int32_t sub_cap = 0;
+    DebugLog dl{};            // iteration log (cfg.debug), allocated by cm_create
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<char> graph_key;
@@ -181,7 +182,13 @@ KArgs make_args(cm_graph *g) {
     a.t = g->tune;
     a.ctl = g->ctl;
     a.bar = g->bar;
+    a.dl = g->dl;
     return a;
+}
+
+// Debug mode: every update call starts an empty iteration log.
+void debug_reset(cm_graph *g) {
+    if (g->dl.n) HIPCHK(fill_u64(g->dl.n, 0ull, 2, g->stream));
 }
 
 void sync_ctl(cm_graph *g) {
@@ -432,18 +439,34 @@ void fill_stats(cm_graph *g, cm_batch_stats *st, int64_t applied, int64_t droppe
     st->rounds = (int64_t)c.st_rounds;
     st->grid_steps = (int64_t)c.st_grid_steps;
     st->local_steps = (int64_t)c.st_local_steps;
+    st->cand_degree = (int64_t)c.st_cdeg;
+    st->evicted_degree = (int64_t)c.st_edeg;
+    st->changed_degree = (int64_t)c.st_hdeg;
 }
 
-// Algorithmic bytes of the maintenance launches of a batch: what the method
-// must read or write, counted once per access (no cache effects):
-//  partition, per remaining edge and claim round: edge index 4 + endpoints 8
-//    + two core gathers 8 + claim atomics 16 (claim and select passes) = 36
-//  apply, per selected edge: list append or tombstone 2x(4+8) + SD update 8 = 32
-//  traversal, per adjacency entry read: id 4 + core 4 + SD/counter 4 = 12
-//  per candidate / changed vertex: list offset and length 12 + counter 4 = 16
-int64_t alg_bytes(const Ctl &c, int rounds) {
-    return (int64_t)(36ull * c.st_remaining * (unsigned long long)rounds + 32ull * c.st_selected +
-                     12ull * c.st_scanned + 16ull * (c.st_candidates + c.st_changed));
+// Algorithmic bytes of a batch: what the method itself must move, from the
+// sets Algorithms 1-7 define, counted once per access (no cache effects) and
+// independent of how many list entries the kernels happen to scan:
+//  partition, per remaining edge per iteration: edge 8 + two core gathers 8
+//    + claim atomic and read 8 + compaction 8 = 32
+//  validation and apply, per applied edge: 2 x (length atomic 4 + entry 4 +
+//    slot 4) + SD deltas 8 + validation 8 = 40
+//  per insertion candidate (CSD count) and per evicted / peeled vertex
+//    (counter decrements): offset and length 16 + per list entry id, core
+//    and SD or counter 12
+//  per vertex whose core moved: per list entry 20 (SD recount: id + core;
+//    neighbour delta: core + atomic + id)
+int64_t alg_bytes(unsigned long long remaining, unsigned long long applied, unsigned long long icand,
+                  unsigned long long cdeg, unsigned long long evicted, unsigned long long edeg,
+                  unsigned long long hdeg) {
+    return (int64_t)(32ull * remaining + 40ull * applied + 16ull * icand + 12ull * cdeg + 16ull * evicted +
+                     12ull * edeg + 20ull * hdeg);
+}
+int64_t alg_bytes(const Ctl &c) {
+    return alg_bytes(c.st_remaining, c.st_selected, c.st_icand, c.st_cdeg, c.st_evicted, c.st_edeg, c.st_hdeg);
+}
+int64_t alg_bytes(const ProgOut &o) {
+    return alg_bytes(o.remaining, o.selected, o.icand, o.cdeg, o.evicted, o.edeg, o.hdeg);
 }
 
 // Validate a batch already staged in g->b.src_in/dst_in (s items).  Returns
@@ -602,7 +625,7 @@ void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
     if (stats) {
         stats->launches = launches;
         stats->kernel_ms = kms;
-        stats->alg_bytes = alg_bytes(*g->hctl, g->tune.rounds);
+        stats->alg_bytes = alg_bytes(*g->hctl);
     }
 }
 
@@ -796,13 +819,10 @@ void stats_from_out(cm_graph *g, const ProgOut &o, int64_t items, int launches, 
     r->scanned = (int64_t)o.scanned;
     r->rounds = (int64_t)o.rounds;
     r->local_steps = (int64_t)o.steps;
-    Ctl tmp{};
-    tmp.st_remaining = o.remaining;
-    tmp.st_selected = o.selected;
-    tmp.st_scanned = o.scanned;
-    tmp.st_candidates = o.candidates;
-    tmp.st_changed = o.changed;
-    r->alg_bytes = alg_bytes(tmp, g->tune.rounds);
+    r->alg_bytes = alg_bytes(o);
+    r->cand_degree = (int64_t)o.cdeg;
+    r->evicted_degree = (int64_t)o.edeg;
+    r->changed_degree = (int64_t)o.hdeg;
     r->launches = launches;
     r->kernel_ms = kms;
 }
@@ -904,6 +924,7 @@ const char *cm_strerror(int status) {
     case CM_E_STATE: return "invalid state";
     case CM_E_DEVICE: return "device error";
     case CM_E_INTERNAL: return "internal error";
+    case CM_E_IO: return "snapshot file error";
     default: return "unknown status";
     }
 }
@@ -940,6 +961,11 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         g->tune.async_steps = g->cfg.async_steps ? 1 : 0;
         g->tune.single_edge = g->cfg.single_edge ? 1 : 0;
+        if (g->cfg.expand_mode < 0 || g->cfg.expand_mode > 2) {
+            g->err = "expand_mode must be 0, 1 or 2";
+            throw Fail{CM_E_ARG};
+        }
+        g->tune.prune = g->cfg.expand_mode == 2 ? 0 : 1;
         if (g->tune.single_edge) g->tune.rounds = 1;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
@@ -966,6 +992,17 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         dev_alloc(g, &g->u64_scratch, 4);
         HIPCHK(hipEventCreate(&g->ev0));
         HIPCHK(hipEventCreate(&g->ev1));
+        if (g->cfg.debug < 0) {
+            g->err = "debug must be >= 0";
+            throw Fail{CM_E_ARG};
+        }
+        if (g->cfg.debug) {
+            g->dl.cap = g->cfg.debug > 1 ? (int64_t)g->cfg.debug : ((int64_t)1 << 20);
+            dev_alloc(g, &g->dl.sel, 3 * g->dl.cap);
+            dev_alloc(g, &g->dl.chg, 3 * g->dl.cap);
+            dev_alloc(g, &g->dl.n, 2);
+            HIPCHK(fill_u64(g->dl.n, 0ull, 2, g->stream));
+        }
         HIPCHK(hipHostMalloc((void **)&g->lout, sizeof(LaunchOut) * cm_graph::LSLOTS, hipHostMallocDefault));
         std::memset(g->lout, 0, sizeof(LaunchOut) * cm_graph::LSLOTS);
         for (auto &pr : g->lev)
@@ -999,6 +1036,9 @@ void cm_destroy(cm_graph *g) {
         for (auto &e : pr)
             if (e) (void)hipEventDestroy(e);
     if (g->lout) (void)hipHostFree(g->lout);
+    dev_free(g->dl.sel);
+    dev_free(g->dl.chg);
+    dev_free(g->dl.n);
     delete g;
 }
 
@@ -1149,6 +1189,7 @@ static int edge_call(cm_graph *g, int64_t s, const int32_t *src, const int32_t *
     if (s < 0 || (s > 0 && (!src || !dst))) return finish(g, CM_E_ARG, stats, t0);
     try {
         require_ready(g, true);
+        debug_reset(g);
         if (s == 0) return finish(g, CM_OK, stats, t0);
         ensure_batch(g, s);
         stage_inputs(g, s, src, dst, on_device);
@@ -1184,6 +1225,7 @@ int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t
     bool counted = false;
     try {
         require_ready(g, true);
+        debug_reset(g);
         hipStream_t st = g->stream;
         first = g->g.n_ids;
         if (first_new_id) *first_new_id = first;
@@ -1288,6 +1330,7 @@ int cm_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int on_device
     if (c < 0 || (c > 0 && !ids)) return finish(g, CM_E_ARG, stats, t0);
     try {
         require_ready(g, true);
+        debug_reset(g);
         if (c == 0) return finish(g, CM_OK, stats, t0);
         hipStream_t st = g->stream;
         int32_t *dids = nullptr;
@@ -1484,13 +1527,10 @@ void serve_collect(cm_graph *g) {
         r.scanned = (int64_t)o.scanned;
         r.rounds = (int64_t)o.rounds;
         r.local_steps = (int64_t)o.steps;
-        Ctl tmp{};
-        tmp.st_remaining = o.remaining;
-        tmp.st_selected = o.selected;
-        tmp.st_scanned = o.scanned;
-        tmp.st_candidates = o.candidates;
-        tmp.st_changed = o.changed;
-        r.alg_bytes = alg_bytes(tmp, g->tune.rounds);
+        r.alg_bytes = alg_bytes(o);
+        r.cand_degree = (int64_t)o.cdeg;
+        r.evicted_degree = (int64_t)o.edeg;
+        r.changed_degree = (int64_t)o.hdeg;
         if (o.status == 0) {
             const bool ins = b.kind == 0 || b.kind == 2;
             g->m += ins ? o.valid : -(int64_t)o.valid;
@@ -1844,6 +1884,205 @@ int cm_serve_stop(cm_graph *g) {
     return CM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Snapshot file: header, then int32 core[n_ids], int32 SD[n_ids], and the m
+// edges as int32 src[m], int32 dst[m] (each undirected edge once, (min, max)).
+struct SnapHeader {
+    char magic[8];
+    int32_t version;
+    int32_t n_ids;
+    int32_t n_alive;
+    int32_t pad;
+    int64_t m;
+    uint64_t checksum;  // word-wise FNV-1a of the payload
+};
+constexpr char SNAP_MAGIC[8] = {'C', 'M', 'S', 'N', 'A', 'P', '0', '1'};
+constexpr int32_t SNAP_VERSION = 1;
+
+void fnv_words(uint64_t &h, const int32_t *p, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= (uint64_t)(uint32_t)p[i];
+        h *= 0x100000001b3ull;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int cm_snapshot(cm_graph *g, const char *path) {
+    if (!g || !path) return CM_E_ARG;
+    try {
+        require_ready(g, true);
+        hipStream_t st = g->stream;
+        const int32_t n = g->g.n_ids;
+        const int64_t m = g->m;
+        std::vector<int32_t> core((size_t)std::max(n, 1)), sd((size_t)std::max(n, 1));
+        std::vector<int32_t> xs((size_t)std::max<int64_t>(m, 1)), ys((size_t)std::max<int64_t>(m, 1));
+        if (n > 0) {
+            HIPCHK(hipMemcpyAsync(core.data(), g->g.core, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(sd.data(), g->g.mcd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+        }
+        if (m > 0) {
+            int32_t *dx = nullptr, *dy = nullptr;
+            dev_alloc(g, &dx, m);
+            dev_alloc(g, &dy, m);
+            HIPCHK(fill_u64(g->u64_scratch, 0ull, 1, st));
+            KArgs a = make_args(g);
+            HIPCHK(export_edges(a, dx, dy, m, g->u64_scratch, g->grid_reg, st));
+            HIPCHK(hipMemcpyAsync(xs.data(), dx, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(ys.data(), dy, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            dev_free(dx);
+            dev_free(dy);
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        for (int32_t v = 0; v < n; ++v)
+            if (core[(size_t)v] < 0) sd[(size_t)v] = 0;
+        SnapHeader h{};
+        std::memcpy(h.magic, SNAP_MAGIC, 8);
+        h.version = SNAP_VERSION;
+        h.n_ids = n;
+        h.n_alive = g->n_alive;
+        h.m = m;
+        uint64_t cs = 0xcbf29ce484222325ull;
+        fnv_words(cs, core.data(), (size_t)n);
+        fnv_words(cs, sd.data(), (size_t)n);
+        fnv_words(cs, xs.data(), (size_t)m);
+        fnv_words(cs, ys.data(), (size_t)m);
+        h.checksum = cs;
+        FILE *f = std::fopen(path, "wb");
+        if (!f) {
+            g->err = std::string("cannot open ") + path + " for writing";
+            return CM_E_IO;
+        }
+        bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+        ok = ok && std::fwrite(core.data(), sizeof(int32_t), (size_t)n, f) == (size_t)n;
+        ok = ok && std::fwrite(sd.data(), sizeof(int32_t), (size_t)n, f) == (size_t)n;
+        ok = ok && std::fwrite(xs.data(), sizeof(int32_t), (size_t)m, f) == (size_t)m;
+        ok = ok && std::fwrite(ys.data(), sizeof(int32_t), (size_t)m, f) == (size_t)m;
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) {
+            g->err = std::string("write to ") + path + " failed";
+            return CM_E_IO;
+        }
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    g->err.clear();
+    return CM_OK;
+}
+
+int cm_restore(const cm_config *cfg, const char *path, cm_graph **out) {
+    if (!path || !out) return CM_E_ARG;
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return CM_E_IO;
+    SnapHeader h{};
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, SNAP_MAGIC, 8) == 0 &&
+              h.version == SNAP_VERSION && h.n_ids >= 0 && h.n_ids < INT_MAX - 1 && h.m >= 0 &&
+              h.n_alive >= 0 && h.n_alive <= h.n_ids;
+    std::vector<int32_t> core, sd, xs, ys;
+    if (ok) {
+        // the payload must be exactly the size the header announces
+        const long here = std::ftell(f);
+        ok = here >= 0 && std::fseek(f, 0, SEEK_END) == 0;
+        const long end = ok ? std::ftell(f) : -1;
+        ok = ok && end >= here && (uint64_t)(end - here) == 4ull * (2ull * (uint64_t)h.n_ids + 2ull * (uint64_t)h.m) &&
+             std::fseek(f, here, SEEK_SET) == 0;
+    }
+    if (ok) {
+        const size_t n = (size_t)h.n_ids, m = (size_t)h.m;
+        core.resize(std::max<size_t>(n, 1));
+        sd.resize(std::max<size_t>(n, 1));
+        xs.resize(std::max<size_t>(m, 1));
+        ys.resize(std::max<size_t>(m, 1));
+        ok = std::fread(core.data(), sizeof(int32_t), n, f) == n && std::fread(sd.data(), sizeof(int32_t), n, f) == n &&
+             std::fread(xs.data(), sizeof(int32_t), m, f) == m && std::fread(ys.data(), sizeof(int32_t), m, f) == m;
+        if (ok) {
+            uint64_t cs = 0xcbf29ce484222325ull;
+            fnv_words(cs, core.data(), n);
+            fnv_words(cs, sd.data(), n);
+            fnv_words(cs, xs.data(), m);
+            fnv_words(cs, ys.data(), m);
+            ok = cs == h.checksum;
+        }
+        // consistency: cores in range, dead ids hold no edge, the alive count matches
+        int64_t alive = 0;
+        for (size_t v = 0; ok && v < n; ++v) {
+            ok = core[v] >= -1 && core[v] < h.n_ids && sd[v] >= 0 && (core[v] >= 0 || sd[v] == 0);
+            alive += core[v] >= 0;
+        }
+        ok = ok && alive == h.n_alive;
+        for (size_t e = 0; ok && e < m; ++e)
+            ok = xs[e] >= 0 && xs[e] < h.n_ids && ys[e] >= 0 && ys[e] < h.n_ids && core[(size_t)xs[e]] >= 0 &&
+                 core[(size_t)ys[e]] >= 0;
+    }
+    std::fclose(f);
+    if (!ok) return CM_E_IO;
+    cm_graph *g = nullptr;
+    int rc = cm_create(cfg, &g);
+    if (rc != CM_OK) return rc;
+    rc = cm_load_graph(g, h.n_ids, h.m, xs.data(), ys.data(), 0);
+    if (rc != CM_OK) {
+        cm_destroy(g);
+        return rc == CM_E_NOMEM || rc == CM_E_DEVICE ? rc : CM_E_IO;
+    }
+    try {
+        hipStream_t st = g->stream;
+        if (h.n_ids > 0) {
+            HIPCHK(hipMemcpyAsync(g->g.core, core.data(), sizeof(int32_t) * (size_t)h.n_ids, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(g->g.mcd, sd.data(), sizeof(int32_t) * (size_t)h.n_ids, hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        g->n_alive = h.n_alive;
+        g->decomposed = true;
+    } catch (const Fail &fl) {
+        cm_destroy(g);
+        return fl.code;
+    }
+    *out = g;
+    return CM_OK;
+}
+
+int cm_debug_log(cm_graph *g, int64_t *n_sel, int32_t *sel, int64_t sel_cap, int64_t *n_chg, int32_t *chg,
+                 int64_t chg_cap) {
+    if (!g || sel_cap < 0 || chg_cap < 0 || (sel_cap > 0 && !sel) || (chg_cap > 0 && !chg)) return CM_E_ARG;
+    if (!g->dl.n) {
+        g->err = "the iteration log needs cm_config.debug";
+        return CM_E_STATE;
+    }
+    if (g->serving) {
+        g->err = "the graph is being served (call cm_serve_stop first)";
+        return CM_E_STATE;
+    }
+    try {
+        hipStream_t st = g->stream;
+        unsigned long long cnt[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(cnt, g->dl.n, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (n_sel) *n_sel = (int64_t)cnt[0];
+        if (n_chg) *n_chg = (int64_t)cnt[1];
+        const int64_t ks = std::min<int64_t>(std::min<int64_t>((int64_t)cnt[0], g->dl.cap), sel_cap);
+        const int64_t kc = std::min<int64_t>(std::min<int64_t>((int64_t)cnt[1], g->dl.cap), chg_cap);
+        if (ks > 0)
+            HIPCHK(hipMemcpyAsync(sel, g->dl.sel, sizeof(int32_t) * 3 * (size_t)ks, hipMemcpyDeviceToHost, st));
+        if (kc > 0)
+            HIPCHK(hipMemcpyAsync(chg, g->dl.chg, sizeof(int32_t) * 3 * (size_t)kc, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if ((int64_t)cnt[0] > g->dl.cap || (int64_t)cnt[1] > g->dl.cap) {
+            g->err = "the iteration log overflowed its capacity";
+            return CM_E_CAPACITY;
+        }
+    } catch (const Fail &f) {
+        return f.code;
+    }
+    return CM_OK;
+}
+
 int cm_phase_times(cm_graph *g, double *ms, int64_t *counts, int32_t n, int reset) {
     if (!g || n < 0 || n > PH_SLOTS || (n > 0 && !ms)) return CM_E_ARG;
     try {
@@ -1929,6 +2168,7 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
         for (int32_t b = 0; b < nsub; ++b) sub_status[b] = CM_OK;
     try {
         require_ready(g, true);
+        debug_reset(g);
         if (nb == 0) return CM_OK;
         if (offsets[0] != 0) { g->err = "offsets[0] must be 0"; throw Fail{CM_E_ARG}; }
         int64_t max_s = 0;
@@ -2026,13 +2266,10 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
                 r.scanned = (int64_t)o.scanned;
                 r.rounds = (int64_t)o.rounds;
                 r.local_steps = (int64_t)o.steps;
-                Ctl tmp{};
-                tmp.st_remaining = o.remaining;
-                tmp.st_selected = o.selected;
-                tmp.st_scanned = o.scanned;
-                tmp.st_candidates = o.candidates;
-                tmp.st_changed = o.changed;
-                r.alg_bytes = alg_bytes(tmp, g->tune.rounds);
+                r.alg_bytes = alg_bytes(o);
+                r.cand_degree = (int64_t)o.cdeg;
+                r.evicted_degree = (int64_t)o.edeg;
+                r.changed_degree = (int64_t)o.hdeg;
                 r.launches = j == 0 ? launches : 0;
                 r.graph_launch = used_graph;
                 r.kernel_ms = j == 0 ? kms : 0.0;

@@ -75,6 +75,10 @@ struct Ctl {
     unsigned long long st_rounds;       // cascade rounds (expansion, eviction, peel)
     unsigned long long st_grid_steps;   // steps run by the whole grid
     unsigned long long st_local_steps;  // steps run inside one workgroup
+    unsigned long long st_icand;        // insertion candidates visited
+    unsigned long long st_cdeg;         // list entries of the insertion candidates
+    unsigned long long st_edeg;         // list entries of the evicted / peeled vertices
+    unsigned long long st_hdeg;         // list entries of the vertices whose core moved
     // phase clock (device wall clock ticks, summed until the host clears them;
     // written by global thread 0 only): indices are StepKind for grid steps,
     // then PH_LOCAL .. PH_COMPACT below
@@ -191,8 +195,13 @@ struct Tune {
     int32_t local_work;  // ... and only if their lists hold at most this many entries
     int32_t async_steps; // cascades as work-queue steps
     int32_t single_edge; // one edge per iteration (the sequential regime) instead of a superior edge set
-    int32_t pad;
+    int32_t prune;       // expansion visits the neighbours of a candidate only once its CSD exceeds its
+                         // core (Algorithm 3); 0 = claims them while counting the CSD
 };
+
+// Chunk items of the expansion's claim pass (pruned expansion) carry this
+// flag in the chunk index.
+constexpr int32_t CLAIM_CHUNK = 0x40000000;
 
 constexpr int COOP_THREADS = 512;  // workgroup size of the cooperative kernels
 
@@ -210,6 +219,17 @@ struct LaunchOut {
     int32_t pad[3];
 };
 
+// Debug log of the iterations (cm_config.debug): every selected edge of an
+// edge iteration as (iteration stamp, u, v) with u < v, and every core change
+// of an edge iteration as (iteration stamp, v, new core).  n[i] counts the
+// entries recorded (it may pass cap: the entries beyond cap are lost).
+struct DebugLog {
+    int32_t *sel;              // [3 * cap] or null when the log is off
+    int32_t *chg;              // [3 * cap]
+    unsigned long long *n;     // [2]
+    int64_t cap;
+};
+
 struct KArgs {
     DevGraph g;
     DevBatch b;
@@ -225,6 +245,7 @@ struct KArgs {
     int32_t cur;         // remaining list that receives the validated batch
     int32_t strict;      // packed sub-batches: drop a sub-batch with an invalid item
     LaunchOut *lout;     // maintenance launch outcome (pinned host) or null
+    DebugLog dl;         // iteration log (debug mode) or all null
 };
 
 // Per-batch parameters of the validation / reservation steps.
@@ -256,6 +277,7 @@ struct ProgOut {
     int32_t vdone;       // vertex batches: vertices inserted / deleted
     int32_t pad;
     unsigned long long remaining, selected, candidates, evicted, changed, scanned, rounds, steps;
+    unsigned long long icand, cdeg, edeg, hdeg;
 };
 // Why a serving launch ended (ServeHdr.exit_reason; 0 while it runs).
 enum ServeExit : int32_t { SV_RUN = 1, SV_STOP = 2, SV_IDLE = 3, SV_POOL = 4, SV_ABORT = 5, SV_TOOBIG = 6 };

@@ -50,6 +50,7 @@ __global__ void k_ctl_batch_reset(Ctl *c, int cur) {
         c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
         c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
         c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
+        c->st_icand = 0; c->st_cdeg = 0; c->st_edeg = 0; c->st_hdeg = 0;
         (void)cur;
     }
 }
@@ -323,9 +324,9 @@ __global__ void k_dec_prep(KArgs a) {
 
 __global__ void __launch_bounds__(COOP_THREADS) k_decompose(KArgs a) {
     gbar_setup(a.bar);
-    long long scanned = 0;
-    decompose(a, scanned);
-    flush_stat(&a.ctl->st_scanned, scanned);
+    Acc acc{};
+    decompose(a, acc);
+    flush_acc(a.ctl, acc);
 }
 
 __global__ void k_mcd_init(KArgs a) {
@@ -368,10 +369,10 @@ __global__ void k_del_compact(KArgs a) { del_compact(a, grid_team()); }
 __global__ void __launch_bounds__(COOP_THREADS) k_maintain(KArgs a) {
     gbar_setup(a.bar);
     int32_t ep = ld_rlx(&a.ctl->epoch);
-    long long scanned = 0;
+    Acc acc{};
     int pubs = 0;
-    int n = run_iterations(a, a.inserting, a.max_iters, ep, scanned, pubs);
-    flush_stat(&a.ctl->st_scanned, scanned);
+    int n = run_iterations(a, a.inserting, a.max_iters, ep, acc, pubs);
+    flush_acc(a.ctl, acc);
     if (gtid() == 0) {
         a.ctl->epoch = ep;
         a.ctl->iters_done = n;

@@ -21,11 +21,46 @@ __device__ __forceinline__ void flush_stat(unsigned long long *dst, long long v)
     if (lane() == 0 && v) atomicAdd(dst, (unsigned long long)v);
 }
 
+// Per-thread statistics of a launch, kept in registers and summed into the
+// control block at the end of a batch: adjacency entries read by the
+// traversal phases, and the list entries of the method's sets (insertion
+// candidates, evicted / peeled vertices, vertices whose core moved).
+struct Acc {
+    long long scanned, cdeg, edeg, hdeg;
+};
+__device__ __forceinline__ void flush_acc(Ctl *c, Acc &acc) {
+    flush_stat(&c->st_scanned, acc.scanned);
+    flush_stat(&c->st_cdeg, acc.cdeg);
+    flush_stat(&c->st_edeg, acc.edeg);
+    flush_stat(&c->st_hdeg, acc.hdeg);
+    acc = Acc{};
+}
+
 // Queue length as published by its tail, clamped to the buffer capacity
 // (a tail can pass the capacity only after an overflow, which aborts the batch).
 __device__ __forceinline__ int32_t qlen(const int32_t *tail, int32_t cap) {
     int32_t n = ld_rlx(tail);
     return n < cap ? n : cap;
+}
+
+// Debug log entry (a, b, c) for every active lane with pred set (one
+// atomic per wave).
+__device__ __forceinline__ void dbg_put(int32_t *buf, unsigned long long *cnt, int64_t cap, bool pred, int32_t x,
+                                        int32_t y, int32_t z) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane() == leader) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) {
+        const unsigned long long pos = base + (unsigned long long)__popcll(m & ((1ull << lane()) - 1ull));
+        if (pos < (unsigned long long)cap) {
+            buf[3 * pos] = x;
+            buf[3 * pos + 1] = y;
+            buf[3 * pos + 2] = z;
+        }
+    }
 }
 
 // Count the active lanes with pred set into *ctr (one atomic per wave).
@@ -601,6 +636,7 @@ __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int 
             if (fu) a.g.matched[u] = mstamp;
             if (fv) a.g.matched[v] = mstamp;
         }
+        if (a.dl.sel) dbg_put(a.dl.sel, &a.dl.n[0], a.dl.cap, win, it.ep, u, v);
         // a winner applies itself in this step (no separate apply step)
         if (it.ins) apply_edge_insert(a, it, i, win);
         else apply_edge_delete(a, it, i, win);
@@ -679,7 +715,7 @@ __device__ __forceinline__ bool star_old_edge(const KArgs &a, const StarCtx &sc,
 // h-index of the current cores of star v's existing neighbours (wave-wide;
 // every lane returns it).
 __device__ __forceinline__ int32_t star_hindex(const KArgs &a, const StarCtx &sc, int32_t lo, int32_t hi,
-                                               long long &scanned) {
+                                               Acc &acc) {
     int32_t deg = 0;
     for (int32_t j = lo + lane(); j < hi; j += WAVE) {
         int32_t w;
@@ -698,7 +734,7 @@ __device__ __forceinline__ int32_t star_hindex(const KArgs &a, const StarCtx &sc
         if (cnt >= mid) l = mid;
         else h = mid - 1;
     }
-    if (lane() == 0) scanned += (long long)(hi - lo);
+    if (lane() == 0) acc.scanned += (long long)(hi - lo);
     return l;
 }
 
@@ -713,7 +749,7 @@ __device__ __forceinline__ bool star_del_claims(const KArgs &a, const StarCtx &s
     return sc.firstidx[w] != 0x7fffffff || a.g.core[w] <= a.g.core[x];
 }
 
-__device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
+__device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const StarCtx &sc = it.sc;
     if (T.lead()) {
@@ -737,7 +773,7 @@ __device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const
             const int32_t v = sc.v0 + id;
             int32_t lo, hi;
             star_run(sc, id, lo, hi);
-            const int32_t hk = star_hindex(a, sc, lo, hi, scanned);
+            const int32_t hk = star_hindex(a, sc, lo, hi, acc);
             if (lane() == 0) a.g.dec[v] = hk + 1;  // kept until the star is applied
             for (int32_t j = lo + lane(); j < hi; j += WAVE) {
                 int32_t w;
@@ -762,7 +798,7 @@ __device__ __forceinline__ void star_claim(const KArgs &a, const Iter &it, const
             if (sc.firstidx[v] != 0x7fffffff && star_del_claims(a, sc, v, u))
                 atomicMin(&a.g.claim[u], star_key(it, a, (uint32_t)v));
         }
-        if (T.lead()) scanned += sc.ng;
+        if (T.lead()) acc.scanned += sc.ng;
     }
 }
 
@@ -922,7 +958,7 @@ __device__ __forceinline__ void star_kill(const KArgs &a, const Iter &it, const 
 
 // Asynchronous expansion (Algorithm 3 closure) of the roots pushed into
 // queue 0 by the apply step; evictions go to queue 1.
-__device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, long long &scanned) {
+__device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
@@ -953,7 +989,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
                 if (w >= 0 && is_support(g, w, k)) ++pcd;
             }
             __hip_atomic_store(&g.cd[v], pcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            scanned += L;
+            acc.scanned += L;
         }
         push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, v, lanev, &c->overflow);
         apush(a, 1, aq_item(AQ_V, v, 0), lanev && pcd <= k && L <= a.t.large_deg);
@@ -969,7 +1005,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
                 apush_vertex(a, 0, AQ_CNT, w, act && claim(w, k));
                 ++s;
             }
-            if (lanev && pcd > k) scanned += L;
+            if (lanev && pcd > k) acc.scanned += L;
         }
         // everything else: one wave per item
         unsigned long long m = __ballot(fresh && !lanev);
@@ -995,11 +1031,11 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
                 part = wave_sum(part);
                 if (lane() == 0) {
                     __hip_atomic_store(&g.cd[x], part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    scanned += Lx;
+                    acc.scanned += Lx;
                 }
                 push_agg<int32_t>(a.q.cand, a.q.vcap, &c->cand_count, x, lane() == 0, &c->overflow);
                 if (part > kx) {
-                    if (lane() == 0) scanned += Lx;
+                    if (lane() == 0) acc.scanned += Lx;
                     expand_list(x, 0, Lx, kx);
                 } else {
                     apush(a, 1, aq_item(AQ_V, x, 0), lane() == 0);
@@ -1014,7 +1050,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
                 part = wave_sum(part);
                 int last = 0;
                 if (lane() == 0) {
-                    scanned += hi - lo;
+                    acc.scanned += hi - lo;
                     atomicAdd(&g.cd[x], part);
                     wave_drain();  // the partial sum lands before this chunk counts as done
                     last = atomicAdd(&g.done[x], 1) == nch - 1;
@@ -1033,7 +1069,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
                 }
             } else {  // AQ_EXP: claim the neighbours in one chunk
                 const int32_t lo = cx * a.t.chunk, hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
-                if (lane() == 0) scanned += hi - lo;
+                if (lane() == 0) acc.scanned += hi - lo;
                 expand_list(x, lo, hi, kx);
             }
         }
@@ -1041,7 +1077,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, lon
 }
 
 // Asynchronous eviction (Algorithm 4 cascade) of the vertices in queue 1.
-__device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, long long &scanned) {
+__device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
@@ -1067,7 +1103,7 @@ __device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, long
                 apush_vertex(a, 1, AQ_CH, w, act && hit(w, k));
                 ++s;
             }
-            if (lanev) scanned += L;
+            if (lanev) acc.scanned += L;
         }
         unsigned long long m = __ballot(fresh && !lanev);
         while (m) {
@@ -1082,14 +1118,14 @@ __device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, long
                 lo = aq_c(itw) * a.t.chunk;
                 hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
             }
-            if (lane() == 0) scanned += hi - lo;
+            if (lane() == 0) acc.scanned += hi - lo;
             wave_walk(g, xv, lo, hi, [&](int32_t w, int32_t) { apush_vertex(a, 1, AQ_CH, w, hit(w, kx)); });
         }
     });
 }
 
 // Asynchronous peel (Algorithms 6-7 cascade) of the roots in queue 1.
-__device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, long long &scanned) {
+__device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
@@ -1120,7 +1156,7 @@ __device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, long 
                 body(act ? p[s] : -1, k);
                 ++s;
             }
-            if (lanev) scanned += L;
+            if (lanev) acc.scanned += L;
         }
         unsigned long long m = __ballot(fresh && !lanev);
         while (m) {
@@ -1135,13 +1171,134 @@ __device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, long 
                 lo = aq_c(itw) * a.t.chunk;
                 hi = lo + a.t.chunk < Lx ? lo + a.t.chunk : Lx;
             }
-            if (lane() == 0) scanned += hi - lo;
+            if (lane() == 0) acc.scanned += hi - lo;
             wave_walk(g, xv, lo, hi, [&](int32_t w, int32_t) { body(w, kx); });
         }
     });
 }
 
-__device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+// Positive traversal with Algorithm 3's pruning: a visited vertex first
+// counts its CSD, and only a vertex whose CSD exceeds k visits (claims) its
+// level-k neighbours w with SD(w) > k -- in the same step for a list walked
+// by one wave, and in the next round (chunk items flagged CLAIM_CHUNK) for a
+// long list whose CSD is summed over chunks.  The visited set is then the
+// one Algorithm 3 defines: the roots plus everything reachable from them
+// through vertices with CSD > k.  It still holds every riser (a riser has
+// more than k supporters, so CSD > k, and each connected piece of risers
+// contains a root), and every level-k neighbour counted by an expanding
+// vertex is visited, so peeling it by "cd <= k" leaves exactly the risers.
+__device__ __forceinline__ void expand_round_pruned(const KArgs &a, const Iter &it, int r, const Team &T,
+                                                    Acc &acc) {
+    Ctl *c = a.ctl;
+    const DevGraph &g = a.g;
+    const int sc = r % 3, sn = (r + 1) % 3;
+    const int bc = r & 1, bn = bc ^ 1;
+    const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
+    const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
+    const int32_t ep = it.ep;
+    auto support = [&](int32_t w, int32_t k) -> bool {
+        if (w < 0) return false;
+        const int32_t cw = g.core[w];
+        return cw > k || (cw == k && g.mcd[w] > k);
+    };
+    // claim w for the visited set (level k, SD > k, not yet visited)
+    auto claim = [&](int32_t w, int32_t k) -> bool {
+        if (w < 0 || g.core[w] != k || g.mcd[w] <= k) return false;
+        if (g.stamp[w] == ep || atomicExch(&g.stamp[w], ep) == ep) return false;
+        g.cd[w] = 0;
+        return true;
+    };
+    WaveBuf bq = wave_buf(0), be = wave_buf(1), bcand = wave_buf(2);
+    auto push_next = [&](int32_t w, bool p) {
+        push_vertex_wb(a, bq, a.q.fq[bn], &c->fq_tail[sn], a.q.fh[bn], &c->fh_tail[sn], w, p);
+    };
+    auto push_evict = [&](int32_t v, bool p) {
+        push_vertex_wb(a, be, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, p);
+    };
+    auto push_cand = [&](int32_t v, bool p) {
+        wb_push(bcand, a.q.cand, a.q.vcap, &c->cand_count, v, p, &c->overflow);
+    };
+    for_batches(T, a.q.fq[bc], nq, [&](int32_t v) {
+        const int32_t L = v >= 0 ? g.len[v] : 0;
+        const int32_t k = v >= 0 ? g.core[v] : 0;
+        const bool big = L > a.t.large_deg;
+        if (big) {
+            const int nch = nchunks(L, a.t.chunk);
+            const int base = atomicAdd(&c->fh_tail[sn], nch);
+            for (int q = 0; q < nch; ++q) {
+                if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
+                else atomicOr(&c->overflow, 1);
+            }
+        }
+        const bool live = v >= 0 && !big;
+        int32_t pcd = 0;
+        flat_walk(g, v, live ? L : 0, [&](int32_t j, int32_t w, unsigned long long own) {
+            const bool sup = support(j >= 0 ? w : -1, __shfl(k, j < 0 ? 0 : j));
+            pcd += __popcll(__ballot(sup) & own);
+        });
+        if (live) { g.cd[v] = pcd; acc.scanned += L; }
+        push_cand(v, live);
+        push_evict(v, live && pcd <= k);
+        const bool grow = live && pcd > k;
+        if (__ballot(grow)) {
+            flat_walk(g, v, grow ? L : 0, [&](int32_t j, int32_t w, unsigned long long) {
+                const int32_t kj = __shfl(k, j < 0 ? 0 : j);
+                push_next(w, j >= 0 && claim(w, kj));
+            });
+            if (grow) acc.scanned += L;
+        }
+    });
+    // chunk items: CSD partial sums (the last chunk decides), or the claim
+    // pass of a long list whose CSD exceeded k
+    for (int32_t jx = T.wave(); jx < nh; jx += T.nwaves()) {
+        const int64_t item = a.q.fh[bc][jx];
+        const int32_t v = item_v(item);
+        const int32_t cf = item_c(item);
+        const bool claim_pass = (cf & CLAIM_CHUNK) != 0;
+        const int32_t ci = cf & ~CLAIM_CHUNK;
+        const int32_t L = g.len[v];
+        const int32_t k = g.core[v];
+        const int32_t lo = ci * a.t.chunk, hi = lo + a.t.chunk < L ? lo + a.t.chunk : L;
+        const int32_t nch = nchunks(L, a.t.chunk);
+        if (lane() == 0) acc.scanned += hi - lo;
+        if (claim_pass) {
+            wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { push_next(w, claim(w, k)); });
+            continue;
+        }
+        int32_t part = 0;
+        wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { part += support(w, k) ? 1 : 0; });
+        part = wave_sum(part);
+        int last = 0;
+        if (lane() == 0) {
+            atomicAdd(&g.cd[v], part);
+            wave_drain();  // the partial sum lands before this chunk counts as done
+            last = atomicAdd(&g.done[v], 1) == nch - 1;
+        }
+        last = __shfl(last, 0);
+        if (last) {
+            int32_t tot = 0;
+            if (lane() == 0) {
+                g.done[v] = 0;
+                tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            tot = __shfl(tot, 0);
+            push_cand(v, lane() == 0);
+            push_evict(v, lane() == 0 && tot <= k);
+            if (tot > k && lane() == 0) {
+                const int base = atomicAdd(&c->fh_tail[sn], nch);
+                for (int q = 0; q < nch; ++q) {
+                    if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q | CLAIM_CHUNK);
+                    else atomicOr(&c->overflow, 1);
+                }
+            }
+        }
+    }
+    wb_flush(bq, a.q.fq[bn], a.q.vcap, &c->fq_tail[sn], &c->overflow);
+    wb_flush(be, a.q.eq[0], a.q.vcap, &c->eq_tail[0], &c->overflow);
+    wb_flush(bcand, a.q.cand, a.q.vcap, &c->cand_count, &c->overflow);
+}
+
+__device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int r, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -1187,6 +1344,10 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         wb_push(bcand, a.q.cand, a.q.vcap, &c->cand_count, v, p, &c->overflow);
     };
 
+    if (a.t.prune) {
+        expand_round_pruned(a, it, r, T, acc);
+        return;
+    }
     // Lists of up to `large` slots: flattened walks of the wave's batch;
     // longer root lists are counted chunk by chunk next round.
     for_batches(T, a.q.fq[bc], nq, [&](int32_t v) {
@@ -1209,7 +1370,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             pcd += __popcll(__ballot(sup) & own);
             push_next(w, cl);
         });
-        if (live) { g.cd[v] = pcd; scanned += L; }
+        if (live) { g.cd[v] = pcd; acc.scanned += L; }
         push_cand(v, live);
         push_evict(v, live && pcd <= k);
     });
@@ -1226,7 +1387,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         part = wave_sum(part);
         int last = 0;
         if (lane() == 0) {
-            scanned += hi - lo;
+            acc.scanned += hi - lo;
             atomicAdd(&g.cd[v], part);
             wave_drain();  // the partial sum lands before this chunk counts as done
             last = atomicAdd(&g.done[v], 1) == nch - 1;
@@ -1251,7 +1412,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
 // Negative traversal (Algorithm 4) as rounds: an evicted candidate lowers the
 // counter of each candidate neighbour at its level; a neighbour is evicted
 // exactly once, when its counter crosses from k+1 to k.
-__device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+__device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int r, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -1275,11 +1436,11 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     auto push_next = [&](int32_t w, bool p) {
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
-    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
+    acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
                                 [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
-        if (lane() == 0) scanned += hi - lo;
+        if (lane() == 0) acc.scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
     });
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
@@ -1290,7 +1451,7 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
 // is cd = SD(w) - dec[w] (SD on G minus the set) and w is peeled exactly
 // once, when cd crosses from k to k-1.  dec is cleared after the iteration
 // through the `touched` list.
-__device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T, long long &scanned) {
+__device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
@@ -1315,10 +1476,10 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, fire);
         push_vertex_wb(a, bchg, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
-    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
+    acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
-        if (lane() == 0) scanned += hi - lo;
+        if (lane() == 0) acc.scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
     });
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
@@ -1328,21 +1489,30 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
 
 // Core update (Algorithm 1: +1 for every surviving candidate; Algorithm 5:
 // -1 for every peeled vertex).  SD of a moved vertex is rebuilt next step.
-__device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const Team &T) {
+__device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
+    long long &cdeg = acc.cdeg, &edeg = acc.edeg, &hdeg = acc.hdeg;  // list entries of the method's sets
     if (it.ins) {
         const int32_t n = qlen(&c->cand_count, a.q.vcap);
-        if (T.lead()) c->st_candidates += (unsigned long long)n;
+        if (T.lead()) {
+            c->st_candidates += (unsigned long long)n;
+            c->st_icand += (unsigned long long)n;
+        }
         for (int32_t idx = T.rank; idx < n; idx += T.size) {
             int32_t v = a.q.cand[idx];
             int32_t k = g.core[v];
             bool up = g.cd[v] > k;
+            const int32_t L = g.len[v];
+            cdeg += L;
+            if (up) hdeg += L;
+            else edeg += L;
             if (up) {
                 g.core[v] = k + 1;
                 g.chg[v] = it.ep;
                 g.mcd[v] = 0;
             }
+            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, up, it.ep, v, k + 1);
             count_agg(&c->changed_count, up);
             push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, up);
         }
@@ -1355,20 +1525,29 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
         }
         for (int32_t idx = T.rank; idx < n; idx += T.size) {
             int32_t v = a.q.chg[idx];
-            g.core[v] -= 1;
+            const int32_t nc = g.core[v] - 1;
+            edeg += g.len[v];
+            hdeg += g.len[v];
+            g.core[v] = nc;
             g.chg[v] = it.ep;
             g.mcd[v] = 0;
+            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, true, it.ep, v, nc);
         }
         const int32_t nh = qlen(&c->chh_count, a.q.hcap);
         for (int32_t idx = T.rank; idx < nh; idx += T.size) {
             int64_t item = a.q.chh[idx];
             bool first = item_c(item) == 0;
+            int32_t v = -1, nc = 0;
             if (first) {
-                int32_t v = item_v(item);
-                g.core[v] -= 1;
+                v = item_v(item);
+                nc = g.core[v] - 1;
+                edeg += g.len[v];
+                hdeg += g.len[v];
+                g.core[v] = nc;
                 g.chg[v] = it.ep;
                 g.mcd[v] = 0;
             }
+            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, first, it.ep, v, nc);
             count_agg(&c->changed_count, first);
         }
         for (int32_t idx = T.rank; idx < nt; idx += T.size) g.dec[a.q.touched[idx]] = 0;
@@ -1378,7 +1557,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
 // SD maintenance after the core update: a moved vertex recounts SD from its
 // list; an unmoved neighbour w gains (insert) or loses (delete) one when the
 // moved vertex crossed w's core.
-__device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const Team &T, long long &scanned) {
+__device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
@@ -1406,7 +1585,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         flat_walk(g, v, big ? 0 : L, [&](int32_t j, int32_t w, unsigned long long own) {
             cnt += __popcll(__ballot(nb(w, __shfl(cv, j < 0 ? 0 : j)) != 0) & own);
         });
-        if (v >= 0 && !big) { g.mcd[v] = cnt; scanned += L; }
+        if (v >= 0 && !big) { g.mcd[v] = cnt; acc.scanned += L; }
         unsigned long long m = __ballot(big);
         while (m) {
             const int src = __ffsll((long long)m) - 1;
@@ -1417,7 +1596,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
             int32_t tot = 0;
             wave_walk(g, vv, 0, LL, [&](int32_t w, int32_t) { tot += nb(w, cvv); });
             tot = wave_sum(tot);
-            if (lane() == 0) { g.mcd[vv] = tot; scanned += LL; }
+            if (lane() == 0) { g.mcd[vv] = tot; acc.scanned += LL; }
         }
     });
     const int32_t nh = qlen(&c->chh_count, a.q.hcap);
@@ -1426,7 +1605,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         int32_t cnt = 0;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { cnt += nb(w, cv); });
         cnt = wave_sum(cnt);
-        if (lane() == 0) { atomicAdd(&g.mcd[v], cnt); scanned += hi - lo; }
+        if (lane() == 0) { atomicAdd(&g.mcd[v], cnt); acc.scanned += hi - lo; }
     });
 }
 
@@ -1556,10 +1735,10 @@ __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &
 }
 
 __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const PC &pc, const Team &T,
-                                         long long &scanned) {
+                                         Acc &acc) {
     switch (pc.step) {
     case S_CLAIM:
-        if (it.sc.mode) star_claim(a, it, T, scanned);
+        if (it.sc.mode) star_claim(a, it, T, acc);
         else part_claim(a, it, pc.r, T);
         break;
     case S_SELECT:
@@ -1571,22 +1750,22 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
         else star_apply_delete(a, it, T);
         break;
     case S_EXPAND:
-        if (a.t.async_steps) expand_async(a, it, scanned);
-        else expand_round(a, it, pc.r, T, scanned);
+        if (a.t.async_steps) expand_async(a, it, acc);
+        else expand_round(a, it, pc.r, T, acc);
         break;
     case S_EVICT:
-        if (a.t.async_steps) evict_async(a, it, scanned);
-        else evict_round(a, it, pc.r, T, scanned);
+        if (a.t.async_steps) evict_async(a, it, acc);
+        else evict_round(a, it, pc.r, T, acc);
         break;
     case S_PEEL:
-        if (a.t.async_steps) peel_async(a, it, scanned);
-        else peel_round(a, it, pc.r, T, scanned);
+        if (a.t.async_steps) peel_async(a, it, acc);
+        else peel_round(a, it, pc.r, T, acc);
         break;
     case S_CORE:
-        apply_core(a, it, T);
+        apply_core(a, it, T, acc);
         if (it.sc.mode == 2) star_kill(a, it, T);
         break;
-    case S_MCD: mcd_phase(a, it, T, scanned); break;
+    case S_MCD: mcd_phase(a, it, T, acc); break;
     default: break;
     }
 }
@@ -1596,7 +1775,7 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
 // iterations run.  Workgroup 0 publishes the step where a local run stopped
 // in one of two slots (alternating), so a slow workgroup still reading the
 // previous publication is never overtaken.
-__device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_iters, int32_t &ep, long long &scanned,
+__device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_iters, int32_t &ep, Acc &acc,
                               int &pubs, const StarCtx &sc = StarCtx{}) {
     Ctl *c = a.ctl;
     int it_n = 0;
@@ -1615,7 +1794,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
             if (force || !step_is_local(a, it, pc, work)) {
                 force = false;
                 const unsigned long long t0 = ph_start();
-                run_step(a, it, pc, grid_team(), scanned);
+                run_step(a, it, pc, grid_team(), acc);
                 if (gtid() == 0) c->st_grid_steps += 1;
                 gbar(a.bar);
                 ph_stop(c, pc.step, t0);
@@ -1628,7 +1807,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                     bool fg = false;
                     for (;;) {
                         if (!block_local_ok(a, it, pc, T)) { fg = true; break; }
-                        run_step(a, it, pc, T, scanned);
+                        run_step(a, it, pc, T, acc);
                         if (threadIdx.x == 0) c->st_local_steps += 1;
                         __syncthreads();
                         pc = next_pc(a, it, pc);
@@ -1709,6 +1888,7 @@ __device__ __forceinline__ void prog_clear_stats(const KArgs &a, const Team &T) 
         c->st_iters = 0; c->st_remaining = 0; c->st_selected = 0;
         c->st_candidates = 0; c->st_evicted = 0; c->st_changed = 0; c->st_scanned = 0;
         c->st_rounds = 0; c->st_grid_steps = 0; c->st_local_steps = 0;
+        c->st_icand = 0; c->st_cdeg = 0; c->st_edeg = 0; c->st_hdeg = 0;
         c->vd_total = 0;
         c->vd_tail = 0;
         c->vd_bad = 0x7fffffff;
@@ -1732,6 +1912,10 @@ __device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t 
     o.scanned = c->st_scanned;
     o.rounds = c->st_rounds;
     o.steps = c->st_grid_steps + c->st_local_steps;
+    o.icand = c->st_icand;
+    o.cdeg = c->st_cdeg;
+    o.edeg = c->st_edeg;
+    o.hdeg = c->st_hdeg;
 }
 
 // Validation and (insertion) capacity reservation of the edge batch bc.
@@ -1784,7 +1968,7 @@ __device__ __forceinline__ int prog_prepare(const KArgs &a, const BatchCtx &bc, 
 }
 
 // After the iterations: compaction (deletion) and the scan statistic.
-__device__ __forceinline__ void prog_finish(const KArgs &a, bool inserting, long long &scanned) {
+__device__ __forceinline__ void prog_finish(const KArgs &a, bool inserting, Acc &acc) {
     Ctl *c = a.ctl;
     if (!inserting) {
         const unsigned long long t0 = ph_start();
@@ -1792,8 +1976,7 @@ __device__ __forceinline__ void prog_finish(const KArgs &a, bool inserting, long
         gbar(a.bar);
         ph_stop(c, PH_COMPACT, t0);
     }
-    flush_stat(&c->st_scanned, scanned);
-    scanned = 0;
+    flush_acc(c, acc);
     gbar(a.bar);
 }
 
@@ -1894,7 +2077,7 @@ __device__ __forceinline__ void vdel_finish_ids(const KArgs &a, const ProgDesc *
 // Run batch B (index j of the launch).  Returns 1 when the launch must stop
 // for a pool repack before this batch, else 0 (outcome recorded in out).
 __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd, const ProgBatch &B, ProgOut &out,
-                                             int32_t bstamp, int32_t &ep, long long &scanned, int &pubs) {
+                                             int32_t bstamp, int32_t &ep, Acc &acc, int &pubs) {
     Ctl *c = a.ctl;
     const Team G = grid_team();
     const int32_t n_ids = B.n_ids > 0 ? B.n_ids : a.g.n_ids;
@@ -2030,9 +2213,9 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
             });
         }
         const bool star = kind == P_STARS_IN || kind == P_STARS_OUT;
-        iters += run_iterations(a, vb.inserting, 0x7fffffff, ep, scanned, pubs, star ? sc : StarCtx{});
+        iters += run_iterations(a, vb.inserting, 0x7fffffff, ep, acc, pubs, star ? sc : StarCtx{});
     }
-    if (pass0 != 0 && validate) prog_finish(a, vb.inserting, scanned);
+    if (pass0 != 0 && validate) prog_finish(a, vb.inserting, acc);
     if (B.kind == 3) {
         vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
         gbar(a.bar);
@@ -2056,7 +2239,7 @@ __device__ __forceinline__ void run_program(const KArgs &a) {
     Ctl *c = a.ctl;
     ProgDesc *pd = a.prog;
     int32_t ep = ld_rlx(&c->epoch);
-    long long scanned = 0;
+    Acc acc{};
     int pubs = 0;
     const int32_t nb = pd->nb;
     int32_t j = pd->first;
@@ -2068,7 +2251,7 @@ __device__ __forceinline__ void run_program(const KArgs &a) {
             if (gtid() == 0) atomicOr(&c->overflow, 8);
             break;
         }
-        if (run_one_batch(a, pd, B, pd->out[j], pd->bstamp0 + 2 * (j - pd->first), ep, scanned, pubs)) {
+        if (run_one_batch(a, pd, B, pd->out[j], pd->bstamp0 + 2 * (j - pd->first), ep, acc, pubs)) {
             failed = 1;
             break;
         }
@@ -2092,7 +2275,7 @@ __device__ __forceinline__ void run_server(const KArgs &a) {
     ProgDesc *pd = a.prog;
     ServeHdr *h = pd->hdr;
     int32_t ep = ld_rlx(&c->epoch);
-    long long scanned = 0;
+    Acc acc{};
     int pubs = 0;
     long long j = pd->sfirst;
     int32_t reason = SV_STOP;
@@ -2117,7 +2300,7 @@ __device__ __forceinline__ void run_server(const KArgs &a) {
         const ProgBatch B = c->sv_batch;
         if (hash_slots(B.s) > a.b.hcap || B.s > a.b.cap) { reason = SV_TOOBIG; break; }
         if (run_one_batch(a, pd, B, pd->out[j % pd->ring], pd->bstamp0 + 2 * (int32_t)(j - pd->sfirst), ep,
-                          scanned, pubs)) {
+                          acc, pubs)) {
             reason = SV_POOL;
             break;
         }
@@ -2186,7 +2369,7 @@ __device__ __forceinline__ void dec_sweep(const KArgs &a, const DState &st, cons
     if (lane() == 0 && mymin != 0x7fffffff) atomicMin(&c->min_deg[s1], mymin);
 }
 
-__device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, const Team &T, long long &scanned) {
+__device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, const Team &T, Acc &acc) {
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int sc = st.f % 3, sn = (st.f + 1) % 3, sx = (st.f + 2) % 3;
@@ -2208,10 +2391,10 @@ __device__ __forceinline__ void dec_round(const KArgs &a, const DState &st, cons
     auto push_next = [&](int32_t w, bool p) {
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
-    scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
+    acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
                                 [&](int32_t w, int32_t) { push_next(w, body(w)); });
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
-        if (lane() == 0) scanned += hi - lo;
+        if (lane() == 0) acc.scanned += hi - lo;
         wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, body(w)); });
     });
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
@@ -2266,7 +2449,7 @@ __device__ __forceinline__ DState dec_next(const KArgs &a, const DState &st) {
     return nx;
 }
 
-__device__ __forceinline__ void decompose(const KArgs &a, long long &scanned) {
+__device__ __forceinline__ void decompose(const KArgs &a, Acc &acc) {
     Ctl *c = a.ctl;
     DState st{D_SWEEP, 0, 0, 0};
     int pubs = 0;
@@ -2278,7 +2461,7 @@ __device__ __forceinline__ void decompose(const KArgs &a, long long &scanned) {
         if (force || work > a.t.local_items) {
             force = false;
             if (st.step == D_SWEEP) dec_sweep(a, st, grid_team());
-            else { dec_round(a, st, grid_team(), scanned); kmax = st.k; }
+            else { dec_round(a, st, grid_team(), acc); kmax = st.k; }
             if (gtid() == 0) c->st_grid_steps += 1;
             gbar(a.bar);
             st = dec_next(a, st);
@@ -2290,7 +2473,7 @@ __device__ __forceinline__ void decompose(const KArgs &a, long long &scanned) {
                 for (;;) {
                     if (!dec_block_local_ok(a, st, T)) { fg = true; break; }
                     if (st.step == D_SWEEP) dec_sweep(a, st, T);
-                    else { dec_round(a, st, T, scanned); kmax = st.k; }
+                    else { dec_round(a, st, T, acc); kmax = st.k; }
                     if (threadIdx.x == 0) c->st_local_steps += 1;
                     __syncthreads();
                     st = dec_next(a, st);
