@@ -90,13 +90,15 @@ def contract(workload, value, steps, warmup, ms_per_step, global_batch, form):
     }
 
 
-def roofline(kernel, stats, note, traffic_key=None):
+def roofline(kernel, stats, note, traffic_key=None, method_bytes=None):
     """Algorithmic bytes of the launches over their HIP-event time; the
     measured HBM traffic per launch is attached when it was taken on the
-    current kernel sources."""
+    current kernel sources.  method_bytes (per launch), when given, replaces
+    the bytes the timed launches counted: the method's own bytes counted on
+    a pass that visits exactly Algorithm 3's sets."""
     kms = sum(x["kernel_ms"] for x in stats)
     launches = sum(x["launches"] for x in stats)
-    abytes = sum(x["alg_bytes"] for x in stats)
+    abytes = sum(x["alg_bytes"] for x in stats) if method_bytes is None else method_bytes * launches
     achieved = (abytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
     out = {
         "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -351,11 +353,11 @@ def bench_rmat22(args, cm, torch):
         return n, ds, dd, kinds[:ns], offs[:ns + 1], dx[:offs[ns]], dy[:offs[ns]]
     params, tuning = tuned_params(args, n, s.size, np.diff(offs), sample)
 
-    def run(mode, use_graph, reps, per_batch=False):
+    def run(mode, use_graph, reps, per_batch=False, extra=None):
         """reps passes over the stream from the freshly loaded graph: one
         cm_run_batches call for the whole stream, or (per_batch) one call per
         batch with its latency."""
-        g = cm.Graph(mode=mode, timing=True, use_graph=use_graph, **params)
+        g = cm.Graph(mode=mode, timing=True, use_graph=use_graph, **{**params, **(extra or {})})
         times, allstats, lat = [], [], []
         try:
             for rep in range(reps):
@@ -392,6 +394,11 @@ def bench_rmat22(args, cm, torch):
     pt, pstats = pt[-1:], pstats[-1:]
     qt, qstats, qcores, _, qlat = run(cm.MODE_PERSISTENT, False, 1, per_batch=True)
     assert np.array_equal(bcores, qcores), "persistent and batched forms disagree"
+    # the method's own bytes: one untimed pass whose expansion visits exactly
+    # Algorithm 3's sets (pruned); partitions and cores are the same in every form
+    mt, mstats, mcores, _, _ = run(cm.MODE_PERSISTENT, True, 1, extra={"expand_mode": 1})
+    assert np.array_equal(bcores, mcores), "pruned and one-pass expansions disagree"
+    method_bytes = sum(x["alg_bytes"] for x in mstats[0])
     value = total * len(bt) / sum(bt)
     plain_value = total / pt[0]
     out = contract(f"r-mat scale 22 edge factor 16 (n={n} m={s.size}); stream of 64 batches, sizes "
@@ -400,7 +407,14 @@ def bench_rmat22(args, cm, torch):
                    value, args.steps, args.warmup, sum(bt) * 1e3 / len(bt), total,
                    "batched (the whole stream in one persistent launch, hipGraph replay)")
     flat = [x for run_ in bstats for x in run_]
-    out["roofline"] = roofline("k_program", flat, "the whole 64-batch stream", traffic_key="rmat22-stream")
+    out["roofline"] = roofline("k_program", flat, "the whole 64-batch stream", traffic_key="rmat22-stream",
+                               method_bytes=method_bytes)
+    out["roofline"]["alg_bytes_source"] = ("the method's sets (Algorithm 3's pruned expansion), counted on "
+                                           f"an untimed pass of the same stream ({mt[0]:.2f}s)")
+    out["roofline"]["timed_form_counted_bytes_per_launch"] = sum(x["alg_bytes"] for x in flat) / max(len(bt), 1)
+    out["roofline"]["scanned_over_method_entries"] = (
+        sum(x["scanned"] for x in flat) / max(len(bt), 1) /
+        max(sum(x["cand_degree"] + x["evicted_degree"] + x["changed_degree"] for x in mstats[0]), 1))
     plat = [x["ms_total"] for x in pstats[0]]
     out["speedup_batched_vs_plain"] = value / plain_value
     out["latency_ms"] = {"p50": pct(plat, 50), "p99": pct(plat, 99),
@@ -409,7 +423,8 @@ def bench_rmat22(args, cm, torch):
         "form": "plain (host loop, one cooperative launch per superior edge set)",
         "value": plain_value, "ms_per_step": pt[0] * 1e3,
         "latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "per": "batch"},
-        "roofline": roofline("k_maintain", pstats[0], "one superior edge set"),
+        "roofline": roofline("k_maintain", pstats[0], "one superior edge set",
+                             method_bytes=method_bytes / max(sum(x["launches"] for x in pstats[0]), 1)),
     }
     out["persistent"] = {
         "form": "persistent (one cooperative launch per batch, one call per batch)",

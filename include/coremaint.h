@@ -101,8 +101,9 @@ typedef struct cm_config {
                                    or for `debug` entries when debug > 1 */
     int32_t expand_mode;        /* insertion's subcore expansion (Algorithm 3): 1 = a candidate
                                    visits its neighbours only once its CSD exceeds its core (the
-                                   algorithm's pruning); 2 = it claims them while counting its
-                                   CSD (one pass per list, a larger visited set); 0 = default (1) */
+                                   algorithm's pruning: two passes over an expanding list); 2 = it
+                                   claims them while counting its CSD (one pass per list, a
+                                   larger visited set, same cores); 0 = default (2) */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 

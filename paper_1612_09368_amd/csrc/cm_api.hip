@@ -965,7 +965,7 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
             g->err = "expand_mode must be 0, 1 or 2";
             throw Fail{CM_E_ARG};
         }
-        g->tune.prune = g->cfg.expand_mode == 2 ? 0 : 1;
+        g->tune.prune = g->cfg.expand_mode == 1 ? 1 : 0;
         if (g->tune.single_edge) g->tune.rounds = 1;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
