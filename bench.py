@@ -48,7 +48,10 @@ HBM_PEAK_GBS = 8000.0
 # passes (FETCH_SIZE, then WRITE_SIZE) scaled by calibration kernels of known footprint; each entry
 # names the kernel sources it was measured on and is reported only while their hash matches (the
 # summaries and commands are under profiles/).
-TRAFFIC = {}
+TRAFFIC = {
+    "rmat22-stream": {"kernel": "k_program", "bytes_per_launch": 3254.3e9,
+                      "sources_sha256": "2dd2ec771b5ed97081128539681bfac75df49e288cf7f438e06de4e351f77894"},
+}
 KERNEL_SOURCES = ["cm_internal.h", "cm_kernels.hip", "cm_phases.h", "cm_walk.h"]
 
 
