@@ -177,6 +177,26 @@ int cm_insert_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *d
 int cm_delete_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst,
                     int on_device, cm_batch_stats *stats);
 
+/* Largest batch of cm_update_edges_noalloc. */
+#define CM_NOALLOC_MAX_ITEMS (1 << 16)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as cm_insert_edges (kind CM_BATCH_INSERT) or cm_delete_edges (kind
+ * CM_BATCH_DELETE), with src / dst in device memory, that allocates nothing:
+ * the per-call batch arrays, batch hash and locate-scan queue live in one
+ * file-scope device array of the library (about 13 MiB, held by every GPU
+ * the library runs on until the process ends).  Limits: s <=
+ * CM_NOALLOC_MAX_ITEMS, and 2 s + (adjacency pool slots) / chunk + 1024 <=
+ * 2^20 (about 2.3 x 10^8 pool slots with the default chunk of 256), else
+ * CM_E_CAPACITY before any work; an insertion that would need
+ * a larger adjacency pool returns CM_E_CAPACITY with the graph unchanged
+ * (cm_insert_edges grows the pool instead).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (from any handle, on any
+ * stream) race and must not be issued. */
+int cm_update_edges_noalloc(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
+                            cm_batch_stats *stats);
+
 /* Vertex insertion (Introduction: a new vertex enters with core 0, then its
  * edges are inserted).  c new vertices get ids first..first+c-1 where
  * first = n_ids on entry (*first_new_id receives it, may be NULL).  Vertex i

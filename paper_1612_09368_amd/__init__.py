@@ -32,7 +32,7 @@ EXPORTED = [
     "cm_num_edges", "cm_export_edges", "cm_get_superior_degrees", "cm_run_batches", "cm_phase_times",
     "cm_serve_config_default", "cm_serve_start", "cm_serve_submit_edges", "cm_serve_submit_insert_vertices",
     "cm_serve_submit_delete_vertices", "cm_serve_poll", "cm_serve_result", "cm_serve_stop",
-    "cm_snapshot", "cm_restore", "cm_debug_log",
+    "cm_snapshot", "cm_restore", "cm_debug_log", "cm_update_edges_noalloc",
 ]
 REQ_INSERT_EDGES, REQ_DELETE_EDGES, REQ_INSERT_VERTICES, REQ_DELETE_VERTICES = 0, 1, 2, 3
 
@@ -147,6 +147,7 @@ def library():
         "cm_serve_poll": (ctypes.c_int, [P, P]),
         "cm_serve_result": (ctypes.c_int, [P, I64, P]),
         "cm_serve_stop": (ctypes.c_int, [P]),
+        "cm_update_edges_noalloc": (ctypes.c_int, [P, I32, I64, P, P, P]),
         "cm_snapshot": (ctypes.c_int, [P, ctypes.c_char_p]),
         "cm_restore": (ctypes.c_int, [P, ctypes.c_char_p, P]),
         "cm_debug_log": (ctypes.c_int, [P, P, P, I64, P, P, I64]),
@@ -311,6 +312,17 @@ class Graph:
 
     def delete_edges(self, src, dst, check=True):
         return self._edges(self._lib.cm_delete_edges, src, dst, check, "cm_delete_edges")
+
+    def update_edges_noalloc(self, kind, src, dst, check=True):
+        """cm_update_edges_noalloc: insert (kind BATCH_INSERT) or delete
+        (BATCH_DELETE) device-resident edges without allocating."""
+        ps, ds, ks, m = _ptr(src, np.int32)
+        pd, dd, kd, m2 = _ptr(dst, np.int32)
+        if m != m2 or not ds or not dd:
+            raise ValueError("src and dst must be device arrays of the same length")
+        st, stats = self._call_stats(self._lib.cm_update_edges_noalloc, int(kind), m, ps, pd, check=check,
+                                     what="cm_update_edges_noalloc")
+        return stats if check else (st, stats)
 
     def insert_vertices(self, off, nbrs, check=True):
         po, do, ko, c1 = _ptr(off, np.int64)

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <chrono>
 #include <initializer_list>
+#include <mutex>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -97,12 +98,57 @@ struct cm_graph {
     bool loaded = false;
     bool decomposed = false;
     bool poisoned = false;
+    bool no_alloc = false;    // inside cm_update_edges_noalloc: the pool may not grow
+    void *na_scratch = nullptr;  // this device's address of the allocation-free scratch array
     int64_t m = 0;
     int32_t n_alive = 0;
     int32_t epoch = 0;
     int32_t bstamp = 0;
     std::string err;
 };
+
+// ---------------------------------------------------------------------------
+// Allocation-free edge updates (cm_update_edges_noalloc): the batch arrays,
+// the batch hash and the locate-scan queue of one call live in this
+// file-scope device array instead of buffers the handle allocates.  Every
+// GPU holds its own copy at its own address, looked up once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t NA_ITEMS = CM_NOALLOC_MAX_ITEMS;  // largest batch
+constexpr int64_t NA_HASH = 2 * NA_ITEMS;           // hash slots for it (power of two)
+constexpr int64_t NA_SCAN = (int64_t)1 << 20;       // locate-scan chunk items
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+// layout: int32 err, eu, ev, hslot, rem0, rem1, sel, esel [NA_ITEMS]; int64 su, sv [NA_ITEMS];
+// u64 hkey [NA_HASH]; int32 hval [NA_HASH]; int64 scanq [NA_SCAN]
+constexpr size_t NA_I32 = na_align(sizeof(int32_t) * NA_ITEMS);
+constexpr size_t NA_I64 = na_align(sizeof(int64_t) * NA_ITEMS);
+constexpr size_t NA_BYTES = 8 * NA_I32 + 2 * NA_I64 + na_align(sizeof(unsigned long long) * NA_HASH) +
+                            na_align(sizeof(int32_t) * NA_HASH) + na_align(sizeof(int64_t) * NA_SCAN);
+constexpr int NA_DEVICES = 64;
+std::mutex na_mu;
+void *na_addr[NA_DEVICES] = {};
+}  // namespace
+
+__device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+// Address of this device's scratch array (the device must be current);
+// resolved once per device.
+hipError_t na_lookup(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= NA_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (!na_addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        na_addr[device] = p;
+    }
+    *out = na_addr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -516,6 +562,10 @@ void reserve(cm_graph *g, int cur) {
         sync_ctl(g);
         check_overflow(g);
         if (!g->hctl->pool_fail) return;
+        if (g->no_alloc) {
+            g->err = "adjacency pool full (the allocation-free call cannot grow it; nothing was applied)";
+            throw Fail{CM_E_CAPACITY};
+        }
         // pool exhausted: repack with room for this batch, then redo
         int64_t extra = 4 * (int64_t)g->hctl->rem_count[cur] + (int64_t)g->g.pool_size / 2;
         repack(g, extra);
@@ -944,6 +994,7 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
             return CM_E_ARG;
         }
         HIPCHK(hipGetDevice(&g->device));
+        HIPCHK(na_lookup(g->device, &g->na_scratch));
         g->stream = (hipStream_t)g->cfg.stream;
         HIPCHK(hipDeviceGetAttribute(&g->num_cu, hipDeviceAttributeMultiprocessorCount, g->device));
         int coop_ok = 0;
@@ -1209,6 +1260,87 @@ int cm_insert_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *d
 int cm_delete_edges(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device,
                     cm_batch_stats *stats) {
     return edge_call(g, s, src, dst, on_device, stats, false);
+}
+
+int cm_update_edges_noalloc(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
+                            cm_batch_stats *stats) {
+    if (!g) return CM_E_ARG;
+    double t0 = now_ms();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->first_bad = -1;
+    }
+    if ((kind != CM_BATCH_INSERT && kind != CM_BATCH_DELETE) || s < 0 || (s > 0 && (!src || !dst)))
+        return finish(g, CM_E_ARG, stats, t0);
+    if (s > CM_NOALLOC_MAX_ITEMS) {
+        g->err = "batch larger than CM_NOALLOC_MAX_ITEMS";
+        return finish(g, CM_E_CAPACITY, stats, t0);
+    }
+    try {
+        require_ready(g, true);
+        debug_reset(g);
+        if (s == 0) return finish(g, CM_OK, stats, t0);
+        if (!g->na_scratch) {
+            g->err = "allocation-free scratch not resolved on this device";
+            throw Fail{CM_E_DEVICE};
+        }
+        // every list the locate scan may queue: one chunk item per chunk of a
+        // distinct endpoint's list
+        const int64_t scan_need = 2 * s + g->g.pool_size / std::max(1, g->tune.chunk) + 1024;
+        if (scan_need > NA_SCAN) {
+            g->err = "graph too large for the allocation-free locate-scan queue";
+            throw Fail{CM_E_CAPACITY};
+        }
+        hipStream_t st = g->stream;
+        unsigned char *base = (unsigned char *)g->na_scratch;
+        size_t at = 0;
+        auto carve = [&](size_t bytes) {
+            unsigned char *p = base + at;
+            at += bytes;
+            return (void *)p;
+        };
+        DevBatch nb = g->b;  // vertex-sized arrays (vlist, reloc) stay the handle's own
+        nb.cap = (int32_t)NA_ITEMS;
+        nb.err = (int32_t *)carve(NA_I32);
+        nb.eu = (int32_t *)carve(NA_I32);
+        nb.ev = (int32_t *)carve(NA_I32);
+        nb.hslot = (int32_t *)carve(NA_I32);
+        nb.rem[0] = (int32_t *)carve(NA_I32);
+        nb.rem[1] = (int32_t *)carve(NA_I32);
+        nb.sel = (int32_t *)carve(NA_I32);
+        nb.esel = (int32_t *)carve(NA_I32);
+        nb.su = (int64_t *)carve(NA_I64);
+        nb.sv = (int64_t *)carve(NA_I64);
+        nb.hkey = (unsigned long long *)carve(na_align(sizeof(unsigned long long) * NA_HASH));
+        nb.hval = (int32_t *)carve(na_align(sizeof(int32_t) * NA_HASH));
+        nb.scanq = (int64_t *)carve(na_align(sizeof(int64_t) * NA_SCAN));
+        nb.scap = (int32_t)NA_SCAN;
+        nb.hcap = (int32_t)next_pow2(std::max<int64_t>(2 * s, 1024));
+        nb.src_in = const_cast<int32_t *>(src);
+        nb.dst_in = const_cast<int32_t *>(dst);
+        nb.sub_in = nullptr;
+        // the array keeps the last call's contents (any handle's): clear the
+        // hash and the selection stamps this call reads
+        HIPCHK(fill_u64(nb.hkey, ~0ull, nb.hcap, st));
+        HIPCHK(fill_i32(nb.hval, INT_MAX, nb.hcap, st));
+        HIPCHK(fill_i32(nb.esel, 0, s, st));
+        const DevBatch saved = g->b;
+        g->b = nb;
+        g->no_alloc = true;
+        try {
+            int64_t dropped = 0;
+            edge_batch(g, s, kind == CM_BATCH_INSERT, stats, &dropped, false, false);
+        } catch (...) {
+            g->b = saved;
+            g->no_alloc = false;
+            throw;
+        }
+        g->b = saved;
+        g->no_alloc = false;
+    } catch (const Fail &f) {
+        return finish(g, f.code, stats, t0);
+    }
+    return finish(g, CM_OK, stats, t0);
 }
 
 int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs, int on_device,
