@@ -133,6 +133,9 @@ typedef struct cm_batch_stats {
                                set plus the empty one that ends the batch, queued before the
                                host knew no edges were left) */
     int32_t graph_launch;   /* 1 when the launch was replayed from a hipGraph */
+    int32_t group;          /* serving: requests that ran in one fused batch with this one
+                               (1 = alone; the statistics above are the batch's) */
+    int32_t first_stamp;    /* iteration stamp of the batch's first iteration (debug log) */
     double kernel_ms;       /* summed HIP-event time of those launches (timing = 1; the
                                plain mode times every launch) */
     double ms_total;        /* wall time of the call */
@@ -293,7 +296,8 @@ typedef struct cm_serve_config {
                                  the most incident edges one vertex deletion may gather (default 2^22) */
     int64_t budget_bytes;     /* device bytes unfinished requests may claim (default 2^30) */
     int32_t vertex_headroom;  /* vertex capacity kept beyond the ids in use (default 2^20) */
-    int32_t reserved;
+    int32_t fuse;             /* continuous batching across sessions: most requests fused into one
+                                 batch (<= 32; 0 or 1 = every request runs alone; strict mode only) */
 } cm_serve_config;
 
 #define CM_REQ_INSERT_EDGES 0
@@ -309,9 +313,21 @@ int cm_serve_start(cm_graph *g, const cm_serve_config *cfg);
 /* Submit an edge request (kind CM_REQ_INSERT_EDGES / CM_REQ_DELETE_EDGES; s
  * pairs in host arrays, copied before return).  *ticket receives its
  * position in the request order.  CM_E_BUSY: not admitted now, submit it
- * again later; CM_E_CAPACITY: larger than max_items. */
-int cm_serve_submit_edges(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
-                          int64_t *ticket);
+ * again later; CM_E_CAPACITY: larger than max_items.
+ *
+ * session >= 0 names an independent session: the caller guarantees that
+ * requests of different sessions touch disjoint vertex sets with no edge
+ * between them (e.g. independent graphs packed into one handle).  With
+ * cfg.fuse > 1, consecutive published edge requests of one kind from
+ * distinct sessions run fused in one batch (continuous batching): they are
+ * validated together, each keeping its own strictness (an invalid request
+ * changes nothing and gets its own status), share their iterations, and
+ * each gets the result it would get alone, since the sessions cannot
+ * influence each other's core numbers (a disjoint union's cores are its
+ * members' cores).  Requests of one session never share a batch, and a
+ * session < 0 never fuses. */
+int cm_serve_submit_edges(cm_graph *g, int32_t session, int32_t kind, int64_t s, const int32_t *src,
+                          const int32_t *dst, int64_t *ticket);
 
 /* Submit a vertex insertion: c new vertices with neighbour lists in CSR
  * form (off int64[c+1] with off[0] = 0, nbrs int32[off[c]], host memory).
@@ -356,11 +372,14 @@ int cm_restore(const cm_config *cfg, const char *path, cm_graph **out);
  * cfg.debug > 0 (Algorithms 1 and 5 step by step): sel receives sel_cap
  * entries of 3 int32 (iteration stamp, u, v), one per edge of a selected
  * superior edge set, u < v; chg receives chg_cap entries (iteration stamp,
- * v, new core), one per core number moved by an edge iteration.  Stamps
- * grow by one per iteration, so the entries of one stamp are one superior
- * edge set and the core changes it caused.  *n_sel / *n_chg receive the
- * counts recorded.  Vertex-star iterations (vertex operations in the
- * persistent form and in batch programs) are not logged.  CM_E_STATE
+ * v, new core), one per core number moved by an iteration.  Stamps grow by
+ * one per iteration, so the entries of one stamp are one superior edge set
+ * and the core changes it caused.  *n_sel / *n_chg receive the counts
+ * recorded.  The sets of vertex-star iterations (vertex operations in the
+ * persistent form, batch programs and serving) are not logged, their core
+ * changes of existing vertices are (a new vertex's starting core and a
+ * deleted vertex's -1 are not).  In serving, the log covers everything
+ * since cm_serve_start.  CM_E_STATE
  * without debug mode; CM_E_CAPACITY when the log overflowed (entries past
  * its capacity are lost; the counts still report the totals). */
 int cm_debug_log(cm_graph *g, int64_t *n_sel, int32_t *sel, int64_t sel_cap, int64_t *n_chg, int32_t *chg,

@@ -69,7 +69,7 @@ class ServeConfig(ctypes.Structure):
         ("max_items", ctypes.c_int64),
         ("budget_bytes", ctypes.c_int64),
         ("vertex_headroom", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fuse", ctypes.c_int32),
     ]
 
 
@@ -94,6 +94,8 @@ class BatchStats(ctypes.Structure):
         ("local_steps", ctypes.c_int64),
         ("launches", ctypes.c_int32),
         ("graph_launch", ctypes.c_int32),
+        ("group", ctypes.c_int32),
+        ("first_stamp", ctypes.c_int32),
         ("kernel_ms", ctypes.c_double),
         ("ms_total", ctypes.c_double),
     ]
@@ -141,7 +143,7 @@ def library():
         "cm_phase_times": (ctypes.c_int, [P, P, P, I32, ctypes.c_int]),
         "cm_serve_config_default": (None, [P]),
         "cm_serve_start": (ctypes.c_int, [P, P]),
-        "cm_serve_submit_edges": (ctypes.c_int, [P, I32, I64, P, P, P]),
+        "cm_serve_submit_edges": (ctypes.c_int, [P, I32, I32, I64, P, P, P]),
         "cm_serve_submit_insert_vertices": (ctypes.c_int, [P, I32, P, P, P, P]),
         "cm_serve_submit_delete_vertices": (ctypes.c_int, [P, I32, P, P]),
         "cm_serve_poll": (ctypes.c_int, [P, P]),

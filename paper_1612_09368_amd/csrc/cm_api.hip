@@ -81,6 +81,7 @@ struct cm_graph {
     ServeHdr *shdr = nullptr;       // pinned
     ProgBatch *sring = nullptr;     // pinned [ring_requests]
     ProgOut *sout = nullptr;        // pinned [ring_requests]
+    int32_t *d_bsub = nullptr;      // request index of each item of a fused batch [batch_cap]
     int32_t *ssrc = nullptr, *sdst = nullptr;  // pinned payload [ring_items]
     int64_t s_next = 0;             // tickets issued (= batches published)
     int64_t s_done = 0;             // batches finished (host view)
@@ -693,6 +694,10 @@ int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats
         if (stats) fill_stats(g, stats, 0, *dropped, fb);
         return 0;
     }
+    if (stats) {
+        stats->group = 1;
+        stats->first_stamp = g->epoch + 1;
+    }
     KArgs a = make_args(g);
     a.inserting = inserting ? 1 : 0;
     a.cur = cur;
@@ -869,6 +874,8 @@ void stats_from_out(cm_graph *g, const ProgOut &o, int64_t items, int launches, 
     r->scanned = (int64_t)o.scanned;
     r->rounds = (int64_t)o.rounds;
     r->local_steps = (int64_t)o.steps;
+    r->group = 1;
+    r->first_stamp = o.ep0;
     r->alg_bytes = alg_bytes(o);
     r->cand_degree = (int64_t)o.cdeg;
     r->evicted_degree = (int64_t)o.edeg;
@@ -1629,6 +1636,7 @@ void serve_free(cm_graph *g) {
     g->sring = nullptr;
     g->sout = nullptr;
     g->ssrc = g->sdst = nullptr;
+    dev_free(g->d_bsub);
 }
 
 template <class T>
@@ -1659,6 +1667,8 @@ void serve_collect(cm_graph *g) {
         r.scanned = (int64_t)o.scanned;
         r.rounds = (int64_t)o.rounds;
         r.local_steps = (int64_t)o.steps;
+        r.group = o.group;
+        r.first_stamp = o.ep0;
         r.alg_bytes = alg_bytes(o);
         r.cand_degree = (int64_t)o.cdeg;
         r.evicted_degree = (int64_t)o.edeg;
@@ -1689,6 +1699,9 @@ void serve_launch(cm_graph *g) {
     hd->gcap = g->batch_cap;
     hd->firstidx = g->firstidx;
     hd->hdr = host_dev_ptr(g, g->shdr);
+    hd->bsub = g->d_bsub;
+    hd->sub_bad = g->d_sub_bad;
+    hd->fuse = std::max(1, g->scfg.fuse);
     int khz = 0;
     HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
     hd->idle_ticks = (unsigned long long)std::max(1, g->scfg.idle_ms) * (unsigned long long)std::max(khz, 1);
@@ -1807,7 +1820,8 @@ int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
         if (cfg) c = *cfg;
         else cm_serve_config_default(&c);
         if (c.ring_requests < 1 || c.ring_items < 1 || c.max_items < 1 || c.max_items > c.ring_items ||
-            c.max_items > INT_MAX / 4 || c.idle_ms < 1 || c.budget_bytes < 1 || c.vertex_headroom < 0) {
+            c.max_items > INT_MAX / 4 || c.idle_ms < 1 || c.budget_bytes < 1 || c.vertex_headroom < 0 ||
+            c.fuse < 0 || c.fuse > FUSE_MAX) {
             g->err = "bad serving configuration";
             throw Fail{CM_E_ARG};
         }
@@ -1820,6 +1834,13 @@ int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
         int want = g->cfg.blocks_per_cu > 0 ? g->cfg.blocks_per_cu : 1;
         g->coop_serve = g->num_cu * std::max(1, std::min(want, bpc));
         serve_free(g);
+        dev_alloc(g, &g->d_bsub, g->batch_cap);
+        {
+            int64_t cap = g->sub_cap;
+            grow_dev(g, g->d_sub_bad, cap, FUSE_MAX);
+            g->sub_cap = (int32_t)cap;
+        }
+        debug_reset(g);
         HIPCHK(hipHostMalloc((void **)&g->shdr, sizeof(ServeHdr), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&g->sring, sizeof(ProgBatch) * (size_t)c.ring_requests, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&g->sout, sizeof(ProgOut) * (size_t)c.ring_requests, hipHostMallocDefault));
@@ -1848,8 +1869,8 @@ int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
     return CM_OK;
 }
 
-int cm_serve_submit_edges(cm_graph *g, int32_t kind, int64_t s, const int32_t *src, const int32_t *dst,
-                          int64_t *ticket) {
+int cm_serve_submit_edges(cm_graph *g, int32_t session, int32_t kind, int64_t s, const int32_t *src,
+                          const int32_t *dst, int64_t *ticket) {
     if (!g || (kind != CM_REQ_INSERT_EDGES && kind != CM_REQ_DELETE_EDGES) || s < 0 ||
         (s > 0 && (!src || !dst)))
         return CM_E_ARG;
@@ -1872,6 +1893,7 @@ int cm_serve_submit_edges(cm_graph *g, int32_t kind, int64_t s, const int32_t *s
         b.s = (int32_t)s;
         b.kind = kind;
         b.n_ids = g->s_n_ids;
+        b.session = session < 0 ? -1 : session;
         serve_publish(g, b, start, bytes, g->s_n_ids, ticket);
         serve_pump(g);
     } catch (const Fail &f) {
@@ -1923,6 +1945,7 @@ int cm_serve_submit_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, 
         b.off = pos;
         b.s = (int32_t)total;
         b.kind = CM_REQ_INSERT_VERTICES;
+        b.session = -1;
         b.v0 = v0;
         b.nv = c;
         b.n_ids = v0 + c;
@@ -1953,6 +1976,7 @@ int cm_serve_submit_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, 
         b.off = pos;
         b.s = c;
         b.kind = CM_REQ_DELETE_VERTICES;
+        b.session = -1;
         b.n_ids = g->s_n_ids;
         serve_publish(g, b, start, bytes, g->s_n_ids, ticket);
         serve_pump(g);
@@ -2404,6 +2428,8 @@ int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t 
                 r.changed_degree = (int64_t)o.hdeg;
                 r.launches = j == 0 ? launches : 0;
                 r.graph_launch = used_graph;
+                r.group = 1;
+                r.first_stamp = o.ep0;
                 r.kernel_ms = j == 0 ? kms : 0.0;
             }
         }

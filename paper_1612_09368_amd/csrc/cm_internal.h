@@ -27,8 +27,14 @@ struct ProgBatch {
     int32_t v0;          // kind 2: first new id
     int32_t nv;          // kind 2: new ids [v0, v0 + nv); items are their edges (new id, neighbour)
     int32_t n_ids;       // ids in use for this batch (0: the launch's); kind 3: items are ids
+    int32_t session;     // serving: independent session of the request (-1: none)
+    int32_t nsub;        // serving: requests fused into this batch (0: one request); item i then
+                         // belongs to request bsub[i] of the group
     int32_t pad;
 };
+
+// Most requests one served batch may fuse.
+constexpr int FUSE_MAX = 32;
 
 // ---------------------------------------------------------------------------
 // Control block: counters shared by all workgroups of a launch.  Rotating
@@ -95,6 +101,8 @@ struct Ctl {
     unsigned long long one_key;   // single-edge regime: largest complemented claim key of the iteration
     int32_t sv_decision;          // serving: decision of the waiting thread
     ProgBatch sv_batch;           // serving: descriptor of the current batch
+    int32_t sv_gn;                // serving: requests fused into the current batch
+    int32_t sv_goff[FUSE_MAX + 1];  // serving: item offsets of the fused requests in the batch
 };
 
 // Phase-clock slots after the step kinds (0 .. 7).
@@ -275,6 +283,8 @@ struct ProgOut {
     int32_t valid;       // edges applied
     int32_t iterations;
     int32_t vdone;       // vertex batches: vertices inserted / deleted
+    int32_t group;       // requests in the batch that ran this one (1 unless fused)
+    int32_t ep0;         // first iteration stamp of that batch
     int32_t pad;
     unsigned long long remaining, selected, candidates, evicted, changed, scanned, rounds, steps;
     unsigned long long icand, cdeg, edeg, hdeg;
@@ -307,6 +317,9 @@ struct ProgDesc {
     int64_t gcap;
     int32_t *firstidx;   // [n_cap] vertex-deletion duplicate marks (INT_MAX between uses)
     ServeHdr *hdr;       // serving: request ring header (null for a fixed program)
+    int32_t *bsub;       // serving: request of each item of a fused batch (capacity: batch items)
+    int32_t fuse;        // serving: most requests fused into one batch (1: none)
+    int32_t pad_f;
     long long sfirst;    // serving: first batch of this launch
     unsigned long long idle_ticks;  // serving: wall-clock ticks without work before leaving
     int32_t ring;        // serving: ring slots

@@ -1512,7 +1512,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
                 g.chg[v] = it.ep;
                 g.mcd[v] = 0;
             }
-            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, up, it.ep, v, k + 1);
+            if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, up, it.ep, v, k + 1);
             count_agg(&c->changed_count, up);
             push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, up);
         }
@@ -1531,7 +1531,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
             g.core[v] = nc;
             g.chg[v] = it.ep;
             g.mcd[v] = 0;
-            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, true, it.ep, v, nc);
+            if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, true, it.ep, v, nc);
         }
         const int32_t nh = qlen(&c->chh_count, a.q.hcap);
         for (int32_t idx = T.rank; idx < nh; idx += T.size) {
@@ -1547,7 +1547,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
                 g.chg[v] = it.ep;
                 g.mcd[v] = 0;
             }
-            if (a.dl.chg && it.sc.mode == 0) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, first, it.ep, v, nc);
+            if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, first, it.ep, v, nc);
             count_agg(&c->changed_count, first);
         }
         for (int32_t idx = T.rank; idx < nt; idx += T.size) g.dec[a.q.touched[idx]] = 0;
@@ -1897,8 +1897,10 @@ __device__ __forceinline__ void prog_clear_stats(const KArgs &a, const Team &T) 
 }
 
 __device__ __forceinline__ void prog_record(const KArgs &a, ProgOut &o, int32_t status, int32_t fb, int32_t valid,
-                                           int32_t iters, int32_t vdone) {
+                                           int32_t iters, int32_t vdone, int32_t ep0) {
     Ctl *c = a.ctl;
+    o.group = 1;
+    o.ep0 = ep0;
     o.status = status;
     o.first_bad = fb;
     o.valid = valid;
@@ -2081,10 +2083,13 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
     Ctl *c = a.ctl;
     const Team G = grid_team();
     const int32_t n_ids = B.n_ids > 0 ? B.n_ids : a.g.n_ids;
+    const int32_t ep_first = ep + 1;  // stamp of the batch's first iteration
     BatchCtx bc;
     bc.src = pd->src + B.off;
     bc.dst = pd->dst + B.off;
-    bc.sub = (pd->sub && B.kind <= 1) ? pd->sub + B.off : nullptr;
+    // fused served requests carry batch-local request ids; a packed program
+    // carries program-wide sub-batch ids
+    bc.sub = B.nsub > 0 ? pd->bsub : (pd->sub && B.kind <= 1) ? pd->sub + B.off : nullptr;
     bc.sub_bad = pd->sub_bad;
     bc.s = B.s;
     bc.inserting = B.kind == 0 || B.kind == 2;
@@ -2108,7 +2113,7 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
     if (B.kind == 3) {
         // vertex deletion
         if (B.s > a.b.cap) {
-            if (gtid() == 0) prog_record(a, out, -9, -1, 0, 0, 0);
+            if (gtid() == 0) prog_record(a, out, -9, -1, 0, 0, 0, ep_first);
             gbar(a.bar);
             return 0;
         }
@@ -2124,7 +2129,7 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
             const int32_t code = total > pd->gcap && !(pd->strict && bad != 0x7fffffff) ? -9 : a.b.err[bad];
             gbar(a.bar);  // every thread has read the counters and err[bad]
             vdel_finish_ids(a, pd, ids, B.s, false, G);
-            if (gtid() == 0) prog_record(a, out, code, bad == 0x7fffffff ? -1 : bad, 0, 0, 0);
+            if (gtid() == 0) prog_record(a, out, code, bad == 0x7fffffff ? -1 : bad, 0, 0, 0, ep_first);
             gbar(a.bar);
             return 0;
         }
@@ -2219,7 +2224,7 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
     if (B.kind == 3) {
         vdel_finish_ids(a, pd, ids, B.s, status == 0, G);
         gbar(a.bar);
-        if (gtid() == 0) prog_record(a, out, status, vbad == 0x7fffffff ? -1 : vbad, valid, iters, vdone);
+        if (gtid() == 0) prog_record(a, out, status, vbad == 0x7fffffff ? -1 : vbad, valid, iters, vdone, ep_first);
         gbar(a.bar);
         return 0;
     }
@@ -2231,7 +2236,7 @@ __device__ __forceinline__ int run_one_batch(const KArgs &a, const ProgDesc *pd,
         }
     }
     gbar(a.bar);  // every thread has read the counters before the next batch resets them
-    if (gtid() == 0) prog_record(a, out, status, fb, valid, iters, vdone);
+    if (gtid() == 0) prog_record(a, out, status, fb, valid, iters, vdone, ep_first);
     return 0;
 }
 
@@ -2270,6 +2275,15 @@ __device__ __forceinline__ void run_program(const KArgs &a) {
 // broadcasts the decision through the grid barrier; after each batch it
 // publishes the finished count (system-scope release).  Every wave leaves
 // when the decision is not "run".
+//
+// Continuous batching across sessions: when fusion is on, the edge requests
+// published behind request j that have the same kind, belong to distinct
+// independent sessions (disjoint graphs, no edge between them) and lie
+// contiguously in the payload ring join j's batch, up to `fuse` requests:
+// they are validated as one batch whose items carry their request's index
+// (each request keeps its own strictness), and their iterations are shared.
+// A disjoint union has no edge between its members, so every vertex's core
+// moves exactly as it would with its own request alone.
 __device__ __forceinline__ void run_server(const KArgs &a) {
     Ctl *c = a.ctl;
     ProgDesc *pd = a.prog;
@@ -2279,33 +2293,88 @@ __device__ __forceinline__ void run_server(const KArgs &a) {
     int pubs = 0;
     long long j = pd->sfirst;
     int32_t reason = SV_STOP;
+    const Team G = grid_team();
     for (;;) {
         if (bar_aborted(a.bar)) { reason = SV_ABORT; break; }
         if (gtid() == 0) {
             int32_t d = SV_RUN;
+            long long tail = 0;
             const unsigned long long t0 = (unsigned long long)wall_clock64();
             for (;;) {
-                long long tail = __hip_atomic_load(&h->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                tail = __hip_atomic_load(&h->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
                 if (tail > j) break;
                 if (__hip_atomic_load(&h->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) { d = SV_STOP; break; }
                 if ((unsigned long long)wall_clock64() - t0 > pd->idle_ticks) { d = SV_IDLE; break; }
                 __builtin_amdgcn_s_sleep(16);
             }
-            if (d == SV_RUN) c->sv_batch = pd->batches[j % pd->ring];  // one host read, not one per thread
+            if (d == SV_RUN) {
+                ProgBatch B = pd->batches[j % pd->ring];  // one host read, not one per thread
+                int32_t gn = 1;
+                c->sv_goff[0] = 0;
+                c->sv_goff[1] = B.s;
+                if (pd->fuse > 1 && pd->strict && B.kind <= 1 && B.session >= 0) {
+                    int32_t sess[FUSE_MAX];
+                    sess[0] = B.session;
+                    int64_t total = B.s, end = B.off + B.s;
+                    while (gn < pd->fuse && gn < FUSE_MAX && j + gn < tail) {
+                        const ProgBatch X = pd->batches[(j + gn) % pd->ring];
+                        if (X.kind != B.kind || X.session < 0 || X.off != end) break;
+                        if (total + X.s > a.b.cap || hash_slots((int32_t)(total + X.s)) > a.b.hcap) break;
+                        bool again = false;
+                        for (int32_t q = 0; q < gn; ++q) again |= sess[q] == X.session;
+                        if (again) break;
+                        sess[gn] = X.session;
+                        total += X.s;
+                        end += X.s;
+                        ++gn;
+                        c->sv_goff[gn] = (int32_t)total;
+                    }
+                    B.s = (int32_t)total;
+                }
+                B.nsub = gn > 1 ? gn : 0;
+                c->sv_batch = B;
+                c->sv_gn = gn;
+            }
             c->sv_decision = d;
         }
         gbar(a.bar);
         const int32_t d = ld_rlx(&c->sv_decision);
         if (d != SV_RUN) { reason = d; break; }
         const ProgBatch B = c->sv_batch;
+        const int32_t gn = ld_rlx(&c->sv_gn);
         if (hash_slots(B.s) > a.b.hcap || B.s > a.b.cap) { reason = SV_TOOBIG; break; }
+        if (gn > 1) {
+            // request index of every item, and a clear outcome word per request
+            for (int32_t i = G.rank; i < B.s; i += G.size) {
+                int32_t q = 0;
+                while (q + 1 < gn && ld_rlx(&c->sv_goff[q + 1]) <= i) ++q;
+                pd->bsub[i] = q;
+            }
+            for (int32_t q = G.rank; q < gn; q += G.size) pd->sub_bad[q] = ~0ull;
+            gbar(a.bar);
+        }
         if (run_one_batch(a, pd, B, pd->out[j % pd->ring], pd->bstamp0 + 2 * (int32_t)(j - pd->sfirst), ep,
                           acc, pubs)) {
             reason = SV_POOL;
             break;
         }
-        if (gtid() == 0) __hip_atomic_store(&h->head, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        ++j;
+        if (gtid() == 0 && gn > 1) {
+            // each fused request gets its own outcome: status, first bad item
+            // and applied count of its items, the shared batch's statistics
+            const ProgOut o = pd->out[j % pd->ring];
+            for (int32_t q = 0; q < gn; ++q) {
+                ProgOut r = o;
+                const unsigned long long sb = pd->sub_bad[q];
+                const int32_t lo = c->sv_goff[q], sq = c->sv_goff[q + 1] - lo;
+                r.status = sb == ~0ull ? 0 : -(int32_t)(sb & 0xffull);
+                r.first_bad = sb == ~0ull ? -1 : (int32_t)(sb >> 8) - lo;
+                r.valid = r.status == 0 ? sq : 0;
+                r.group = gn;
+                pd->out[(j + q) % pd->ring] = r;
+            }
+        }
+        if (gtid() == 0) __hip_atomic_store(&h->head, j + gn, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        j += gn;
     }
     if (gtid() == 0) {
         c->epoch = ep;

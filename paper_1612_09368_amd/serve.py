@@ -3,7 +3,9 @@
 ``Server`` wraps the ``cm_serve_*`` calls: requests are copied into the
 library's pinned request ring and published; one persistent launch picks
 each one up as soon as it is published (requests arriving while others run
-join the running launch) and applies them in ticket order.  A submit that
+join the running launch) and applies them in ticket order.  With ``fuse`` >
+1, edge requests of distinct independent sessions that are waiting together
+run fused in one batch, sharing its iterations.  A submit that
 the library cannot admit yet (ring, payload space or memory budget full)
 returns None; the caller polls and submits it again.
 
@@ -46,14 +48,17 @@ class Server:
         self.graph._check(st, what)
         return int(ticket.value)
 
-    def submit_edges(self, kind, src, dst):
-        """kind REQ_INSERT_EDGES / REQ_DELETE_EDGES; returns the ticket or None (busy)."""
+    def submit_edges(self, kind, src, dst, session=-1):
+        """kind REQ_INSERT_EDGES / REQ_DELETE_EDGES; session >= 0 names an
+        independent session (see cm_serve_submit_edges); returns the ticket
+        or None (busy)."""
         s, ps = _c(src, np.int32)
         d, pd = _c(dst, np.int32)
         if s.size != d.size:
             raise ValueError("src and dst differ in length")
         t = ctypes.c_int64()
-        return self._submit(self._lib.cm_serve_submit_edges(self.graph._h, kind, s.size, ps, pd, ctypes.byref(t)),
+        return self._submit(self._lib.cm_serve_submit_edges(self.graph._h, int(session), kind, s.size, ps, pd,
+                                                            ctypes.byref(t)),
                             t, "cm_serve_submit_edges")
 
     def submit_insert_vertices(self, off, nbrs):
@@ -93,15 +98,15 @@ class Server:
             self.graph._check(self._lib.cm_serve_stop(self.graph._h), "cm_serve_stop")
 
 
-def submit_request(server, req):
+def submit_request(server, req, session=-1):
     """req: ("ins", src, dst) | ("del", src, dst) | ("vins", off, nbrs) | ("vdel", ids).
     Returns (ticket, first new id or -1) or None when busy."""
     kind = req[0]
     if kind == "ins":
-        t = server.submit_edges(REQ_INSERT_EDGES, req[1], req[2])
+        t = server.submit_edges(REQ_INSERT_EDGES, req[1], req[2], session)
         return None if t is None else (t, -1)
     if kind == "del":
-        t = server.submit_edges(REQ_DELETE_EDGES, req[1], req[2])
+        t = server.submit_edges(REQ_DELETE_EDGES, req[1], req[2], session)
         return None if t is None else (t, -1)
     if kind == "vins":
         return server.submit_insert_vertices(req[1], req[2])
@@ -121,9 +126,10 @@ def request_updates(req):
     return 0
 
 
-def run_stream(server, requests, arrivals=None, poll_sleep=0.0):
+def run_stream(server, requests, arrivals=None, poll_sleep=0.0, sessions=None):
     """Submit `requests` in order at `arrivals` (seconds from the start; None
-    = as fast as admission allows) and wait for all of them.
+    = as fast as admission allows) and wait for all of them; sessions[i]
+    (optional) is request i's independent session.
 
     Returns dict with per-request arrays: ticket, first_id, t_arrival,
     t_submit, t_done (seconds) and the BatchStats of each request."""
@@ -141,7 +147,7 @@ def run_stream(server, requests, arrivals=None, poll_sleep=0.0):
     while nxt < n or done_seen <= last:
         now = time.perf_counter() - t0
         while nxt < n and t_arr[nxt] <= now:
-            r = submit_request(server, requests[nxt])
+            r = submit_request(server, requests[nxt], -1 if sessions is None else int(sessions[nxt]))
             if r is None:
                 break
             tickets[nxt], first_ids[nxt] = r
