@@ -104,6 +104,9 @@ typedef struct cm_config {
                                    algorithm's pruning: two passes over an expanding list); 2 = it
                                    claims them while counting its CSD (one pass per list, a
                                    larger visited set, same cores); 0 = default (2) */
+    int32_t stamp_limit;        /* iteration stamps restart (the kernels clear the arrays that hold
+                                   them, at an iteration boundary) before a stamp passes this;
+                                   0 = default (2^28, also the largest allowed) */
     void *stream;               /* hipStream_t to run on; NULL = the null stream */
 } cm_config;
 

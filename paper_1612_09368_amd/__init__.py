@@ -57,6 +57,7 @@ class Config(ctypes.Structure):
         ("single_edge", ctypes.c_int32),
         ("debug", ctypes.c_int32),
         ("expand_mode", ctypes.c_int32),
+        ("stamp_limit", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -199,7 +200,7 @@ class Graph:
     def __init__(self, mode=MODE_PLAIN, strict=True, vertex_capacity=0, edge_capacity_hint=0,
                  partition_rounds=0, blocks_per_cu=0, small_degree=0, large_degree=0, chunk=0,
                  local_edges=0, local_items=0, local_work=0, timing=False, use_graph=False, async_steps=False,
-                 single_edge=False, debug=0, expand_mode=0, stream=None, _restore_from=None):
+                 single_edge=False, debug=0, expand_mode=0, stamp_limit=0, stream=None, _restore_from=None):
         lib = library()
         cfg = Config()
         lib.cm_config_default(ctypes.byref(cfg))
@@ -221,6 +222,7 @@ class Graph:
         cfg.single_edge = 1 if single_edge else 0
         cfg.debug = int(debug)
         cfg.expand_mode = int(expand_mode)
+        cfg.stamp_limit = int(stamp_limit)
         cfg.stream = stream if stream is not None else default_stream()
         h = ctypes.c_void_p()
         if _restore_from is None:

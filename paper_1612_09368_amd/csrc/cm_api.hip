@@ -99,6 +99,7 @@ struct cm_graph {
     bool loaded = false;
     bool decomposed = false;
     bool poisoned = false;
+    int clock_khz = 0;        // device wall clock rate
     bool no_alloc = false;    // inside cm_update_edges_noalloc: the pool may not grow
     void *na_scratch = nullptr;  // this device's address of the allocation-free scratch array
     int64_t m = 0;
@@ -233,8 +234,33 @@ KArgs make_args(cm_graph *g) {
     return a;
 }
 
+// Bounds of the kernels' waits, in device wall-clock ticks: a grid barrier
+// wait may last BAR_WAIT_MS plus `extra_ms` (a serving launch's idle wait,
+// during which one thread waits for the host while the others sit at the
+// barrier), a workgroup's chain of local steps runs at most LOCAL_SLICE_MS
+// before it passes a barrier.
+constexpr unsigned long long BAR_WAIT_MS = 10000, LOCAL_SLICE_MS = 20;
+void set_bar_bounds(cm_graph *g, int64_t extra_ms) {
+    const unsigned long long khz = (unsigned long long)g->clock_khz;
+    const unsigned long long v[2] = {(BAR_WAIT_MS + (unsigned long long)std::max<int64_t>(extra_ms, 0)) * khz,
+                                     LOCAL_SLICE_MS * khz};
+    HIPCHK(hipMemcpyAsync(&g->bar->wait_ticks[0], &v[0], sizeof(v[0]), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(&g->bar->slice_ticks[0], &v[1], sizeof(v[1]), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+}
+
+// Batch stamps (bmark values) restart before they could overflow: the host
+// clears the marks between calls.
+void bstamp_guard(cm_graph *g) {
+    if (g->bstamp < (1 << 29) || !g->g.bmark) return;
+    HIPCHK(fill_i32(g->g.bmark, 0, g->g.n_cap, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    g->bstamp = 0;
+}
+
 // Debug mode: every update call starts an empty iteration log.
 void debug_reset(cm_graph *g) {
+    bstamp_guard(g);
     if (g->dl.n) HIPCHK(fill_u64(g->dl.n, 0ull, 2, g->stream));
 }
 
@@ -1024,6 +1050,11 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
             throw Fail{CM_E_ARG};
         }
         g->tune.prune = g->cfg.expand_mode == 1 ? 1 : 0;
+        if (g->cfg.stamp_limit < 0) {
+            g->err = "stamp_limit must be >= 0";
+            throw Fail{CM_E_ARG};
+        }
+        g->tune.stamp_limit = g->cfg.stamp_limit > 0 ? std::min(g->cfg.stamp_limit, EPOCH_REWIND) : EPOCH_REWIND;
         if (g->tune.single_edge) g->tune.rounds = 1;
         if (g->tune.large_deg < g->tune.small_deg) g->tune.large_deg = g->tune.small_deg;
         int bpc_m = 0, bpc_d = 0;
@@ -1043,6 +1074,12 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         HIPCHK(hipMemsetAsync(g->ctl, 0, sizeof(Ctl), g->stream));
         dev_alloc(g, &g->bar, 1);
         HIPCHK(hipMemsetAsync(g->bar, 0, sizeof(Bar), g->stream));
+        HIPCHK(hipDeviceGetAttribute(&g->clock_khz, hipDeviceAttributeWallClockRate, g->device));
+        if (g->clock_khz <= 0) {
+            g->err = "device wall clock rate unknown";
+            throw Fail{CM_E_DEVICE};
+        }
+        set_bar_bounds(g, 0);
         HIPCHK(hipHostMalloc((void **)&g->hctl, sizeof(Ctl), hipHostMallocDefault));
         std::memset(g->hctl, 0, sizeof(Ctl));
         HIPCHK(hipHostMalloc((void **)&g->hu64, 4 * sizeof(unsigned long long), hipHostMallocDefault));
@@ -1688,6 +1725,7 @@ void serve_collect(cm_graph *g) {
 
 void serve_launch(cm_graph *g) {
     hipStream_t st = g->stream;
+    bstamp_guard(g);
     ProgDesc *hd = g->h_prog;
     std::memset(hd, 0, sizeof(ProgDesc));
     hd->batches = host_dev_ptr(g, g->sring);
@@ -1841,6 +1879,7 @@ int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
             g->sub_cap = (int32_t)cap;
         }
         debug_reset(g);
+        set_bar_bounds(g, c.idle_ms);
         HIPCHK(hipHostMalloc((void **)&g->shdr, sizeof(ServeHdr), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&g->sring, sizeof(ProgBatch) * (size_t)c.ring_requests, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void **)&g->sout, sizeof(ProgOut) * (size_t)c.ring_requests, hipHostMallocDefault));
@@ -2033,6 +2072,7 @@ int cm_serve_stop(cm_graph *g) {
         g->g.n_ids = std::max(g->g.n_ids, g->s_n_ids);
         g->serving = false;
         serve_free(g);
+        set_bar_bounds(g, 0);
     } catch (const Fail &f) {
         g->serving = false;
         return f.code;
@@ -2312,7 +2352,7 @@ int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap, int64_
 int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t *offsets,
                    const int32_t *src, const int32_t *dst, const int32_t *sub, int32_t nsub,
                    int on_device, cm_batch_stats *results, int32_t *sub_status) {
-    if (!g || nb < 0 || (nb > 0 && (!kinds || !offsets))) return CM_E_ARG;
+    if (!g || nb < 0 || nb > (1 << 28) || (nb > 0 && (!kinds || !offsets))) return CM_E_ARG;
     if (nsub < 0 || (sub && nsub == 0)) return CM_E_ARG;
     double t0 = now_ms();
     if (results)

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cm_keys.h"
+
 namespace cm {
 
 constexpr int WAVE = 64;
@@ -124,6 +126,8 @@ struct Bar {
     unsigned int gen[32];
     unsigned int abort[32];   // set when a wait gives up; later barriers return at once
     unsigned long long xreg[XSLOTS * 16];  // per XCC: (launch epoch << 32) | workgroups on it
+    unsigned long long wait_ticks[16];   // [0]: device wall-clock ticks a barrier wait may last
+    unsigned long long slice_ticks[16];  // [0]: ticks one workgroup's chain of local steps may run
 };
 
 // Per-vertex device arrays plus the adjacency pool.
@@ -205,6 +209,8 @@ struct Tune {
     int32_t single_edge; // one edge per iteration (the sequential regime) instead of a superior edge set
     int32_t prune;       // expansion visits the neighbours of a candidate only once its CSD exceeds its
                          // core (Algorithm 3); 0 = claims them while counting the CSD
+    int32_t stamp_limit; // iteration stamps restart (stamp arrays cleared) before passing this
+    int32_t pad;
 };
 
 // Chunk items of the expansion's claim pass (pruned expansion) carry this
@@ -290,7 +296,11 @@ struct ProgOut {
     unsigned long long icand, cdeg, edeg, hdeg;
 };
 // Why a serving launch ended (ServeHdr.exit_reason; 0 while it runs).
-enum ServeExit : int32_t { SV_RUN = 1, SV_STOP = 2, SV_IDLE = 3, SV_POOL = 4, SV_ABORT = 5, SV_TOOBIG = 6 };
+enum ServeExit : int32_t { SV_RUN = 1, SV_STOP = 2, SV_IDLE = 3, SV_POOL = 4, SV_ABORT = 5, SV_TOOBIG = 6,
+                           SV_RESTAMP = 7 };
+// A serving launch hands back to the host after this many batches (their
+// batch stamps, two per batch from the launch's first, stay below 2^29).
+constexpr long long SERVE_BATCHES = 1ll << 27;
 
 // Serving header in pinned host memory; each word on its own 128-byte line.
 struct ServeHdr {
@@ -465,17 +475,26 @@ __device__ __forceinline__ unsigned xcc_id() {
     return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (XSLOTS - 1);  // HW_REG_XCC_ID[3:0]
 }
 
-// Wait (bounded, about a second) until the generation word moves past g0;
-// a workgroup that never arrives is a bug: the barrier then trips the abort
-// word instead of hanging, and the drivers stop at their next check.
+// Wait until the generation word moves past g0, for at most wait_ticks of
+// the device wall clock (the host sets it above every wait the drivers can
+// create legitimately: a serving launch's idle wait, a workgroup's slice of
+// local steps); a workgroup that never arrives is a bug: the barrier then
+// trips the abort word instead of hanging, and the drivers stop at their
+// next check.
 __device__ __forceinline__ void bar_wait(Bar *b, unsigned g0) {
     unsigned polls = 0;
+    unsigned long long t0 = 0;
     while (__hip_atomic_load(&b->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
         if (__hip_atomic_load(&b->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         __builtin_amdgcn_s_sleep(2);
-        if (++polls > (1u << 25)) {
-            __hip_atomic_store(&b->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+        if ((++polls & 1023u) == 0u) {
+            const unsigned long long now = (unsigned long long)wall_clock64();
+            if (t0 == 0) {
+                t0 = now;
+            } else if (now - t0 > __hip_atomic_load(&b->wait_ticks[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(&b->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
         }
     }
     // one acquire for the whole workgroup after the wait (polls stay relaxed)
@@ -574,6 +593,20 @@ __device__ __forceinline__ void gbar(Bar *b) {
         bar_wait(b, g0);
     }
     __syncthreads();
+}
+
+// Whether the chain of local steps that workgroup 0 started at t0 (thread
+// 0's clock) has used its slice: decided by thread 0, the same answer in
+// every thread of the workgroup (all of them must call).
+__device__ __forceinline__ bool slice_over(const Bar *b, unsigned long long t0) {
+    __shared__ int over;
+    if (threadIdx.x == 0)
+        over = (unsigned long long)wall_clock64() - t0 >
+               __hip_atomic_load(&b->slice_ticks[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const bool r = over != 0;
+    __syncthreads();
+    return r;
 }
 
 __device__ __forceinline__ bool bar_aborted(Bar *b) {

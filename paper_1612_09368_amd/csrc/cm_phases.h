@@ -357,11 +357,6 @@ struct PC {
     int32_t r;
 };
 
-__device__ __forceinline__ bool matched_before(uint32_t m, int32_t ep, int rounds, int r) {
-    uint32_t lo = (uint32_t)ep * (uint32_t)rounds + 1u;
-    uint32_t hi = (uint32_t)ep * (uint32_t)rounds + (uint32_t)r;
-    return m >= lo && m <= hi;
-}
 
 // ===========================================================================
 // Asynchronous traversal steps.
@@ -452,6 +447,8 @@ __device__ __forceinline__ void aq_run(const KArgs &a, int qi, P &&proc) {
     const int32_t cap = a.q.acap;
     constexpr int G = 16;
     unsigned polls = 0;
+    unsigned long long t0 = 0;   // clock when the step last showed progress to this wave
+    int32_t seen = -1;           // items handed out when last checked
     for (;;) {
         int32_t base = 0;
         if (lane() == 0) base = atomicAdd(&c->aq_head[qi], G);
@@ -476,14 +473,26 @@ __device__ __forceinline__ void aq_run(const KArgs &a, int qi, P &&proc) {
                 wave_drain();  // children pushed (pending raised) before this item counts as done
                 if (lane() == 0) atomicSub(&c->aq_pend[qi], __popcll(fm));
                 polls = 0;
+                t0 = 0;
                 continue;
             }
             if (ld_rlx(&c->aq_pend[qi]) == 0 || bar_aborted(a.bar)) { done = true; break; }
             __builtin_amdgcn_s_sleep(1);
-            if (++polls > (1u << 24)) {  // bounded: a lost item is a bug, not a hang
-                if (lane() == 0) __hip_atomic_store(&a.bar->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                done = true;
-                break;
+            if ((++polls & 1023u) == 0u) {
+                // bounded: a wait longer than the barrier bound with no item
+                // handed out anywhere is a lost item (a bug), not a hang
+                const unsigned long long now = (unsigned long long)wall_clock64();
+                const int32_t tail = ld_rlx(&c->aq_tail[qi]);
+                if (tail != seen || t0 == 0) {
+                    seen = tail;
+                    t0 = now;
+                } else if (now - t0 > __hip_atomic_load(&a.bar->wait_ticks[0], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)) {
+                    if (lane() == 0)
+                        __hip_atomic_store(&a.bar->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    done = true;
+                    break;
+                }
             }
         }
         if (done) break;
@@ -516,8 +525,7 @@ __device__ __forceinline__ void part_claim(const KArgs &a, const Iter &it, int r
         c->st_remaining += (unsigned long long)it.n_r;
     }
     const int32_t *R = a.b.rem[it.cur];
-    const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds + (uint32_t)r;
-    const unsigned long long hi = (unsigned long long)(0xFFFFFFFFu - sr) << 32;
+    const unsigned long long hi = claim_hi(it.ep, a.t.rounds, r);
     for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
         int32_t i = R[idx];
         if (r > 0 && a.b.esel[i] == it.ep) continue;
@@ -616,9 +624,8 @@ __device__ __forceinline__ void part_select(const KArgs &a, const Iter &it, int 
     Ctl *c = a.ctl;
     const bool last = r == a.t.rounds - 1;
     const int32_t *R = a.b.rem[it.cur];
-    const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds + (uint32_t)r;
-    const unsigned long long hi = (unsigned long long)(0xFFFFFFFFu - sr) << 32;
-    const uint32_t mstamp = sr + 1u;
+    const unsigned long long hi = claim_hi(it.ep, a.t.rounds, r);
+    const uint32_t mstamp = matched_stamp(it.ep, a.t.rounds, r);
     for (int32_t idx = T.rank; idx < it.n_r; idx += T.size) {
         int32_t i = R[idx];
         if (r > 0 && a.b.esel[i] == it.ep) continue;  // taken in an earlier round
@@ -698,11 +705,10 @@ __device__ __forceinline__ int32_t lower_bound_i32(const int32_t *p, int32_t n, 
 }
 
 __device__ __forceinline__ unsigned long long star_key(const Iter &it, const KArgs &a, uint32_t id) {
-    const uint32_t sr = (uint32_t)it.ep * (uint32_t)a.t.rounds;
-    return ((unsigned long long)(0xFFFFFFFFu - sr) << 32) | mix32(id);
+    return claim_hi(it.ep, a.t.rounds, 0) | mix32(id);
 }
 __device__ __forceinline__ uint32_t star_mstamp(const Iter &it, const KArgs &a) {
-    return (uint32_t)it.ep * (uint32_t)a.t.rounds + 1u;
+    return matched_stamp(it.ep, a.t.rounds, 0);
 }
 
 // Insertion star i: item j of [lo, hi) is an edge of v = v0 + i to an
@@ -1770,6 +1776,25 @@ __device__ __forceinline__ void run_step(const KArgs &a, const Iter &it, const P
     }
 }
 
+// Restart the iteration stamps (whole grid, at an iteration boundary, where
+// no stamp is live): every array that holds one goes back to its cleared
+// value, so stamps from 1 on are fresh again (the caller keeps the stamp's
+// parity, which selects the remaining-edge list).
+__device__ __forceinline__ void restamp(const KArgs &a) {
+    const Team G = grid_team();
+    const DevGraph &g = a.g;
+    for (int32_t i = G.rank; i < g.n_cap; i += G.size) {
+        g.claim[i] = ~0ull;
+        g.matched[i] = 0u;
+        g.stamp[i] = 0;
+        g.chg[i] = 0;
+        g.cd[i] = 0;
+    }
+    for (int32_t i = G.rank; i < a.b.cap; i += G.size) a.b.esel[i] = 0;
+    if (G.lead()) a.ctl->one_key = 0ull;
+    gbar(a.bar);
+}
+
 // Runs up to max_iters iterations of the current batch (each one superior
 // edge set).  ep is the last iteration stamp used (in/out).  Returns the
 // iterations run.  Workgroup 0 publishes the step where a local run stopped
@@ -1780,6 +1805,13 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
     Ctl *c = a.ctl;
     int it_n = 0;
     for (; it_n < max_iters; ++it_n) {
+        if (ep >= a.t.stamp_limit) {
+            restamp(a);
+            // restart at 0 or 1, keeping ep's parity: the iteration stamped
+            // ep + 1 reads the remaining list rem[(ep + 1) & 1], where the
+            // previous iteration (or the batch's validation) left the edges
+            ep &= 1;
+        }
         Iter it;
         it.ep = ep + 1;
         it.cur = it.ep & 1;
@@ -1805,6 +1837,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                 if (blockIdx.x == 0) {
                     const Team T = block_team();
                     bool fg = false;
+                    const unsigned long long tl = (unsigned long long)wall_clock64();
                     for (;;) {
                         if (!block_local_ok(a, it, pc, T)) { fg = true; break; }
                         run_step(a, it, pc, T, acc);
@@ -1814,6 +1847,10 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                         if (pc.step == S_DONE) break;
                         work = step_work(a, it, pc);
                         if (!step_is_local(a, it, pc, work)) break;
+                        // a long chain (a cascade of many small rounds) hands
+                        // back to the grid once per slice, so that no barrier
+                        // wait outlasts its bound
+                        if (slice_over(a.bar, tl)) break;
                     }
                     if (threadIdx.x == 0) {
                         c->ipub[slot][0] = pc.step;
@@ -2296,6 +2333,7 @@ __device__ __forceinline__ void run_server(const KArgs &a) {
     const Team G = grid_team();
     for (;;) {
         if (bar_aborted(a.bar)) { reason = SV_ABORT; break; }
+        if (j - pd->sfirst >= SERVE_BATCHES) { reason = SV_RESTAMP; break; }
         if (gtid() == 0) {
             int32_t d = SV_RUN;
             long long tail = 0;
@@ -2539,6 +2577,7 @@ __device__ __forceinline__ void decompose(const KArgs &a, Acc &acc) {
             if (blockIdx.x == 0) {
                 const Team T = block_team();
                 bool fg = false;
+                const unsigned long long tl = (unsigned long long)wall_clock64();
                 for (;;) {
                     if (!dec_block_local_ok(a, st, T)) { fg = true; break; }
                     if (st.step == D_SWEEP) dec_sweep(a, st, T);
@@ -2548,6 +2587,7 @@ __device__ __forceinline__ void decompose(const KArgs &a, Acc &acc) {
                     st = dec_next(a, st);
                     if (st.step == D_DONE) break;
                     if (dec_work(a, st) > a.t.local_items) break;
+                    if (slice_over(a.bar, tl)) break;
                 }
                 if (threadIdx.x == 0) {
                     c->dpub[slot][0] = st.step;
