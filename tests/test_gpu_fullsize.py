@@ -150,3 +150,83 @@ def test_rmat22_stream_plain_leading_batches(cm, rmat22):
         progress(f"plain: batches 0..{PLAIN_CHECKED - 1} match the oracle")
     finally:
         g.close()
+
+
+POOL_COUNT = 512
+
+
+@pytest.fixture(scope="module")
+def pool512(oracle_mod):
+    """The benchmark's 512 Chung-Lu graphs (n log-uniform in [1000, 200000],
+    mean degree U[4, 32], exponent 2.3), each with an insertion batch and a
+    deletion batch of 5% of its edges, plus the oracle's cores of every
+    member after its insertion batch and after its deletion batch (members
+    in parallel threads; BZ releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t = time.time()
+    pool = graphgen.chung_lu_pool(POOL_COUNT, graphgen.rng_for("bench-pool512"), workers=WORKERS)
+    progress(f"pool generated in {time.time() - t:.0f}s")
+
+    def member(m):
+        n, s, d, ins, dele = m
+        ref = oracle_mod.DynamicGraph(n, s, d)
+        assert ref.insert_edges(*ins)[0] == 0
+        c1 = ref.cores()
+        assert ref.delete_edges(*dele)[0] == 0
+        return c1, ref.cores()
+
+    with ThreadPoolExecutor(max_workers=WORKERS) as ex:
+        states = list(ex.map(member, pool))
+    progress(f"pool oracle ready after {time.time() - t:.0f}s")
+    return pool, states
+
+
+def test_pool512_every_member(cm, pool512):
+    """The 512 graphs packed as one disjoint union, every member batch a
+    sub-batch: stage 1 (all insertion batches) and stage 2 (all deletion
+    batches) as two calls, each member's cores compared with the oracle
+    after each stage; then both stages in one call replayed from a hipGraph
+    (as timed) on a fresh handle, compared at the end."""
+    import torch
+    pool, states = pool512
+    dev = torch.device("cuda:0")
+    graphs = [(n, s, d) for n, s, d, _, _ in pool]
+    batches = []
+    for gid, (_, _, _, ins, dele) in enumerate(pool):
+        batches.append((gid, cm.BATCH_INSERT, ins[0], ins[1]))
+        batches.append((gid, cm.BATCH_DELETE, dele[0], dele[1]))
+    base, us, ud = cm.union_edges(graphs)
+    kinds, offs, xs, ys, sub, nsub, order = cm.pack_batches(base, batches)
+    assert kinds.tolist() == [cm.BATCH_INSERT, cm.BATCH_DELETE]
+    want = [np.concatenate([st[k] for st in states]) for k in (0, 1)]
+    dus, dud, dx, dy, dsub = (torch.from_numpy(z).to(dev) for z in (us, ud, xs, ys, sub))
+    from paper_1612_09368_amd import autotune
+    params, _ = autotune.params_for(int(base[-1]), us.size, [b[2].size for b in batches])
+
+    def load():
+        g = cm.Graph(mode=cm.MODE_PERSISTENT, use_graph=True, timing=True, **params)
+        g.load(int(base[-1]), dus, dud)
+        g.decompose()
+        return g
+
+    g = load()
+    try:
+        for stage in (0, 1):
+            lo, hi = int(offs[stage]), int(offs[stage + 1])
+            res, sst = g.run_batches(kinds[stage:stage + 1], np.array([0, hi - lo], np.int64), dx[lo:hi],
+                                     dy[lo:hi], sub=dsub[lo:hi], nsub=nsub)
+            assert res[0].status == 0 and (sst == 0).all()
+            got = g.cores()
+            bad = np.nonzero(got != want[stage])[0]
+            assert bad.size == 0, (f"stage {stage}: {bad.size} cores differ, first in graph "
+                                   f"{np.searchsorted(base, bad[0], side='right') - 1}")
+            progress(f"pool stage {stage}: every member matches the oracle")
+    finally:
+        g.close()
+    g = load()
+    try:
+        res, sst = g.run_batches(kinds, offs, dx, dy, sub=dsub, nsub=nsub)
+        assert all(r.status == 0 for r in res) and (sst == 0).all() and res[0].graph_launch == 1
+        assert np.array_equal(g.cores(), want[1])
+    finally:
+        g.close()

@@ -297,3 +297,154 @@ def test_vertex_star_bounds(oracle_mod, seed):
         for u in range(n):
             if u not in dead:
                 assert K[u] - 1 <= C2[u] <= K[u], (seed, trial, u)
+
+
+def _definitional_cores_all(n):
+    """Core numbers of every labelled graph on n vertices at once, straight
+    from the definition (core(v) = the largest minimum degree of an induced
+    subgraph containing v): graphs are rows of neighbour bitmasks, and every
+    vertex subset S is tried for every graph in one vectorised pass."""
+    pairs = list(itertools.combinations(range(n), 2))
+    masks = np.arange(1 << len(pairs), dtype=np.int64)
+    adj = np.zeros((masks.size, n), dtype=np.int64)
+    for i, (a, b) in enumerate(pairs):
+        on = (masks >> i) & 1
+        adj[:, a] |= on << b
+        adj[:, b] |= on << a
+    best = np.zeros((masks.size, n), dtype=np.int64)
+    popcount = np.vectorize(lambda x: bin(int(x)).count("1"))
+    table = popcount(np.arange(1 << n))
+    for S in range(1, 1 << n):
+        members = [v for v in range(n) if S >> v & 1]
+        mindeg = np.min(np.stack([table[adj[:, v] & S] for v in members]), axis=0)
+        for v in members:
+            np.maximum(best[:, v], mindeg, out=best[:, v])
+    return pairs, masks, best
+
+
+def test_all_labelled_graphs_n6(oracle_mod):
+    """Every one of the 2^15 labelled graphs on 6 vertices: definition ==
+    BZ == threshold peeling."""
+    n = 6
+    pairs, masks, best = _definitional_cores_all(n)
+    for g in range(masks.size):
+        sel = [p for i, p in enumerate(pairs) if g >> i & 1]
+        s = np.asarray([p[0] for p in sel], dtype=np.int32)
+        d = np.asarray([p[1] for p in sel], dtype=np.int32)
+        z = oracle_mod.bz_cores(n, s, d)
+        assert np.array_equal(z, best[g]), (sel, z, best[g])
+        if g % 7 == 0:  # peeling is slower: every seventh graph
+            assert np.array_equal(oracle_mod.peel_cores(n, s, d), best[g]), sel
+
+
+def test_method_model_fuzz(oracle_mod):
+    """10^4 random tiny cases of the paper's iterative method (Algorithms 1-7
+    with the readings in oracle.method): after every iteration the cores
+    equal BZ of the graph so far, every core moved by at most one in the
+    batch's direction and only at a level of an edge of the iteration's set
+    (lemmas and theorems on superior edge set insertion and deletion,
+    Section IV-A).  Sets holding edges of adjacent levels k and k + 1 -- the
+    case whose proof is informal -- must occur often."""
+    from oracle import method
+    rng = np.random.default_rng(2024)
+    adjacent = 0
+    iterations = 0
+    for case in range(10_000):
+        n = int(rng.integers(4, 12))
+        pairs = _random_graph(rng, n, rng.uniform(0.15, 0.7))
+        all_pairs = list(itertools.combinations(range(n), 2))
+        present = set(pairs)
+        absent = [p for p in all_pairs if p not in present]
+        rng.shuffle(absent)
+        ins = absent[: int(rng.integers(0, len(absent) + 1))]
+        s, d = _edges(pairs) if pairs else (np.empty(0, np.int32), np.empty(0, np.int32))
+        G = method.graph_from_edges(n, s, d)
+        core = {v: int(c) for v, c in enumerate(oracle_mod.bz_cores(n, s, d))}
+        cur = set(pairs)
+        for inserting in (True, False):
+            if inserting:
+                batch = ins
+            else:
+                batch = sorted(cur)
+                rng.shuffle(batch)
+                batch = batch[: int(rng.integers(0, len(batch) + 1))]
+            trace = []
+            prev = dict(core)
+            (method.insert_edges if inserting else method.delete_edges)(G, core, batch, trace=trace)
+            for chosen, snap in trace:
+                iterations += 1
+                levels = {min(prev[u], prev[v]) for u, v in chosen}
+                adjacent += any(k + 1 in levels for k in levels)
+                cur = cur | set(chosen) if inserting else cur - set(chosen)
+                cs, cd_ = _edges(sorted(cur)) if cur else (np.empty(0, np.int32),) * 2
+                ref = oracle_mod.bz_cores(n, cs, cd_)
+                for v in range(n):
+                    delta = snap[v] - prev[v]
+                    assert snap[v] == ref[v], (case, inserting, v)
+                    assert delta in ((0, 1) if inserting else (0, -1)), (case, v, delta)
+                    assert delta == 0 or prev[v] in levels, (case, v, prev[v], levels)
+                prev = snap
+    assert iterations > 20_000
+    assert adjacent > 1_000, adjacent
+
+
+def test_insert_vertices_keep_failed_ids(oracle_mod):
+    """The serving convention: ids of a vertex insertion are handed out when
+    it is submitted, so a rejected request keeps them as dead ids (core -1)
+    and the next request's ids come after them; a valid request's new
+    vertices join with their edges."""
+    E = oracle_mod
+    g = E.DynamicGraph(4, np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32))
+    # rejected: neighbour 9 is out of range
+    st, fb, first = g.insert_vertices(np.array([0, 2, 3]), np.array([0, 9, 1]), keep_failed_ids=True)
+    assert (st, fb, first) == (E.E_RANGE, 1, 4)
+    assert g.n == 6 and g.cores().tolist() == [2, 2, 2, 0, -1, -1] and g.num_edges() == 3
+    # edges to the dead ids are now invalid
+    assert g.insert_edges(np.array([0]), np.array([4]))[0] == E.E_DEAD
+    # the next insertion gets ids 6, 7: vertex 6 joins the triangle, 7 hangs off 6
+    st, fb, first = g.insert_vertices(np.array([0, 3, 4]), np.array([0, 1, 2, 6]), keep_failed_ids=True)
+    assert (st, first) == (E.OK, 6)
+    assert g.cores().tolist() == [3, 3, 3, 0, -1, -1, 3, 1] and g.num_edges() == 7
+    # the one-call convention frees the ids of a rejected request instead
+    h = E.DynamicGraph(3, np.array([0], np.int32), np.array([1], np.int32))
+    st, fb, first = h.insert_vertices(np.array([0, 1]), np.array([7]))
+    assert (st, first) == (E.E_RANGE, -1) and h.n == 3
+
+
+def test_dynamic_graph_matches_a_plain_edge_set(oracle_mod):
+    """The oracle's edge storage (initial keys with a presence mask, later
+    keys in a side array) against a Python set on a random stream of
+    insertions, deletions, re-insertions of deleted initial edges and vertex
+    deletions."""
+    rng = np.random.default_rng(7)
+    n = 60
+    s, d = graphgen.er_graph(n, 300, rng)
+    g = oracle_mod.DynamicGraph(n, s, d)
+    model = set(zip(np.minimum(s, d).tolist(), np.maximum(s, d).tolist()))
+    for step in range(400):
+        op = rng.integers(0, 3)
+        if op == 0:
+            cand = [(a, b) for a, b in itertools.combinations(range(n), 2)
+                    if (a, b) not in model and g.alive[a] and g.alive[b]]
+            if not cand:
+                continue
+            k = min(len(cand), int(rng.integers(1, 8)))
+            pick = [cand[i] for i in rng.choice(len(cand), k, replace=False)]
+            a, b = _edges(pick)
+            assert g.insert_edges(b, a)[0] == oracle_mod.OK  # either orientation
+            model |= set(pick)
+        elif op == 1 and model:
+            cur = sorted(model)
+            k = min(len(cur), int(rng.integers(1, 8)))
+            pick = [cur[i] for i in rng.choice(len(cur), k, replace=False)]
+            a, b = _edges(pick)
+            assert g.delete_edges(a, b)[0] == oracle_mod.OK
+            model -= set(pick)
+        elif op == 2 and step % 50 == 0:
+            live = np.nonzero(g.alive)[0]
+            x = int(rng.choice(live))
+            assert g.delete_vertices(np.array([x]))[0] == oracle_mod.OK
+            model = {(a, b) for a, b in model if x not in (a, b)}
+        assert g.num_edges() == len(model)
+        assert g.keys.tolist() == sorted((a << 32) | b for a, b in model)
+        assert g.has(np.array([(a << 32) | b for a, b in list(model)[:5]], np.int64)).all()
