@@ -641,6 +641,95 @@ def bench_serve(args, cm, torch):
 
 
 # ---------------------------------------------------------------------------
+# pool-serve
+# ---------------------------------------------------------------------------
+def bench_pool_serve(args, cm, torch):
+    """Serving many independent graphs (sessions) from one handle: the
+    512-graph pool packed as one disjoint union, each graph's insertion and
+    deletion batches split into requests of its own session (4 + 4), queued
+    round-robin over the graphs.  Closed loop with every request alone in its
+    batch (fuse = 1), then Poisson arrivals at 0.8 x that request rate, with
+    fuse = 1 and with continuous batching across sessions (fuse = 32); p50 /
+    p99 latency from arrival to result."""
+    import graphgen
+    from paper_1612_09368_amd import serve
+    t = time.time()
+    pool = graphgen.chung_lu_pool(POOL_COUNT, graphgen.rng_for("bench-pool512"), workers=WORKERS)
+    graphs = [(n, s, d) for n, s, d, _, _ in pool]
+    base, us, ud = cm.union_edges(graphs)
+    parts = 4
+    per_graph = []
+    for gid, (_, _, _, ins, dele) in enumerate(pool):
+        reqs = []
+        for kind, (a, b) in (("ins", ins), ("del", dele)):
+            for a2, b2 in zip(np.array_split(a, parts), np.array_split(b, parts)):
+                reqs.append((kind, (a2 + base[gid]).astype(np.int32), (b2 + base[gid]).astype(np.int32)))
+        per_graph.append(reqs)
+    reqs, sess = [], []
+    for k in range(2 * parts):
+        for gid in range(POOL_COUNT):
+            reqs.append(per_graph[gid][k])
+            sess.append(gid)
+    total = sum(r[1].size for r in reqs)
+    log(f"pool serving: {len(reqs)} requests, {total} updates ({time.time() - t:.0f}s)")
+    ds, dd = to_dev(torch, us), to_dev(torch, ud)
+    union_n = int(base[-1])
+    params, tuning = tuned_params(args, union_n, us.size, [r[1].size for r in reqs], None)
+    scfg = dict(ring_requests=8192, ring_items=1 << 25, max_items=1 << 22, budget_bytes=8 << 30,
+                vertex_headroom=1024, idle_ms=20)
+
+    def one_run(arrivals, fuse):
+        g = cm.Graph(mode=cm.MODE_PERSISTENT, **params)
+        try:
+            g.load(union_n, ds, dd)
+            g.decompose()
+            torch.cuda.synchronize()
+            srv = serve.Server(g, fuse=fuse, **scfg)
+            res = serve.run_stream(srv, reqs, arrivals, sessions=sess)
+            srv.stop()
+            cores = g.cores()
+        finally:
+            g.close()
+        st = res["stats"]
+        assert all(x.status == 0 for x in st), "a served request failed"
+        lat = (res["t_done"] - res["t_arrival"]) * 1e3
+        groups = np.array([x.group for x in st])
+        return res["elapsed"], lat, cores, groups
+
+    el, lat_c, cores_c, _ = one_run(None, 1)
+    rate = len(reqs) / el
+    log(f"closed loop, alone: {el:.2f}s, {total / el / 1e6:.2f} M updates/s, {rate:.0f} requests/s")
+    elf, lat_cf, cores_cf, grp_cf = one_run(None, 32)
+    log(f"closed loop, fused: {elf:.2f}s, {total / elf / 1e6:.2f} M updates/s, mean group {grp_cf.mean():.1f}")
+    lam = 0.8 * rate
+    arrivals = np.cumsum(np.random.Generator(np.random.PCG64(9)).exponential(1.0 / lam, len(reqs)))
+    el1, lat1, cores1, _ = one_run(arrivals, 1)
+    el2, lat2, cores2, grp2 = one_run(arrivals, 32)
+    for c in (cores_cf, cores1, cores2):
+        assert np.array_equal(cores_c, c), "served results depend on fusion or arrival timing"
+    log(f"poisson at {lam:.0f}/s: alone p50 {pct(lat1, 50):.2f} p99 {pct(lat1, 99):.2f} ms; "
+        f"fused p50 {pct(lat2, 50):.2f} p99 {pct(lat2, 99):.2f} ms")
+    out = contract(f"serving {POOL_COUNT} independent chung-lu graphs as sessions of one handle (union n={union_n} "
+                   f"m={us.size}); {len(reqs)} requests (each graph's 5% insertion and 5% deletion batches in "
+                   f"{parts} requests each), round-robin over the graphs",
+                   total / elf, 1, 0, elf * 1e3, total,
+                   "served with continuous batching across sessions (fuse 32), closed loop")
+    out["closed_loop_alone"] = {"value": total / el, "requests_per_s": rate,
+                                "latency_ms": {"p50": pct(lat_c, 50), "p99": pct(lat_c, 99)}}
+    out["closed_loop_fused"] = {"value": total / elf, "requests_per_s": len(reqs) / elf,
+                                "mean_group": float(grp_cf.mean()),
+                                "latency_ms": {"p50": pct(lat_cf, 50), "p99": pct(lat_cf, 99)}}
+    out["poisson"] = {"arrival_rate_per_s": lam, "rate_rule": "0.8 x the closed-loop rate with fuse 1",
+                      "alone": {"value": total / el1, "latency_ms": {"p50": pct(lat1, 50), "p99": pct(lat1, 99)}},
+                      "fused": {"value": total / el2, "mean_group": float(grp2.mean()),
+                                "latency_ms": {"p50": pct(lat2, 50), "p99": pct(lat2, 99)}},
+                      "per": "request, arrival to result"}
+    out["tuning"] = tuning
+    out["roofline"] = None
+    return out
+
+
+# ---------------------------------------------------------------------------
 # paper-sweep
 # ---------------------------------------------------------------------------
 SWEEP_UPDATES = 10_000
@@ -789,8 +878,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat22-stream",
-                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "paper-sweep",
-                             "core-levels"])
+                    choices=["chunglu-1m", "rmat22-stream", "chunglu-pool512", "rmat-serve", "pool-serve",
+                             "paper-sweep", "core-levels"])
     ap.add_argument("--sweep-scales", default="15,16,17,18,19,20,21", help="paper-sweep: log2 n values")
     ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
     ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
@@ -823,7 +912,8 @@ def main():
             teardown(torch)
             return
     fn = {"chunglu-1m": bench_cl1m, "rmat22-stream": bench_rmat22, "chunglu-pool512": bench_pool512,
-          "rmat-serve": bench_serve, "paper-sweep": bench_sweep, "core-levels": bench_levels}
+          "rmat-serve": bench_serve, "pool-serve": bench_pool_serve, "paper-sweep": bench_sweep,
+          "core-levels": bench_levels}
     out = fn[args.workload](args, cm, torch)
     print(json.dumps(out), flush=True)
     teardown(torch)
