@@ -637,6 +637,56 @@ def bench_serve(args, cm, torch):
     out["closed_loop"] = {"requests_per_s": rate, "latency_ms": {"p50": pct(lat_c, 50), "p99": pct(lat_c, 99)}}
     out["tuning"] = tuning
     out["roofline"] = None
+    if args.checkpoints:
+        out["checkpoints"] = serve_checkpoints(cm, torch, serve, n, ds, dd, reqs, params, scfg, scale, nreq)
+    return out
+
+
+def serve_checkpoints(cm, torch, serve, n, ds, dd, reqs, params, scfg, scale, nreq):
+    """An untimed closed-loop pass that stops serving at the request counts
+    of the stored checkpoints (tests/golden/serve_checkpoints_r<scale>.json,
+    written on the host by `python -m oracle.serve_checkpoints` for the same
+    seeded stream: 21 evenly spaced counts), hashes the core vector there
+    (SHA-256 of the int32 cores, dead ids -1) and compares it, the id and
+    edge counts and the per-request statuses with the stored values."""
+    import hashlib
+    golden = os.path.join(ROOT, "tests", "golden", f"serve_checkpoints_r{scale}.json")
+    if not os.path.exists(golden):
+        return {"compared": False, "note": f"no stored checkpoints ({os.path.basename(golden)})"}
+    with open(golden) as f:
+        want = json.load(f)
+    if want["workload"] != {"scale": scale, "requests": nreq, "seed_tag": "bench-serve"}:
+        return {"compared": False, "note": "stored checkpoints are for another workload"}
+    marks = [c["after"] for c in want["checkpoints"]]
+
+    def digest(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+    g = cm.Graph(mode=cm.MODE_PERSISTENT, **params)
+    got, statuses = [], []
+    try:
+        g.load(n, ds, dd)
+        g.decompose()
+        done = 0
+        for mark in marks:
+            srv = serve.Server(g, **scfg)
+            res = serve.run_stream(srv, reqs[done:mark], None)
+            srv.stop()
+            statuses += [int(x.status) for x in res["stats"]]
+            c = g.cores()
+            got.append({"after": mark, "cores_sha256": digest(c), "n_ids": int(c.size), "m": g.num_edges()})
+            done = mark
+            log(f"checkpoint after {mark} requests")
+    finally:
+        g.close()
+    st = np.asarray(statuses, dtype=np.int32)
+    out = {"count": len(got), "statuses_sha256": hashlib.sha256(st.tobytes()).hexdigest(),
+           "failed_requests": int((st != 0).sum())}
+    match = [a["cores_sha256"] == b["cores_sha256"] and a["n_ids"] == b["n_ids"] and a["m"] == b["m"]
+             for a, b in zip(got, want["checkpoints"])]
+    out.update({"compared": True, "matched": int(sum(match)), "of": len(want["checkpoints"]),
+                "statuses_match": out["statuses_sha256"] == want["statuses_sha256"],
+                "first_mismatch_after": next((a["after"] for a, ok in zip(got, match) if not ok), None)})
+    assert all(match) and len(got) == len(want["checkpoints"]), f"served checkpoints differ from the oracle: {out}"
     return out
 
 
@@ -883,6 +933,8 @@ def main():
     ap.add_argument("--sweep-scales", default="15,16,17,18,19,20,21", help="paper-sweep: log2 n values")
     ap.add_argument("--scale", type=int, default=24, help="rmat-serve: R-MAT scale")
     ap.add_argument("--requests", type=int, default=10_000, help="rmat-serve: requests")
+    ap.add_argument("--checkpoints", action="store_true",
+                    help="rmat-serve: also compare 21 checkpoints of a served pass with the stored oracle states")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--tune", action="store_true",

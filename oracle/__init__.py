@@ -352,11 +352,42 @@ class DynamicGraph:
             return st, fb
         dead = np.unique(ids[err == 0])
         if dead.size:
-            k = self.keys
-            hit = np.isin(k >> 32, dead) | np.isin(k & 0xFFFFFFFF, dead)
-            self._remove_keys(k[hit])
+            self._remove_keys(self._incident_keys(dead))
             self.alive[dead] = 0
         return OK, fb
+
+    def _incident_keys(self, dead):
+        """Keys of the current edges with an endpoint in the sorted id array
+        `dead`: (lo, hi) keys are sorted by lo, so the edges whose lo is a dead
+        id are contiguous runs; for the hi side the initial keys keep an index
+        sorted by hi (built once, the initial keys never change) and the later
+        keys are few enough to test directly."""
+        dead = np.asarray(dead, dtype=np.int64)
+        mask = 0xFFFFFFFF
+
+        def runs(sorted_vals, lo_vals, hi_vals):
+            a = np.searchsorted(sorted_vals, lo_vals)
+            b = np.searchsorted(sorted_vals, hi_vals)
+            lens = b - a
+            if lens.sum() == 0:
+                return np.empty(0, dtype=np.int64)
+            start = np.repeat(a - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+            return start + np.arange(lens.sum())
+
+        parts = []
+        if self._base.size:
+            i = runs(self._base, dead << 32, (dead + 1) << 32)
+            parts.append(self._base[i[self._present[i]]])
+            if getattr(self, "_hi_order", None) is None:
+                self._hi_order = np.argsort(self._base & mask, kind="stable")
+                self._hi_sorted = (self._base & mask)[self._hi_order]
+            j = self._hi_order[runs(self._hi_sorted, dead, dead + 1)]
+            parts.append(self._base[j[self._present[j]]])
+        if self._added.size:
+            i = runs(self._added, dead << 32, (dead + 1) << 32)
+            parts.append(self._added[i])
+            parts.append(self._added[np.isin(self._added & mask, dead)])
+        return np.unique(np.concatenate(parts)) if parts else np.empty(0, dtype=np.int64)
 
 
 def all_graphs(n: int):

@@ -214,7 +214,7 @@ KArgs make_args(cm_graph *g) {
     require_ptrs(g, {g->ctl, g->bar, g->i64_scratch, g->u64_scratch}, "control block");
     if (g->loaded) {
         const DevGraph &d = g->g;
-        require_ptrs(g, {d.off, d.len, d.cap, d.nbr, d.core, d.mcd, d.stamp, d.chg, d.cd, d.dec,
+        require_ptrs(g, {d.off, d.len, d.cap, d.nbr, d.core, d.mcd, d.stamp.p, d.chg, d.cd.p, d.dec,
                          d.done, d.matched, d.claim, d.bmark, d.gain},
                      "graph arrays");
         const DevQueues &q = g->q;
@@ -295,19 +295,20 @@ void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
     DevGraph ng = g->g;
     ng.n_cap = n_cap;
     hipStream_t st = g->stream;
-    auto grow32 = [&](int32_t *&dst, int32_t *old, int32_t fillv) {
-        dev_alloc(g, &dst, n_cap);
-        HIPCHK(fill_i32(dst, fillv, n_cap, st));
+    auto grow32 = [&](int32_t *&dst, int32_t *old, int32_t fillv, int per = 1) {
+        dev_alloc(g, &dst, (int64_t)per * n_cap);
+        HIPCHK(fill_i32(dst, fillv, (int64_t)per * n_cap, st));
         if (old && n_keep > 0)
-            HIPCHK(hipMemcpyAsync(dst, old, sizeof(int32_t) * (size_t)n_keep, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(dst, old, sizeof(int32_t) * (size_t)per * (size_t)n_keep,
+                                  hipMemcpyDeviceToDevice, st));
     };
     grow32(ng.len, g->g.len, 0);
     grow32(ng.cap, g->g.cap, 0);
     grow32(ng.core, g->g.core, -1);
     grow32(ng.mcd, g->g.mcd, 0);
-    grow32(ng.stamp, g->g.stamp, 0);
+    grow32(ng.stamp.p, g->g.stamp.p, 0, 2);  // (stamp, cd) records: two words per id
     grow32(ng.chg, g->g.chg, 0);
-    grow32(ng.cd, g->g.cd, 0);
+    ng.cd.p = ng.stamp.p + 1;
     grow32(ng.dec, g->g.dec, 0);
     grow32(ng.done, g->g.done, 0);
     grow32((int32_t *&)ng.matched, (int32_t *)g->g.matched, 0);
@@ -325,7 +326,7 @@ void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
     HIPCHK(hipStreamSynchronize(st));
     DevGraph old = g->g;
     dev_free(old.len); dev_free(old.cap); dev_free(old.core); dev_free(old.mcd);
-    dev_free(old.stamp); dev_free(old.chg); dev_free(old.cd); dev_free(old.dec);
+    dev_free(old.stamp.p); dev_free(old.chg); dev_free(old.dec);
     dev_free(old.done); dev_free(old.matched); dev_free(old.bmark); dev_free(old.gain);
     dev_free(old.off); dev_free(old.claim);
     ng.nbr = g->g.nbr;
@@ -949,7 +950,7 @@ void require_ready(cm_graph *g, bool need_cores) {
 void release_all(cm_graph *g) {
     DevGraph &d = g->g;
     dev_free(d.off); dev_free(d.len); dev_free(d.cap); dev_free(d.nbr); dev_free(d.core);
-    dev_free(d.mcd); dev_free(d.stamp); dev_free(d.chg); dev_free(d.cd); dev_free(d.dec);
+    dev_free(d.mcd); dev_free(d.stamp.p); dev_free(d.chg); d.cd.p = nullptr; dev_free(d.dec);
     dev_free(d.done); dev_free(d.matched); dev_free(d.claim); dev_free(d.bmark); dev_free(d.gain);
     DevBatch &b = g->b;
     dev_free(b.err); dev_free(b.eu); dev_free(b.ev); dev_free(b.su); dev_free(b.sv);

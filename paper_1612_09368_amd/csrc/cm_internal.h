@@ -130,6 +130,15 @@ struct Bar {
     unsigned long long slice_ticks[16];  // [0]: ticks one workgroup's chain of local steps may run
 };
 
+// One of two int32 fields that share an 8-byte record per vertex (the
+// record array holds field 0 of vertex v at 2v and field 1 at 2v + 1), so
+// that a kernel touching both fields of a random vertex fetches one cache
+// line instead of two.
+struct Paired {
+    int32_t *p;  // &field of vertex 0
+    __device__ __forceinline__ int32_t &operator[](int64_t v) const { return p[2 * v]; }
+};
+
 // Per-vertex device arrays plus the adjacency pool.
 struct DevGraph {
     int32_t n_cap;       // allocated ids
@@ -141,9 +150,10 @@ struct DevGraph {
     int32_t *nbr;        // [pool_size]
     int32_t *core;       // [n_cap] core number; -1 = dead id
     int32_t *mcd;        // [n_cap] superior degree SD (neighbours with core >= own)
-    int32_t *stamp;      // [n_cap] iteration stamp: candidate (insert) / peeled (delete)
+    Paired stamp;        // [n_cap] iteration stamp: candidate (insert) / peeled (delete); paired with cd
     int32_t *chg;        // [n_cap] iteration stamp: core moved this iteration
-    int32_t *cd;         // [n_cap] insertion counter (CSD, then decremented)
+    Paired cd;           // [n_cap] insertion counter (CSD, then decremented); in the same record as
+                         // stamp, which every access to a candidate's counter checks first
     int32_t *dec;        // [n_cap] deletion peel counter (zero between iterations)
     int32_t *done;       // [n_cap] finished chunks of a long list (zero between uses)
     uint32_t *matched;   // [n_cap] selection round stamp

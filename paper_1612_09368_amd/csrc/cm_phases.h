@@ -1573,12 +1573,15 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         c->st_changed += ch;
         c->st_evicted += ins ? (unsigned long long)ld_rlx(&c->cand_count) - ch : ch;
     }
+    // Only a neighbour at the level the moved vertex crossed (its new core
+    // on insertion, its new core + 1 on deletion) may need a delta, so the
+    // moved-this-iteration stamp is gathered for those alone.
     auto nb = [&](int32_t w, int32_t cv) -> int32_t {
         if (w < 0) return 0;
-        int32_t cw = g.core[w];
-        if (g.chg[w] != ep) {
-            if (ins && cw == cv) atomicAdd(&g.mcd[w], 1);
-            if (!ins && cw == cv + 1) atomicSub(&g.mcd[w], 1);
+        const int32_t cw = g.core[w];
+        if (cw == (ins ? cv : cv + 1) && g.chg[w] != ep) {
+            if (ins) atomicAdd(&g.mcd[w], 1);
+            else atomicSub(&g.mcd[w], 1);
         }
         return cw >= cv ? 1 : 0;
     };
