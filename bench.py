@@ -132,6 +132,16 @@ def tuned_params(args, n, m, batch_sizes, sample):
     stored entry for the workload's signature, else the library defaults."""
     from paper_1612_09368_amd import autotune
     key = autotune.signature(n, m, batch_sizes)
+    params, info = _tuned_params(args, key, sample)
+    if args.set:
+        over = json.loads(args.set)
+        params = {**params, **over}
+        info = {**info, "params": params, "overrides": over}
+    return params, info
+
+
+def _tuned_params(args, key, sample):
+    from paper_1612_09368_amd import autotune
     if args.tune and sample is not None:
         t0 = time.time()
         best, bt, trials = autotune.tune(*sample(), sweeps=2, log=log, budget_s=args.tune_budget)
@@ -940,6 +950,9 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch parameters on the workload's sample first and store them")
     ap.add_argument("--tune-budget", type=float, default=300.0, help="seconds for --tune")
+    ap.add_argument("--set", default="",
+                    help='JSON object of launch parameters that override the tuned or default ones, '
+                         'e.g. \'{"expand_mode": 3}\'')
     ap.add_argument("--no-persistent", action="store_true",
                     help="chunglu-1m: time the plain form only")
     ap.add_argument("--copy-calibration", action="store_true",

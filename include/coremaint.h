@@ -103,7 +103,12 @@ typedef struct cm_config {
                                    visits its neighbours only once its CSD exceeds its core (the
                                    algorithm's pruning: two passes over an expanding list); 2 = it
                                    claims them while counting its CSD (one pass per list, a
-                                   larger visited set, same cores); 0 = default (2) */
+                                   larger visited set, same cores); 3 = as 2, and the pass also
+                                   records the candidate's neighbours at its level with SD above
+                                   it, the only ones whose counters its eviction (Algorithm 4)
+                                   lowers, so that an eviction walks those instead of the whole
+                                   list (one more int32 per adjacency slot of device memory);
+                                   0 = default (3; 2 with async_steps) */
     int32_t stamp_limit;        /* iteration stamps restart (the kernels clear the arrays that hold
                                    them, at an iteration boundary) before a stamp passes this;
                                    0 = default (2^28, also the largest allowed) */

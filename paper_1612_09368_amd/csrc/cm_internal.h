@@ -160,6 +160,15 @@ struct DevGraph {
     unsigned long long *claim;  // [n_cap] selection claim key (smaller wins)
     int32_t *bmark;      // [n_cap] batch stamp (validation scans, reservation)
     int32_t *gain;       // [n_cap] edges a batch adds to the list (zero between uses)
+    // Supporter lists of an insertion iteration (null when off): while the
+    // expansion counts a candidate's CSD it also writes the neighbours that
+    // are level-k candidates-to-be (core == k, SD > k), compacted, into the
+    // candidate's own slot range of `sub`; the eviction then walks those
+    // alone instead of the whole list.  A list of up to `large` slots keeps
+    // its count in slen; a longer one is compacted per chunk, each chunk's
+    // entries ending at a negative entry when fewer than the chunk's slots.
+    int32_t *sub;        // [pool_size] same slot ranges as nbr
+    int32_t *slen;       // [n_cap] supporters written for a list of up to `large` slots
 };
 
 // Edges of one batch after validation.
@@ -220,7 +229,7 @@ struct Tune {
     int32_t prune;       // expansion visits the neighbours of a candidate only once its CSD exceeds its
                          // core (Algorithm 3); 0 = claims them while counting the CSD
     int32_t stamp_limit; // iteration stamps restart (stamp arrays cleared) before passing this
-    int32_t pad;
+    int32_t sublists;    // the one-pass expansion records supporter lists for the eviction
 };
 
 // Chunk items of the expansion's claim pass (pruned expansion) carry this
@@ -355,6 +364,8 @@ struct ProgDesc {
 // Wave helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
+// lanes below this one
+__device__ __forceinline__ unsigned long long lanes_below() { return (1ull << lane()) - 1ull; }
 
 __device__ __forceinline__ int gwave() {
     return (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);

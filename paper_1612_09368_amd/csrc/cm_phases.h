@@ -1325,12 +1325,17 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     // vertex has visited every level-k neighbour its CSD counted.  Peeling
     // the visited set therefore still leaves exactly the risers.
     // Returns whether w supports a level-k vertex; *cl = w newly claimed.
-    auto csd_claim = [&](int32_t w, int32_t k, bool &cl) -> bool {
+    // *lk = w is a level-k supporter (core k, SD > k): a candidate this
+    // iteration, so the only kind of neighbour whose counter an eviction of
+    // the scanned vertex lowers.
+    auto csd_claim = [&](int32_t w, int32_t k, bool &cl, bool &lk) -> bool {
         cl = false;
+        lk = false;
         if (w < 0) return false;
         const int32_t cw = g.core[w];
         if (cw > k) return true;
         if (cw != k || g.mcd[w] <= k) return false;
+        lk = true;
         // already claimed: skip the atomic.  A plain load may return an
         // older stamp (then the atomic decides), never a later one.
         if (g.stamp[w] != ep && atomicExch(&g.stamp[w], ep) != ep) {
@@ -1339,6 +1344,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         }
         return true;
     };
+    const bool sl = a.t.sublists != 0;
     WaveBuf bq = wave_buf(0), be = wave_buf(1), bcand = wave_buf(2);
     auto push_next = [&](int32_t w, bool p) {
         push_vertex_wb(a, bq, a.q.fq[bn], &c->fq_tail[sn], a.q.fh[bn], &c->fh_tail[sn], w, p);
@@ -1369,14 +1375,28 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             }
         }
         const bool live = v >= 0 && !big;
-        int32_t pcd = 0;
-        flat_walk(g, v, live ? L : 0, [&](int32_t j, int32_t w, unsigned long long own) {
-            bool cl;
-            const bool sup = csd_claim(j >= 0 ? w : -1, __shfl(k, j < 0 ? 0 : j), cl);
+        int32_t pcd = 0, nlk = 0;  // CSD; supporters written to this lane's list
+        flat_walk_pos(g.nbr, g, v, live ? L : 0,
+                      [&](int32_t j, int32_t w, unsigned long long own, int64_t oj, int32_t lo) {
+            bool cl, lk;
+            const int32_t jj = j < 0 ? 0 : j;
+            const bool sup = csd_claim(j >= 0 ? w : -1, __shfl(k, jj), cl, lk);
             pcd += __popcll(__ballot(sup) & own);
+            if (sl) {
+                // compacted after the owner's earlier supporters and those
+                // of the lanes before this one that read the same list
+                const unsigned long long lkm = __ballot(lk);
+                const int32_t before = __shfl(nlk, jj);
+                if (lk) g.sub[oj + before + __popcll(lkm & lanes_below() & ~((1ull << lo) - 1ull))] = w;
+                nlk += __popcll(lkm & own);
+            }
             push_next(w, cl);
         });
-        if (live) { g.cd[v] = pcd; acc.scanned += L; }
+        if (live) {
+            g.cd[v] = pcd;
+            if (sl) g.slen[v] = nlk;
+            acc.scanned += L;
+        }
         push_cand(v, live);
         push_evict(v, live && pcd <= k);
     });
@@ -1384,12 +1404,19 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     // Long lists, chunk by chunk; the last chunk to finish has the CSD.
     for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
         int32_t k = g.core[v];
-        int32_t part = 0;
+        int32_t part = 0, nlk = 0;  // nlk: supporters written to this chunk (uniform)
+        int32_t *sp = sl ? g.sub + g.off[v] + lo : nullptr;
         wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) {
-            bool cl;
-            if (csd_claim(w, k, cl)) ++part;
+            bool cl, lk;
+            if (csd_claim(w, k, cl, lk)) ++part;
+            if (sl) {
+                const unsigned long long lkm = __ballot(lk);
+                if (lk) sp[nlk + __popcll(lkm & lanes_below())] = w;
+                nlk += __popcll(lkm);
+            }
             push_next(w, cl);
         });
+        if (sl && nlk < hi - lo && lane() == 0) sp[nlk] = -1;  // end of the chunk's supporters
         part = wave_sum(part);
         int last = 0;
         if (lane() == 0) {
@@ -1442,13 +1469,48 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     auto push_next = [&](int32_t w, bool p) {
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
-    acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
-                                [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
-    for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
-        int32_t k = g.core[x];
-        if (lane() == 0) acc.scanned += hi - lo;
-        wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
-    });
+    if (a.t.sublists) {
+        // Only the evicted vertex's supporter list: every entry is a level-k
+        // candidate of this iteration (the expansion scanned the evicted
+        // vertex, as every candidate, before the first eviction round), so
+        // the counter decrement needs no core or stamp test.
+        auto hit_sup = [&](int32_t w, int32_t k) -> bool {
+            if (w < 0 || g.cd[w] <= k) return false;
+            return atomicSub(&g.cd[w], 1) == k + 1;
+        };
+        for_batches(T, a.q.eq[bc], nq, [&](int32_t v) {
+            int32_t L = v >= 0 ? g.slen[v] : 0;
+            const int32_t len = v >= 0 ? g.len[v] : 0;
+            L = L < len ? L : len;  // never past the list, even on a count left from another iteration
+            const int32_t k = v >= 0 ? g.core[v] : 0;
+            acc.scanned += L;
+            flat_walk_pos(g.sub, g, v, L, [&](int32_t j, int32_t w, unsigned long long, int64_t, int32_t) {
+                push_next(w, hit_sup(w, __shfl(k, j < 0 ? 0 : j)));
+            });
+        });
+        // long lists: each chunk's supporters end at a negative entry
+        for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+            const int32_t k = g.core[x];
+            const int32_t *sp = g.sub + g.off[x];
+            for (int32_t s = lo; s < hi; s += WAVE) {
+                const int32_t i = s + lane();
+                int32_t w = i < hi ? sp[i] : -1;
+                const unsigned long long neg = __ballot(w < 0);
+                if (neg && lane() >= __ffsll((long long)neg) - 1) w = -1;
+                if (lane() == 0) acc.scanned += (neg ? __ffsll((long long)neg) - 1 : WAVE);
+                push_next(w, hit_sup(w, k));
+                if (neg) break;
+            }
+        });
+    } else {
+        acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
+                                    [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
+        for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+            int32_t k = g.core[x];
+            if (lane() == 0) acc.scanned += hi - lo;
+            wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { push_next(w, hit(w, k)); });
+        });
+    }
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
 }
 

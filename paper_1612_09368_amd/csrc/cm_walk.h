@@ -158,14 +158,19 @@ __device__ __forceinline__ void for_batches(const Team &T, const int32_t *q, int
 // and the number L_j of leading slots of its list to walk (0 for none).
 // The lists are laid end to end and every lane takes one slot per step, so
 // a batch of short and medium lists keeps all 64 lanes busy with 64 loads
-// in flight instead of walking the lists one after another.  f(j, w, own)
-// runs on every lane each step (it may use wave votes): j = the lane whose
-// list holds the slot this lane reads (-1 when it reads none), w = the slot's
-// entry (< 0 for a tombstone or none), own = the lanes that read a slot of
-// THIS lane's list in this step, so that popcount(ballot(p) & own) counts p
-// over this lane's slots.
+// in flight instead of walking the lists one after another.  f(j, w, own,
+// oj, lo) runs on every lane each step (it may use wave votes): j = the lane
+// whose list holds the slot this lane reads (-1 when it reads none), w = the
+// slot's entry of `arr` (< 0 for a tombstone or none), own = the lanes that
+// read a slot of THIS lane's list in this step, so that
+// popcount(ballot(p) & own) counts p over this lane's slots; oj = the first
+// slot of lane j's list and lo = the first lane of this step that reads
+// from lane j's list (lanes lo .. this lane - 1 read the slots just before
+// this one), for writing compacted per-list output.  arr is the adjacency
+// pool or an array with its slot ranges.
 template <class F>
-__device__ __forceinline__ void flat_walk(const DevGraph &g, int32_t v, int32_t L, F &&f) {
+__device__ __forceinline__ void flat_walk_pos(const int32_t *arr, const DevGraph &g, int32_t v, int32_t L,
+                                              F &&f) {
     int32_t incl = L;
     for (int o = 1; o < WAVE; o <<= 1) {
         const int32_t t = __shfl_up(incl, o);
@@ -185,14 +190,22 @@ __device__ __forceinline__ void flat_walk(const DevGraph &g, int32_t v, int32_t 
         const int32_t xj = __shfl(excl, j);
         const int64_t oj = __shfl(off, j);
         const bool has = e < total;
-        const int32_t w = has ? g.nbr[oj + (e - xj)] : -1;
+        const int32_t w = has ? arr[oj + (e - xj)] : -1;
         int32_t lo = excl - base, hi = incl - base;
         lo = lo < 0 ? 0 : (lo > WAVE ? WAVE : lo);
         hi = hi < 0 ? 0 : (hi > WAVE ? WAVE : hi);
         const unsigned long long own =
             hi > lo ? ((hi - lo == WAVE ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo) : 0ull;
-        f(has ? j : -1, w, own);
+        const int32_t loj = xj - base > 0 ? xj - base : 0;
+        f(has ? j : -1, w, own, oj, loj);
     }
+}
+// The same over the adjacency pool, without the position arguments.
+template <class F>
+__device__ __forceinline__ void flat_walk(const DevGraph &g, int32_t v, int32_t L, F &&f) {
+    flat_walk_pos(g.nbr, g, v, L, [&](int32_t j, int32_t w, unsigned long long own, int64_t, int32_t) {
+        f(j, w, own);
+    });
 }
 
 // Team-stride over a vertex queue visiting every slot of every list:

@@ -57,21 +57,30 @@ def check_state(g, ref, tag=""):
     assert g.num_edges() == ref.num_edges(), tag
 
 
-ASYNC = False
+FORMS = {
+    "rounds": {},
+    "async": {"async_steps": True},
+    "fullscan": {"expand_mode": 2},
+    "sublists": {"expand_mode": 3},
+}
+FORM = {}
 
 
-@pytest.fixture(autouse=True, params=[False, True], ids=["rounds", "async"])
+@pytest.fixture(autouse=True, params=list(FORMS))
 def _cascade_form(request):
-    """Every parity test runs with round-synchronous cascades and with
-    asynchronous (work-queue) cascades."""
-    global ASYNC
-    ASYNC = request.param
+    """Every parity test runs with round-synchronous cascades (default
+    expansion), with asynchronous (work-queue) cascades, and with the
+    one-pass expansion's eviction walking whole lists and walking the
+    supporter lists recorded by the expansion."""
+    global FORM
+    FORM = FORMS[request.param]
     yield
-    ASYNC = False
+    FORM = {}
 
 
 def new_graph(cm, n, s, d, dev, **kw):
-    kw.setdefault("async_steps", ASYNC)
+    for key, val in FORM.items():
+        kw.setdefault(key, val)
     g = cm.Graph(**kw)
     g.load(n, _t(s, dev), _t(d, dev))
     g.decompose()
