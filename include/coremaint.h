@@ -108,7 +108,12 @@ typedef struct cm_config {
                                    it, the only ones whose counters its eviction (Algorithm 4)
                                    lowers, so that an eviction walks those instead of the whole
                                    list (one more int32 per adjacency slot of device memory);
-                                   0 = default (3; 2 with async_steps) */
+                                   4 = as 3, and every list split into chunks keeps, per chunk,
+                                   the neighbours whose core was at least its owner's at its last
+                                   whole scan, which later expansions read instead of the chunk
+                                   (kept until a change could add a neighbour outside it; one
+                                   more int32 per adjacency slot); 0 = default (4; 2 with
+                                   async_steps) */
     int32_t stamp_limit;        /* iteration stamps restart (the kernels clear the arrays that hold
                                    them, at an iteration boundary) before a stamp passes this;
                                    0 = default (2^28, also the largest allowed) */

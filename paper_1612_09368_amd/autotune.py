@@ -7,8 +7,9 @@ length above which a list is split into chunks and the chunk length
 per wave), the list length walked by one lane in whole-graph passes and in
 the asynchronous cascade form (``small_degree``), the cascade form itself
 (``async_steps``), the expansion form (``expand_mode``: Algorithm 3's
-pruned two-pass walk, the one-pass walk, or the one-pass walk that records
-each candidate's level-k supporters for the eviction), the claim rounds of the partition, and the sizes up to
+pruned two-pass walk, the one-pass walk, the one-pass walk that records
+each candidate's level-k supporters for the eviction, and that form with
+up-lists kept for long lists), the claim rounds of the partition, and the sizes up to
 which a step runs inside one workgroup (``local_edges``, ``local_items``,
 ``local_work``).
 
@@ -44,13 +45,13 @@ SPACE = {
     "local_work": [1024, 4096, 16384],
     "local_edges": [2048, 8192, 32768],
     "async_steps": [0, 1],
-    "expand_mode": [1, 2, 3],
+    "expand_mode": [1, 2, 3, 4],
 }
 ORDER = ["async_steps", "expand_mode", "large_degree", "chunk", "small_degree", "blocks_per_cu", "partition_rounds",
          "local_items", "local_work", "local_edges"]
 DEFAULTS = {"blocks_per_cu": 1, "chunk": 256, "large_degree": 256, "small_degree": 4,
             "partition_rounds": 2, "local_items": 128, "local_work": 16384, "local_edges": 8192,
-            "async_steps": 0, "expand_mode": 3}
+            "async_steps": 0, "expand_mode": 4}
 
 DEFAULT_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 

@@ -315,6 +315,7 @@ void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
     grow32(ng.bmark, g->g.bmark, 0);
     grow32(ng.gain, g->g.gain, 0);
     if (g->tune.sublists) grow32(ng.slen, g->g.slen, 0);
+    if (g->tune.uplists) grow32(ng.ubl, g->g.ubl, -1);
     dev_alloc(g, &ng.off, n_cap);
     HIPCHK(fill_i64(ng.off, 0, n_cap, st));
     if (g->g.off && n_keep > 0)
@@ -329,9 +330,10 @@ void alloc_vertex_arrays(cm_graph *g, int32_t n_cap, int32_t n_keep) {
     dev_free(old.len); dev_free(old.cap); dev_free(old.core); dev_free(old.mcd);
     dev_free(old.stamp.p); dev_free(old.chg); dev_free(old.dec);
     dev_free(old.done); dev_free(old.matched); dev_free(old.bmark); dev_free(old.gain);
-    dev_free(old.off); dev_free(old.claim); dev_free(old.slen);
+    dev_free(old.off); dev_free(old.claim); dev_free(old.slen); dev_free(old.ubl);
     ng.nbr = g->g.nbr;
     ng.sub = g->g.sub;
+    ng.upl = g->g.upl;
     ng.pool_size = g->g.pool_size;
     ng.n_ids = g->g.n_ids;
     g->g = ng;
@@ -478,6 +480,11 @@ void repack(cm_graph *g, int64_t extra) {
         // supporter lists live only within an iteration: nothing to copy
         dev_free(g->g.sub);
         dev_alloc(g, &g->g.sub, pool);
+    }
+    if (g->tune.uplists) {
+        // every up-list is invalidated with the move (repack_finish)
+        dev_free(g->g.upl);
+        dev_alloc(g, &g->g.upl, pool);
     }
     HIPCHK(repack_copy(a, newoff, newnbr, g->grid_reg, st));
     HIPCHK(repack_finish(a, newoff, cnt, g->grid_reg, st));
@@ -959,7 +966,7 @@ void release_all(cm_graph *g) {
     dev_free(d.off); dev_free(d.len); dev_free(d.cap); dev_free(d.nbr); dev_free(d.core);
     dev_free(d.mcd); dev_free(d.stamp.p); dev_free(d.chg); d.cd.p = nullptr; dev_free(d.dec);
     dev_free(d.done); dev_free(d.matched); dev_free(d.claim); dev_free(d.bmark); dev_free(d.gain);
-    dev_free(d.sub); dev_free(d.slen);
+    dev_free(d.sub); dev_free(d.slen); dev_free(d.upl); dev_free(d.ubl);
     DevBatch &b = g->b;
     dev_free(b.err); dev_free(b.eu); dev_free(b.ev); dev_free(b.su); dev_free(b.sv);
     dev_free(b.hslot); dev_free(b.rem[0]); dev_free(b.rem[1]); dev_free(b.sel); dev_free(b.esel);
@@ -1054,12 +1061,13 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         g->tune.async_steps = g->cfg.async_steps ? 1 : 0;
         g->tune.single_edge = g->cfg.single_edge ? 1 : 0;
-        if (g->cfg.expand_mode < 0 || g->cfg.expand_mode > 3) {
-            g->err = "expand_mode must be 0, 1, 2 or 3";
+        if (g->cfg.expand_mode < 0 || g->cfg.expand_mode > 4) {
+            g->err = "expand_mode must be 0 .. 4";
             throw Fail{CM_E_ARG};
         }
         g->tune.prune = g->cfg.expand_mode == 1 ? 1 : 0;
-        g->tune.sublists = (g->cfg.expand_mode == 0 || g->cfg.expand_mode == 3) && !g->tune.async_steps ? 1 : 0;
+        g->tune.sublists = (g->cfg.expand_mode == 0 || g->cfg.expand_mode >= 3) && !g->tune.async_steps ? 1 : 0;
+        g->tune.uplists = (g->cfg.expand_mode == 0 || g->cfg.expand_mode == 4) && !g->tune.async_steps ? 1 : 0;
         if (g->cfg.stamp_limit < 0) {
             g->err = "stamp_limit must be >= 0";
             throw Fail{CM_E_ARG};
@@ -1214,6 +1222,7 @@ int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const i
             if (g->cfg.edge_capacity_hint > pool) pool = g->cfg.edge_capacity_hint;
             dev_alloc(g, &g->g.nbr, pool);
             if (g->tune.sublists) dev_alloc(g, &g->g.sub, pool);
+            if (g->tune.uplists) dev_alloc(g, &g->g.upl, pool);
             g->g.pool_size = pool;
             HIPCHK(fill_i32(g->g.len, 0, g->g.n_cap, st));
             if (m > 0) HIPCHK(scatter_edges(ds, dd, m, g->g.off, g->g.len, g->g.nbr, st));

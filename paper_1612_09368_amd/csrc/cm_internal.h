@@ -169,6 +169,19 @@ struct DevGraph {
     // entries ending at a negative entry when fewer than the chunk's slots.
     int32_t *sub;        // [pool_size] same slot ranges as nbr
     int32_t *slen;       // [n_cap] supporters written for a list of up to `large` slots
+    // Up-lists of long lists (null when off), kept across iterations and
+    // batches: per chunk of a list split into chunks, the neighbours whose
+    // core was at least the owner's when the list was last scanned whole,
+    // compacted into the chunk's slot range of `upl` (a negative entry ends
+    // a chunk holding fewer than its slots).  ubl = the list length at that
+    // scan (slots from ubl on were appended later and are read from nbr), or
+    // -1 when the up-list is invalid.  Every change that could put a
+    // neighbour into the owner's up-set outside it -- a neighbour rising to
+    // the owner's core, the owner's core falling, an edge of the owner
+    // deleted, the list moved -- makes it invalid; a neighbour that falls, or
+    // the owner rising, only leaves extra entries, which every reader tests.
+    int32_t *upl;        // [pool_size] same slot ranges as nbr
+    int32_t *ubl;        // [n_cap]
 };
 
 // Edges of one batch after validation.
@@ -230,6 +243,8 @@ struct Tune {
                          // core (Algorithm 3); 0 = claims them while counting the CSD
     int32_t stamp_limit; // iteration stamps restart (stamp arrays cleared) before passing this
     int32_t sublists;    // the one-pass expansion records supporter lists for the eviction
+    int32_t uplists;     // long lists keep up-lists (scanned by the one-pass expansion)
+    int32_t pad;
 };
 
 // Chunk items of the expansion's claim pass (pruned expansion) carry this

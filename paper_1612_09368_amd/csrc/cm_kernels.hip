@@ -270,6 +270,7 @@ __global__ void k_repack_finish(KArgs a, const int64_t *newoff, const int32_t *c
         bool live = v < g.n_ids && g.core[v] != -1;
         g.off[v] = newoff[v];
         g.len[v] = live ? cnt[v] : 0;
+        if (g.ubl) g.ubl[v] = -1;  // lists moved
     }
 }
 
@@ -300,6 +301,9 @@ __global__ void k_export(KArgs a, int32_t *xs, int32_t *ys, int64_t cap, unsigne
 __global__ void k_dec_prep(KArgs a) {
     const DevGraph &g = a.g;
     Ctl *c = a.ctl;
+    // cores are recomputed from scratch: no up-list survives
+    if (g.ubl)
+        for (int32_t v = gtid(); v < g.n_cap; v += gthreads()) g.ubl[v] = -1;
     for_all_vertices(
         grid_team(), g.n_ids, g, a.t.small_deg,
         [&](int32_t v, int32_t L) {

@@ -288,6 +288,7 @@ __device__ __forceinline__ void res_copy(const KArgs &a, const Team &T) {
             atomicAdd(&a.ctl->garbage, (unsigned long long)a.g.cap[x]);
             a.g.off[x] = a.b.reloc_off[j];
             a.g.cap[x] = a.b.reloc_cap[j];
+            if (a.t.uplists) a.g.ubl[x] = -1;  // the up-list stayed at the old slots
         }
     }
 }
@@ -600,6 +601,10 @@ __device__ __forceinline__ void apply_edge_delete(const KArgs &a, const Iter &it
         int32_t k = cu < cv ? cu : cv;
         a.g.nbr[a.b.su[i]] = TOMB;
         a.g.nbr[a.b.sv[i]] = TOMB;
+        if (a.t.uplists) {  // an up-list may hold the deleted neighbour
+            a.g.ubl[u] = -1;
+            a.g.ubl[v] = -1;
+        }
         if (cu == k) {
             int32_t m = atomicSub(&a.g.mcd[u], 1) - 1;
             if (m < k) { a.g.stamp[u] = it.ep; pu = true; }
@@ -936,6 +941,7 @@ __device__ __forceinline__ void star_apply_delete(const KArgs &a, const Iter &it
                 ++ne;
                 const int32_t x = su ? u : v;  // the leaving star (never both: they claim each other)
                 q = su ? v : u;
+                if (a.t.uplists) g.ubl[q] = -1;
                 const int32_t cq = g.core[q], cx = g.core[x];
                 if (cq <= cx) {
                     int32_t m = atomicSub(&g.mcd[q], 1) - 1;
@@ -1228,14 +1234,7 @@ __device__ __forceinline__ void expand_round_pruned(const KArgs &a, const Iter &
         const int32_t L = v >= 0 ? g.len[v] : 0;
         const int32_t k = v >= 0 ? g.core[v] : 0;
         const bool big = L > a.t.large_deg;
-        if (big) {
-            const int nch = nchunks(L, a.t.chunk);
-            const int base = atomicAdd(&c->fh_tail[sn], nch);
-            for (int q = 0; q < nch; ++q) {
-                if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
-                else atomicOr(&c->overflow, 1);
-            }
-        }
+        push_chunks(a, a.q.fh[bn], &c->fh_tail[sn], v, big ? nchunks(L, a.t.chunk) : 0);
         const bool live = v >= 0 && !big;
         int32_t pcd = 0;
         flat_walk(g, v, live ? L : 0, [&](int32_t j, int32_t w, unsigned long long own) {
@@ -1328,11 +1327,12 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     // *lk = w is a level-k supporter (core k, SD > k): a candidate this
     // iteration, so the only kind of neighbour whose counter an eviction of
     // the scanned vertex lowers.
-    auto csd_claim = [&](int32_t w, int32_t k, bool &cl, bool &lk) -> bool {
+    auto csd_claim = [&](int32_t w, int32_t k, bool &cl, bool &lk, bool *up = nullptr) -> bool {
         cl = false;
         lk = false;
         if (w < 0) return false;
         const int32_t cw = g.core[w];
+        if (up) *up = cw >= k;
         if (cw > k) return true;
         if (cw != k || g.mcd[w] <= k) return false;
         lk = true;
@@ -1366,14 +1366,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         const int32_t L = v >= 0 ? g.len[v] : 0;
         const int32_t k = v >= 0 ? g.core[v] : 0;
         const bool big = L > a.t.large_deg;
-        if (big) {
-            const int nch = nchunks(L, a.t.chunk);
-            const int base = atomicAdd(&c->fh_tail[sn], nch);
-            for (int q = 0; q < nch; ++q) {
-                if (base + q < a.q.hcap) a.q.fh[bn][base + q] = chunk_item(v, q);
-                else atomicOr(&c->overflow, 1);
-            }
-        }
+        push_chunks(a, a.q.fh[bn], &c->fh_tail[sn], v, big ? nchunks(L, a.t.chunk) : 0);
         const bool live = v >= 0 && !big;
         int32_t pcd = 0, nlk = 0;  // CSD; supporters written to this lane's list
         flat_walk_pos(g.nbr, g, v, live ? L : 0,
@@ -1402,25 +1395,66 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     });
 
     // Long lists, chunk by chunk; the last chunk to finish has the CSD.
+    const bool ul = a.t.uplists != 0;
     for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
         int32_t k = g.core[v];
         int32_t part = 0, nlk = 0;  // nlk: supporters written to this chunk (uniform)
-        int32_t *sp = sl ? g.sub + g.off[v] + lo : nullptr;
-        wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) {
+        const int64_t o = g.off[v];
+        int32_t *sp = sl ? g.sub + o + lo : nullptr;
+        // every chunk of v reads the same ubl: it changes only when the last
+        // chunk of v (all others finished) completes a build
+        const int32_t ub = ul ? g.ubl[v] : -1;
+        int32_t seen = 0;  // entries read (uniform)
+        auto body = [&](int32_t w, bool *up) {
             bool cl, lk;
-            if (csd_claim(w, k, cl, lk)) ++part;
+            if (csd_claim(w, k, cl, lk, up)) ++part;
             if (sl) {
                 const unsigned long long lkm = __ballot(lk);
                 if (lk) sp[nlk + __popcll(lkm & lanes_below())] = w;
                 nlk += __popcll(lkm);
             }
             push_next(w, cl);
-        });
+        };
+        if (ub >= 0) {
+            // the chunk's up-list (built from slots [lo, min(hi, ub))), then
+            // the slots appended since
+            const int32_t hb = hi < ub ? hi : ub;
+            const int32_t *up = g.upl + o + lo;
+            for (int32_t s = 0; lo + s < hb; s += WAVE) {
+                const int32_t i = s + lane();
+                int32_t w = lo + i < hb ? up[i] : -1;
+                const unsigned long long neg = __ballot(w < 0);
+                if (neg && lane() >= __ffsll((long long)neg) - 1) w = -1;
+                seen += neg ? __ffsll((long long)neg) - 1 : WAVE;
+                body(w, nullptr);
+                if (neg) break;
+            }
+            const int32_t ab = lo > ub ? lo : ub;
+            if (ab < hi) {
+                seen += hi - ab;
+                wave_walk(g, v, ab, hi, [&](int32_t w, int32_t) { body(w, nullptr); });
+            }
+        } else {
+            // whole chunk; with up-lists on, write this chunk's up-list
+            int32_t nup = 0;
+            int32_t *uw = ul ? g.upl + o + lo : nullptr;
+            seen = hi - lo;
+            wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) {
+                bool up = false;
+                body(w, &up);
+                if (ul) {
+                    const unsigned long long um = __ballot(up);
+                    if (up) uw[nup + __popcll(um & lanes_below())] = w;
+                    nup += __popcll(um);
+                }
+            });
+            if (ul && nup < hi - lo && lane() == 0) uw[nup] = -1;
+        }
         if (sl && nlk < hi - lo && lane() == 0) sp[nlk] = -1;  // end of the chunk's supporters
         part = wave_sum(part);
         int last = 0;
         if (lane() == 0) {
-            acc.scanned += hi - lo;
+            acc.scanned += seen;
             atomicAdd(&g.cd[v], part);
             wave_drain();  // the partial sum lands before this chunk counts as done
             last = atomicAdd(&g.done[v], 1) == nch - 1;
@@ -1431,6 +1465,8 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             if (lane() == 0) {
                 g.done[v] = 0;
                 tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // every chunk wrote its up-list before counting itself done
+                if (ul && ub < 0) g.ubl[v] = g.len[v];
             }
             tot = __shfl(tot, 0);
             push_cand(v, lane() == 0);
@@ -1599,6 +1635,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
             g.core[v] = nc;
             g.chg[v] = it.ep;
             g.mcd[v] = 0;
+            if (a.t.uplists) g.ubl[v] = -1;  // neighbours at the new core join the up-set
             if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, true, it.ep, v, nc);
         }
         const int32_t nh = qlen(&c->chh_count, a.q.hcap);
@@ -1614,6 +1651,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
                 g.core[v] = nc;
                 g.chg[v] = it.ep;
                 g.mcd[v] = 0;
+                if (a.t.uplists) g.ubl[v] = -1;
             }
             if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, first, it.ep, v, nc);
             count_agg(&c->changed_count, first);
@@ -1642,8 +1680,13 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         if (w < 0) return 0;
         const int32_t cw = g.core[w];
         if (cw == (ins ? cv : cv + 1) && g.chg[w] != ep) {
-            if (ins) atomicAdd(&g.mcd[w], 1);
-            else atomicSub(&g.mcd[w], 1);
+            if (ins) {
+                atomicAdd(&g.mcd[w], 1);
+                // the moved vertex rose to w's core: it joins w's up-set
+                if (a.t.uplists) g.ubl[w] = -1;
+            } else {
+                atomicSub(&g.mcd[w], 1);
+            }
         }
         return cw >= cv ? 1 : 0;
     };

@@ -12,23 +12,65 @@
 
 namespace cm {
 
+// Append the chunk items (w, 0), .., (w, nch - 1) of every lane (nch = 0
+// for none) to a chunk queue with one tail atomic per wave: returning
+// atomics on one word serialise (about 11 ns each), and one per long list
+// bound the rounds that push many of them.  The wave writes the items
+// together, lane i taking items i, i + 64, ..., so a very long list does
+// not serialise on its own lane.  A wave with inactive lanes (the last pass
+// of a strided loop) pushes lane by lane instead.
+__device__ __forceinline__ void push_chunks(const KArgs &a, int64_t *hq, int32_t *htail, int32_t w,
+                                            int32_t nch) {
+    if (__ballot(nch > 0) == 0ull) return;
+    if (__ballot(1) != ~0ull) {
+        if (nch > 0) {
+            const int32_t base = atomicAdd(htail, nch);
+            for (int32_t c = 0; c < nch; ++c) {
+                if (base + c < a.q.hcap) hq[base + c] = chunk_item(w, c);
+                else atomicOr(&a.ctl->overflow, 1);
+            }
+        }
+        return;
+    }
+    int32_t incl = nch;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o);
+        if (lane() >= o) incl += t;
+    }
+    const int32_t total = __shfl(incl, WAVE - 1);
+    const int32_t excl = incl - nch;
+    int32_t base = 0;
+    if (lane() == 0) base = atomicAdd(htail, total);
+    base = __shfl(base, 0);
+    for (int32_t e0 = 0; e0 < total; e0 += WAVE) {
+        const int32_t e = e0 + lane();
+        // owner of item e: the last lane whose items start at or before e
+        // (a lane with no items shares its start with the next lane, so
+        // the owner of a valid item always has items)
+        int32_t j = 0;
+        for (int s = WAVE / 2; s > 0; s >>= 1) {
+            const int32_t xc = __shfl(excl, j + s);
+            if (xc <= e) j += s;
+        }
+        const int32_t xj = __shfl(excl, j);
+        const int32_t wj = __shfl(w, j);
+        if (e < total) {
+            const int32_t pos = base + e;
+            if (pos < a.q.hcap) hq[pos] = chunk_item(wj, e - xj);
+            else atomicOr(&a.ctl->overflow, 1);
+        }
+    }
+}
+
 // Route a pushed vertex: short/medium lists to the vertex queue, long lists
 // as `nchunks` items to the chunk queue.  All lanes may call it (pred
-// selects the pushing lanes); a long list costs one atomic on its lane.
+// selects the pushing lanes).
 __device__ __forceinline__ void push_vertex(const KArgs &a, int32_t *vq, int32_t *vtail, int64_t *hq,
                                             int32_t *htail, int32_t w, bool pred) {
     int32_t L = pred ? a.g.len[w] : 0;
     bool big = pred && L > a.t.large_deg;
     push_agg<int32_t>(vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
-    if (big) {
-        int nch = nchunks(L, a.t.chunk);
-        int base = atomicAdd(htail, nch);
-        for (int c = 0; c < nch; ++c) {
-            int pos = base + c;
-            if (pos < a.q.hcap) hq[pos] = chunk_item(w, c);
-            else atomicOr(&a.ctl->overflow, 1);
-        }
-    }
+    push_chunks(a, hq, htail, w, big ? nchunks(L, a.t.chunk) : 0);
 }
 
 // Per-wave push buffers in LDS.  A queue tail is one word that every wave
@@ -69,22 +111,14 @@ __device__ __forceinline__ void wb_push(WaveBuf &b, int32_t *q, int32_t qcap, in
     b.n += __popcll(m);
     if (b.n >= WAVE) wb_flush(b, q, qcap, tail, overflow);
 }
-// push_vertex through a wave buffer (long lists still go straight to the
-// chunk queue, one atomic per list).
+// push_vertex through a wave buffer (long lists go straight to the chunk
+// queue, one atomic per wave).
 __device__ __forceinline__ void push_vertex_wb(const KArgs &a, WaveBuf &b, int32_t *vq, int32_t *vtail,
                                                int64_t *hq, int32_t *htail, int32_t w, bool pred) {
     const int32_t L = pred ? a.g.len[w] : 0;
     const bool big = pred && L > a.t.large_deg;
     wb_push(b, vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
-    if (big) {
-        const int nch = nchunks(L, a.t.chunk);
-        const int base = atomicAdd(htail, nch);
-        for (int c = 0; c < nch; ++c) {
-            const int pos = base + c;
-            if (pos < a.q.hcap) hq[pos] = chunk_item(w, c);
-            else atomicOr(&a.ctl->overflow, 1);
-        }
-    }
+    push_chunks(a, hq, htail, w, big ? nchunks(L, a.t.chunk) : 0);
 }
 
 // Team-stride over the implicit identity list 0..n-1 (whole-graph passes).

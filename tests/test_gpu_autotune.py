@@ -42,7 +42,7 @@ def test_tune_store_and_reuse(cm, oracle_mod, tmp_path):
     dev = torch.device("cuda:0")
     ds, dd, dx, dy = (torch.from_numpy(z).to(dev) for z in (s, d, xs, ys))
     kinds = np.asarray(kinds, np.int32)
-    space = {"expand_mode": [1, 2], "partition_rounds": [1, 2, 3], "large_degree": [64, 256],
+    space = {"expand_mode": [1, 2, 4], "partition_rounds": [1, 2, 3], "large_degree": [64, 256],
              "chunk": [128, 256]}
     best, best_t, trials = autotune.tune(n, ds, dd, kinds, offs, dx, dy, space=space,
                                          order=list(space), sweeps=1)

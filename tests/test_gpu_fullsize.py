@@ -106,14 +106,21 @@ def load(cm, w, torch, **kw):
     return g
 
 
-def test_rmat22_stream_batched(cm, rmat22):
+# launch parameters on top of the tuned ones: as timed, and each other
+# expansion form that keeps state across batches
+STREAM_FORMS = {"tuned": {}, "sublists": {"expand_mode": 3}}
+
+
+@pytest.mark.parametrize("form", list(STREAM_FORMS))
+def test_rmat22_stream_batched(cm, rmat22, form):
     """The whole stream through cm_run_batches in the persistent form
     replayed from a hipGraph (as timed), GROUP batches per call, the full
     core and SD vectors compared after every call."""
     import torch
     w = rmat22
     dev = torch.device("cuda:0")
-    g = load(cm, w, torch, mode=cm.MODE_PERSISTENT, use_graph=True, timing=True, **bench_params(cm, w))
+    params = {**bench_params(cm, w), **STREAM_FORMS[form]}
+    g = load(cm, w, torch, mode=cm.MODE_PERSISTENT, use_graph=True, timing=True, **params)
     try:
         compare(g, w, 0, "decomposition")
         dx = torch.from_numpy(w["xs"]).to(dev)

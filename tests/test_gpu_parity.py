@@ -69,9 +69,9 @@ FORM = {}
 @pytest.fixture(autouse=True, params=list(FORMS))
 def _cascade_form(request):
     """Every parity test runs with round-synchronous cascades (default
-    expansion), with asynchronous (work-queue) cascades, and with the
-    one-pass expansion's eviction walking whole lists and walking the
-    supporter lists recorded by the expansion."""
+    expansion: supporter lists for the eviction and up-lists of long lists),
+    with asynchronous (work-queue) cascades, with the one-pass expansion
+    alone, and with supporter lists but no up-lists."""
     global FORM
     FORM = FORMS[request.param]
     yield
