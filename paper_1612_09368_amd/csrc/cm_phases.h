@@ -570,11 +570,11 @@ __device__ __forceinline__ void apply_edge_insert(const KArgs &a, const Iter &it
         else atomicOr(&c->overflow, 2);
         if (cu == k) {
             int32_t m = atomicAdd(&a.g.mcd[u], 1) + 1;
-            if (m > k) { a.g.stamp[u] = it.ep; a.g.cd[u] = 0; ru = true; }
+            if (m > k) { a.g.stamp[u] = it.ep; a.g.cd[u] = 0; if (a.t.sublists) a.g.slen[u] = 0; ru = true; }
         }
         if (cv == k) {
             int32_t m = atomicAdd(&a.g.mcd[v], 1) + 1;
-            if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; rv = true; }
+            if (m > k) { a.g.stamp[v] = it.ep; a.g.cd[v] = 0; if (a.t.sublists) a.g.slen[v] = 0; rv = true; }
         }
     }
     // Roots enter the vertex queue whatever their length: other threads may
@@ -887,7 +887,12 @@ __device__ __forceinline__ void star_apply_insert(const KArgs &a, const Iter &it
                 ++ne;
                 if (cw <= hk) {  // constrained: v supports w's rise
                     int32_t m = atomicAdd(&g.mcd[w], 1) + 1;
-                    if (m > cw) { g.stamp[w] = it.ep; g.cd[w] = 0; root = true; }
+                    if (m > cw) {
+                        g.stamp[w] = it.ep;
+                        g.cd[w] = 0;
+                        if (a.t.sublists) g.slen[w] = 0;
+                        root = true;
+                    }
                 }
             }
             if (a.t.async_steps) apush(a, 0, aq_item(AQ_V, w, 0), root);
@@ -900,7 +905,11 @@ __device__ __forceinline__ void star_apply_insert(const KArgs &a, const Iter &it
             g.core[v] = hk;
             g.mcd[v] = sd;
             g.dec[v] = 0;
-            if (rv) { g.stamp[v] = it.ep; g.cd[v] = 0; }
+            if (rv) {
+                g.stamp[v] = it.ep;
+                g.cd[v] = 0;
+                if (a.t.sublists) g.slen[v] = 0;
+            }
             atomicAdd(&c->st_selected, (unsigned long long)ne);
         }
         if (a.t.async_steps) apush(a, 0, aq_item(AQ_V, v, 0), rv && lane() == 0);
@@ -1199,6 +1208,16 @@ __device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, Acc &
 // more than k supporters, so CSD > k, and each connected piece of risers
 // contains a root), and every level-k neighbour counted by an expanding
 // vertex is visited, so peeling it by "cd <= k" leaves exactly the risers.
+// Supporter runs longer than one wave step are walked as items of one wave
+// step each.  A wave of the flattened walk takes up to 64 runs, so longer
+// runs could load one wave with far more than the others; and a hub's
+// supporters sit in one run, so wider items would leave a few waves walking
+// it step after step while the round waits.
+__device__ __forceinline__ int32_t evict_large(const KArgs &a) {
+    return a.t.large_deg < WAVE ? a.t.large_deg : WAVE;
+}
+__device__ __forceinline__ int32_t evict_chunk(const KArgs &a) { return a.t.chunk < WAVE ? a.t.chunk : WAVE; }
+
 __device__ __forceinline__ void expand_round_pruned(const KArgs &a, const Iter &it, int r, const Team &T,
                                                     Acc &acc) {
     Ctl *c = a.ctl;
@@ -1340,6 +1359,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         // older stamp (then the atomic decides), never a later one.
         if (g.stamp[w] != ep && atomicExch(&g.stamp[w], ep) != ep) {
             g.cd[w] = 0;
+            if (a.t.sublists) g.slen[w] = 0;
             cl = true;
         }
         return true;
@@ -1349,8 +1369,11 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     auto push_next = [&](int32_t w, bool p) {
         push_vertex_wb(a, bq, a.q.fq[bn], &c->fq_tail[sn], a.q.fh[bn], &c->fh_tail[sn], w, p);
     };
-    auto push_evict = [&](int32_t v, bool p) {
-        push_vertex_wb(a, be, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v, p);
+    // an evicted vertex's walk is its supporter run (sublists) or its list
+    auto push_evict = [&](int32_t v, bool p, int32_t nsup) {
+        push_vertex_wb_len(a, be, a.q.eq[0], &c->eq_tail[0], a.q.eh[0], &c->eh_tail[0], v,
+                           p ? (sl ? nsup : g.len[v]) : 0, p, sl ? evict_large(a) : a.t.large_deg,
+                           sl ? evict_chunk(a) : a.t.chunk);
     };
     auto push_cand = [&](int32_t v, bool p) {
         wb_push(bcand, a.q.cand, a.q.vcap, &c->cand_count, v, p, &c->overflow);
@@ -1391,27 +1414,44 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             acc.scanned += L;
         }
         push_cand(v, live);
-        push_evict(v, live && pcd <= k);
+        push_evict(v, live && pcd <= k, nlk);
     });
 
     // Long lists, chunk by chunk; the last chunk to finish has the CSD.
     const bool ul = a.t.uplists != 0;
     for_chunks(T, a.q.fh[bc], nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t nch) {
         int32_t k = g.core[v];
-        int32_t part = 0, nlk = 0;  // nlk: supporters written to this chunk (uniform)
+        int32_t part = 0;
         const int64_t o = g.off[v];
-        int32_t *sp = sl ? g.sub + o + lo : nullptr;
         // every chunk of v reads the same ubl: it changes only when the last
         // chunk of v (all others finished) completes a build
         const int32_t ub = ul ? g.ubl[v] : -1;
         int32_t seen = 0;  // entries read (uniform)
+        // the chunks of v append to one supporter run: slen[v] (zero since v
+        // was claimed) hands out the slots.  A chunk collects its supporters
+        // in the wave's LDS buffer and reserves them with one atomic at its
+        // end; a chunk longer than the buffer reserves per step.
+        constexpr int SUPBUF = 256;
+        __shared__ int32_t lds_sup[COOP_THREADS / WAVE][SUPBUF];
+        int32_t *sbuf = lds_sup[threadIdx.x / WAVE];
+        const bool bufok = a.t.chunk <= SUPBUF;
+        int32_t ns = 0;  // supporters held in sbuf (uniform)
         auto body = [&](int32_t w, bool *up) {
             bool cl, lk;
             if (csd_claim(w, k, cl, lk, up)) ++part;
             if (sl) {
                 const unsigned long long lkm = __ballot(lk);
-                if (lk) sp[nlk + __popcll(lkm & lanes_below())] = w;
-                nlk += __popcll(lkm);
+                if (lkm) {
+                    if (bufok) {
+                        if (lk) sbuf[ns + __popcll(lkm & lanes_below())] = w;
+                        ns += __popcll(lkm);
+                    } else {
+                        int32_t b = 0;
+                        if (lane() == 0) b = atomicAdd(&g.slen[v], __popcll(lkm));
+                        b = __shfl(b, 0);
+                        if (lk) g.sub[o + b + __popcll(lkm & lanes_below())] = w;
+                    }
+                }
             }
             push_next(w, cl);
         };
@@ -1450,7 +1490,14 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             });
             if (ul && nup < hi - lo && lane() == 0) uw[nup] = -1;
         }
-        if (sl && nlk < hi - lo && lane() == 0) sp[nlk] = -1;  // end of the chunk's supporters
+        if (ns > 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // other lanes' LDS writes first
+            int32_t b = 0;
+            if (lane() == 0) b = atomicAdd(&g.slen[v], ns);
+            b = __shfl(b, 0);
+            for (int32_t i = lane(); i < ns; i += WAVE) g.sub[o + b + i] = sbuf[i];
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // reads done before reuse
+        }
         part = wave_sum(part);
         int last = 0;
         if (lane() == 0) {
@@ -1461,16 +1508,19 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
         }
         last = __shfl(last, 0);
         if (last) {
-            int32_t tot = 0;
+            int32_t tot = 0, nsup = 0;
             if (lane() == 0) {
                 g.done[v] = 0;
                 tot = __hip_atomic_load(&g.cd[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // every chunk wrote its up-list before counting itself done
+                // every chunk added its supporters (and wrote its up-list)
+                // before counting itself done
+                if (sl) nsup = __hip_atomic_load(&g.slen[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (ul && ub < 0) g.ubl[v] = g.len[v];
             }
             tot = __shfl(tot, 0);
+            nsup = __shfl(nsup, 0);
             push_cand(v, lane() == 0);
-            push_evict(v, lane() == 0 && tot <= k);
+            push_evict(v, lane() == 0 && tot <= k, nsup);
         }
     });
     wb_flush(bq, a.q.fq[bn], a.q.vcap, &c->fq_tail[sn], &c->overflow);
@@ -1506,13 +1556,18 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, p);
     };
     if (a.t.sublists) {
-        // Only the evicted vertex's supporter list: every entry is a level-k
+        // Only the evicted vertex's supporter run: every entry is a level-k
         // candidate of this iteration (the expansion scanned the evicted
         // vertex, as every candidate, before the first eviction round), so
-        // the counter decrement needs no core or stamp test.
+        // the counter decrement needs no core or stamp test.  A newly
+        // evicted vertex is queued by the length of its run.
         auto hit_sup = [&](int32_t w, int32_t k) -> bool {
             if (w < 0 || g.cd[w] <= k) return false;
             return atomicSub(&g.cd[w], 1) == k + 1;
+        };
+        auto push_ev = [&](int32_t w, bool p) {
+            push_vertex_wb_len(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w,
+                               p ? g.slen[w] : 0, p, evict_large(a), evict_chunk(a));
         };
         for_batches(T, a.q.eq[bc], nq, [&](int32_t v) {
             int32_t L = v >= 0 ? g.slen[v] : 0;
@@ -1521,23 +1576,28 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
             const int32_t k = v >= 0 ? g.core[v] : 0;
             acc.scanned += L;
             flat_walk_pos(g.sub, g, v, L, [&](int32_t j, int32_t w, unsigned long long, int64_t, int32_t) {
-                push_next(w, hit_sup(w, __shfl(k, j < 0 ? 0 : j)));
+                push_ev(w, hit_sup(w, __shfl(k, j < 0 ? 0 : j)));
             });
         });
-        // long lists: each chunk's supporters end at a negative entry
-        for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
+        // long supporter runs, item by item
+        const int32_t ech = evict_chunk(a);
+        for (int32_t jx = T.wave(); jx < nh; jx += T.nwaves()) {
+            const int64_t item = a.q.eh[bc][jx];
+            const int32_t x = item_v(item);
+            int32_t L = g.slen[x];
+            const int32_t len = g.len[x];
+            L = L < len ? L : len;
+            const int32_t lo = item_c(item) * ech;
+            const int32_t hi = lo + ech < L ? lo + ech : L;
             const int32_t k = g.core[x];
             const int32_t *sp = g.sub + g.off[x];
+            if (lane() == 0 && hi > lo) acc.scanned += hi - lo;
             for (int32_t s = lo; s < hi; s += WAVE) {
                 const int32_t i = s + lane();
-                int32_t w = i < hi ? sp[i] : -1;
-                const unsigned long long neg = __ballot(w < 0);
-                if (neg && lane() >= __ffsll((long long)neg) - 1) w = -1;
-                if (lane() == 0) acc.scanned += (neg ? __ffsll((long long)neg) - 1 : WAVE);
-                push_next(w, hit_sup(w, k));
-                if (neg) break;
+                const int32_t w = i < hi ? sp[i] : -1;
+                push_ev(w, hit_sup(w, k));
             }
-        });
+        }
     } else {
         acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg,
                                     [&](int32_t w, int32_t k) { push_next(w, hit(w, k)); });
@@ -1748,9 +1808,9 @@ __device__ __forceinline__ long long block_sum64(long long v) {
 // List entries a frontier step would walk: the lengths of its vertex items
 // plus a full chunk per chunk item (computed by one workgroup).
 __device__ __forceinline__ long long queue_work(const KArgs &a, const Team &T, const int32_t *q, int32_t n,
-                                                int32_t nchk, int walks) {
+                                                int32_t nchk, int walks, const int32_t *lens) {
     long long w = 0;
-    for (int32_t i = T.rank; i < n; i += T.size) w += a.g.len[q[i]];
+    for (int32_t i = T.rank; i < n; i += T.size) w += lens[q[i]];
     w = block_sum64(w) * walks;
     return w + (long long)nchk * a.t.chunk;
 }
@@ -1763,14 +1823,17 @@ __device__ __forceinline__ bool block_local_ok(const KArgs &a, const Iter &it, c
     long long w = 0;
     switch (pc.step) {
     case S_EXPAND:
-        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap), 1);
+        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap), 1,
+                       a.g.len);
         break;
     case S_EVICT:
     case S_PEEL:
-        w = queue_work(a, T, a.q.eq[pc.r & 1], qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap), 1);
+        // an eviction walks supporter runs when they are kept
+        w = queue_work(a, T, a.q.eq[pc.r & 1], qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap), 1,
+                       pc.step == S_EVICT && a.t.sublists ? a.g.slen : a.g.len);
         break;
     case S_MCD:
-        w = queue_work(a, T, a.q.chg, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap), 1);
+        w = queue_work(a, T, a.q.chg, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap), 1, a.g.len);
         break;
     default: return true;
     }
@@ -2620,7 +2683,7 @@ __device__ __forceinline__ bool dec_block_local_ok(const KArgs &a, const DState 
     Ctl *c = a.ctl;
     const int s = st.f % 3;
     long long w = queue_work(a, T, a.q.eq[st.f & 1], qlen(&c->eq_tail[s], a.q.vcap),
-                             qlen(&c->eh_tail[s], a.q.hcap), 1);
+                             qlen(&c->eh_tail[s], a.q.hcap), 1, a.g.len);
     return w <= a.t.local_work;
 }
 

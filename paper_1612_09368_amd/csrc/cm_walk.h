@@ -112,13 +112,20 @@ __device__ __forceinline__ void wb_push(WaveBuf &b, int32_t *q, int32_t qcap, in
     if (b.n >= WAVE) wb_flush(b, q, qcap, tail, overflow);
 }
 // push_vertex through a wave buffer (long lists go straight to the chunk
-// queue, one atomic per wave).
+// queue, one atomic per wave), for a walk of L entries of w (the caller
+// gives L: the list length, or the length of another per-vertex run) and
+// runs longer than `large` split into items of `chunk` entries.
+__device__ __forceinline__ void push_vertex_wb_len(const KArgs &a, WaveBuf &b, int32_t *vq, int32_t *vtail,
+                                                   int64_t *hq, int32_t *htail, int32_t w, int32_t L,
+                                                   bool pred, int32_t large, int32_t chunk) {
+    const bool big = pred && L > large;
+    wb_push(b, vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
+    push_chunks(a, hq, htail, w, big ? nchunks(L, chunk) : 0);
+}
+// ... for a walk of w's whole list
 __device__ __forceinline__ void push_vertex_wb(const KArgs &a, WaveBuf &b, int32_t *vq, int32_t *vtail,
                                                int64_t *hq, int32_t *htail, int32_t w, bool pred) {
-    const int32_t L = pred ? a.g.len[w] : 0;
-    const bool big = pred && L > a.t.large_deg;
-    wb_push(b, vq, a.q.vcap, vtail, w, pred && !big, &a.ctl->overflow);
-    push_chunks(a, hq, htail, w, big ? nchunks(L, a.t.chunk) : 0);
+    push_vertex_wb_len(a, b, vq, vtail, hq, htail, w, pred ? a.g.len[w] : 0, pred, a.t.large_deg, a.t.chunk);
 }
 
 // Team-stride over the implicit identity list 0..n-1 (whole-graph passes).
