@@ -43,6 +43,32 @@ __device__ __forceinline__ int32_t qlen(const int32_t *tail, int32_t cap) {
     return n < cap ? n : cap;
 }
 
+// The queue tails and counts that the iteration's step machine reads at every
+// step boundary sit in the control block's first 128 bytes.  One wave-wide
+// load after the barrier (or workgroup barrier) that ends a step brings them
+// all, lane i holding word i, instead of a chain of single agent-scope loads
+// (each a round trip past the L1) in the step decision and the next step.
+constexpr int SNAP_WORDS = 32;
+static_assert(offsetof(Ctl, rem_count) == 0 && offsetof(Ctl, changed_count) + 4 <= 4 * SNAP_WORDS,
+              "step-boundary counters must fit the snapshot");
+struct Snap {
+    int32_t v;  // word lane() of the control block (lanes >= SNAP_WORDS: 0)
+};
+// Every lane of the wave must call it.
+__device__ __forceinline__ Snap take_snap(const Ctl *c) {
+    const int32_t *w = reinterpret_cast<const int32_t *>(c);
+    return Snap{lane() < SNAP_WORDS ? ld_rlx(w + lane()) : 0};
+}
+// The snapshot's value of field f (a word of the first 128 bytes of *c).
+// It reads another lane's register: every lane of the wave must call it.
+__device__ __forceinline__ int32_t snap_word(const Snap &s, const Ctl *c, const int32_t *f) {
+    return __shfl(s.v, (int)(f - reinterpret_cast<const int32_t *>(c)));
+}
+__device__ __forceinline__ int32_t sqlen(const Snap &s, const Ctl *c, const int32_t *tail, int32_t cap) {
+    const int32_t n = snap_word(s, c, tail);
+    return n < cap ? n : cap;
+}
+
 // Debug log entry (a, b, c) for every active lane with pred set (one
 // atomic per wave).
 __device__ __forceinline__ void dbg_put(int32_t *buf, unsigned long long *cnt, int64_t cap, bool pred, int32_t x,
@@ -349,6 +375,7 @@ struct Iter {
     int32_t n_r;   // its length
     int32_t ins;   // 1 = insertion batch, 0 = deletion batch
     StarCtx sc;
+    Snap sn;       // control counters as the last step left them
 };
 
 enum StepKind : int32_t { S_CLAIM = 0, S_SELECT, S_APPLY, S_EXPAND, S_EVICT, S_PEEL, S_CORE, S_MCD, S_DONE };
@@ -1224,8 +1251,8 @@ __device__ __forceinline__ void expand_round_pruned(const KArgs &a, const Iter &
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3;
     const int bc = r & 1, bn = bc ^ 1;
-    const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
-    const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
+    const int32_t nq = sqlen(it.sn, c, &c->fq_tail[sc], a.q.vcap);
+    const int32_t nh = sqlen(it.sn, c, &c->fh_tail[sc], a.q.hcap);
     const int32_t ep = it.ep;
     auto support = [&](int32_t w, int32_t k) -> bool {
         if (w < 0) return false;
@@ -1327,8 +1354,8 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
     const int bc = r & 1, bn = bc ^ 1;
-    const int32_t nq = qlen(&c->fq_tail[sc], a.q.vcap);
-    const int32_t nh = qlen(&c->fh_tail[sc], a.q.hcap);
+    const int32_t nq = sqlen(it.sn, c, &c->fq_tail[sc], a.q.vcap);
+    const int32_t nh = sqlen(it.sn, c, &c->fh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->fq_tail[sx] = 0; c->fh_tail[sx] = 0;
         c->st_rounds += 1;
@@ -1456,24 +1483,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
             push_next(w, cl);
         };
         if (ub >= 0) {
-            // the chunk's up-list (built from slots [lo, min(hi, ub))), then
-            // the slots appended since
-            const int32_t hb = hi < ub ? hi : ub;
-            const int32_t *up = g.upl + o + lo;
-            for (int32_t s = 0; lo + s < hb; s += WAVE) {
-                const int32_t i = s + lane();
-                int32_t w = lo + i < hb ? up[i] : -1;
-                const unsigned long long neg = __ballot(w < 0);
-                if (neg && lane() >= __ffsll((long long)neg) - 1) w = -1;
-                seen += neg ? __ffsll((long long)neg) - 1 : WAVE;
-                body(w, nullptr);
-                if (neg) break;
-            }
-            const int32_t ab = lo > ub ? lo : ub;
-            if (ab < hi) {
-                seen += hi - ab;
-                wave_walk(g, v, ab, hi, [&](int32_t w, int32_t) { body(w, nullptr); });
-            }
+            seen = walk_chunk_up(g, v, lo, hi, ub, [&](int32_t w) { body(w, nullptr); });
         } else {
             // whole chunk; with up-lists on, write this chunk's up-list
             int32_t nup = 0;
@@ -1536,8 +1546,8 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
     const int bc = r & 1, bn = bc ^ 1;
-    const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
-    const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
+    const int32_t nq = sqlen(it.sn, c, &c->eq_tail[sc], a.q.vcap);
+    const int32_t nh = sqlen(it.sn, c, &c->eh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
         c->st_rounds += 1;
@@ -1620,8 +1630,8 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
     const DevGraph &g = a.g;
     const int sc = r % 3, sn = (r + 1) % 3, sx = (r + 2) % 3;
     const int bc = r & 1, bn = bc ^ 1;
-    const int32_t nq = qlen(&c->eq_tail[sc], a.q.vcap);
-    const int32_t nh = qlen(&c->eh_tail[sc], a.q.hcap);
+    const int32_t nq = sqlen(it.sn, c, &c->eq_tail[sc], a.q.vcap);
+    const int32_t nh = sqlen(it.sn, c, &c->eh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
         c->st_rounds += 1;
@@ -1641,10 +1651,15 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         push_vertex_wb(a, bchg, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
     acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
+    // a long list with a valid up-list is read through it: the neighbours at
+    // the peeled vertex's core are all in its up-set
     for_chunks(T, a.q.eh[bc], nh, g, a.t.chunk, [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
         int32_t k = g.core[x];
-        if (lane() == 0) acc.scanned += hi - lo;
-        wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
+        const int32_t ub = a.t.uplists ? g.ubl[x] : -1;
+        int32_t seen = hi - lo;
+        if (ub >= 0) seen = walk_chunk_up(g, x, lo, hi, ub, [&](int32_t w) { body(w, k); });
+        else wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
+        if (lane() == 0) acc.scanned += seen;
     });
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
     wb_flush(bt, a.q.touched, a.q.vcap, &c->touched_count, &c->overflow);
@@ -1658,7 +1673,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
     const DevGraph &g = a.g;
     long long &cdeg = acc.cdeg, &edeg = acc.edeg, &hdeg = acc.hdeg;  // list entries of the method's sets
     if (it.ins) {
-        const int32_t n = qlen(&c->cand_count, a.q.vcap);
+        const int32_t n = sqlen(it.sn, c, &c->cand_count, a.q.vcap);
         if (T.lead()) {
             c->st_candidates += (unsigned long long)n;
             c->st_icand += (unsigned long long)n;
@@ -1681,8 +1696,8 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
             push_vertex(a, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, v, up);
         }
     } else {
-        const int32_t n = qlen(&c->chg_count, a.q.vcap);
-        const int32_t nt = qlen(&c->touched_count, a.q.vcap);
+        const int32_t n = sqlen(it.sn, c, &c->chg_count, a.q.vcap);
+        const int32_t nt = sqlen(it.sn, c, &c->touched_count, a.q.vcap);
         if (T.lead()) {
             atomicAdd(&c->changed_count, n);
             c->st_candidates += (unsigned long long)nt;
@@ -1698,7 +1713,7 @@ __device__ __forceinline__ void apply_core(const KArgs &a, const Iter &it, const
             if (a.t.uplists) g.ubl[v] = -1;  // neighbours at the new core join the up-set
             if (a.dl.chg) dbg_put(a.dl.chg, &a.dl.n[1], a.dl.cap, true, it.ep, v, nc);
         }
-        const int32_t nh = qlen(&c->chh_count, a.q.hcap);
+        const int32_t nh = sqlen(it.sn, c, &c->chh_count, a.q.hcap);
         for (int32_t idx = T.rank; idx < nh; idx += T.size) {
             int64_t item = a.q.chh[idx];
             bool first = item_c(item) == 0;
@@ -1728,10 +1743,12 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
     const bool ins = it.ins != 0;
+    // snap_word reads another lane: every lane takes part
+    const unsigned long long ch = (unsigned long long)snap_word(it.sn, c, &c->changed_count);
+    const unsigned long long ncand = (unsigned long long)snap_word(it.sn, c, &c->cand_count);
     if (T.lead()) {
-        unsigned long long ch = (unsigned long long)ld_rlx(&c->changed_count);
         c->st_changed += ch;
-        c->st_evicted += ins ? (unsigned long long)ld_rlx(&c->cand_count) - ch : ch;
+        c->st_evicted += ins ? ncand - ch : ch;
     }
     // Only a neighbour at the level the moved vertex crossed (its new core
     // on insertion, its new core + 1 on deletion) may need a delta, so the
@@ -1750,7 +1767,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         }
         return cw >= cv ? 1 : 0;
     };
-    const int32_t n = qlen(&c->chg_count, a.q.vcap);
+    const int32_t n = sqlen(it.sn, c, &c->chg_count, a.q.vcap);
     for_batches(T, a.q.chg, n, [&](int32_t v) {
         const int32_t L = v >= 0 ? g.len[v] : 0;
         const int32_t cv = v >= 0 ? g.core[v] : 0;
@@ -1773,7 +1790,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
             if (lane() == 0) { g.mcd[vv] = tot; acc.scanned += LL; }
         }
     });
-    const int32_t nh = qlen(&c->chh_count, a.q.hcap);
+    const int32_t nh = sqlen(it.sn, c, &c->chh_count, a.q.hcap);
     for_chunks(T, a.q.chh, nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
         int32_t cv = g.core[v];
         int32_t cnt = 0;
@@ -1823,17 +1840,17 @@ __device__ __forceinline__ bool block_local_ok(const KArgs &a, const Iter &it, c
     long long w = 0;
     switch (pc.step) {
     case S_EXPAND:
-        w = queue_work(a, T, a.q.fq[pc.r & 1], qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap), 1,
+        w = queue_work(a, T, a.q.fq[pc.r & 1], sqlen(it.sn, c, &c->fq_tail[s], a.q.vcap), sqlen(it.sn, c, &c->fh_tail[s], a.q.hcap), 1,
                        a.g.len);
         break;
     case S_EVICT:
     case S_PEEL:
         // an eviction walks supporter runs when they are kept
-        w = queue_work(a, T, a.q.eq[pc.r & 1], qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap), 1,
+        w = queue_work(a, T, a.q.eq[pc.r & 1], sqlen(it.sn, c, &c->eq_tail[s], a.q.vcap), sqlen(it.sn, c, &c->eh_tail[s], a.q.hcap), 1,
                        pc.step == S_EVICT && a.t.sublists ? a.g.slen : a.g.len);
         break;
     case S_MCD:
-        w = queue_work(a, T, a.q.chg, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap), 1, a.g.len);
+        w = queue_work(a, T, a.q.chg, sqlen(it.sn, c, &c->chg_count, a.q.vcap), sqlen(it.sn, c, &c->chh_count, a.q.hcap), 1, a.g.len);
         break;
     default: return true;
     }
@@ -1846,13 +1863,18 @@ __device__ __forceinline__ int64_t step_work(const KArgs &a, const Iter &it, con
     switch (pc.step) {
     case S_CLAIM:
     case S_SELECT: return it.n_r;
-    case S_APPLY: return qlen(&c->sel_count, a.b.cap);
+    case S_APPLY: return sqlen(it.sn, c, &c->sel_count, a.b.cap);
     case S_EXPAND:
-        return frontier_work(a, qlen(&c->fq_tail[s], a.q.vcap), qlen(&c->fh_tail[s], a.q.hcap));
+        return frontier_work(a, sqlen(it.sn, c, &c->fq_tail[s], a.q.vcap), sqlen(it.sn, c, &c->fh_tail[s], a.q.hcap));
     case S_EVICT:
-    case S_PEEL: return frontier_work(a, qlen(&c->eq_tail[s], a.q.vcap), qlen(&c->eh_tail[s], a.q.hcap));
-    case S_CORE: return it.ins ? qlen(&c->cand_count, a.q.vcap) : qlen(&c->chg_count, a.q.vcap);
-    case S_MCD: return frontier_work(a, qlen(&c->chg_count, a.q.vcap), qlen(&c->chh_count, a.q.hcap));
+    case S_PEEL: return frontier_work(a, sqlen(it.sn, c, &c->eq_tail[s], a.q.vcap), sqlen(it.sn, c, &c->eh_tail[s], a.q.hcap));
+    case S_CORE:
+        // a deletion's core step also clears the peel counters of every
+        // touched vertex
+        return it.ins ? sqlen(it.sn, c, &c->cand_count, a.q.vcap)
+                      : (int64_t)sqlen(it.sn, c, &c->chg_count, a.q.vcap) + sqlen(it.sn, c, &c->chh_count, a.q.hcap) +
+                            sqlen(it.sn, c, &c->touched_count, a.q.vcap);
+    case S_MCD: return frontier_work(a, sqlen(it.sn, c, &c->chg_count, a.q.vcap), sqlen(it.sn, c, &c->chh_count, a.q.hcap));
     default: return 0;
     }
 }
@@ -1864,13 +1886,13 @@ __device__ __forceinline__ bool step_is_local(const KArgs &a, const Iter &it, co
     return work <= a.t.local_items;
 }
 
-__device__ __forceinline__ bool slot_empty_f(const KArgs &a, int s) {
+__device__ __forceinline__ bool slot_empty_f(const KArgs &a, const Iter &it, int s) {
     Ctl *c = a.ctl;
-    return ld_rlx(&c->fq_tail[s]) + ld_rlx(&c->fh_tail[s]) == 0;
+    return snap_word(it.sn, c, &c->fq_tail[s]) + snap_word(it.sn, c, &c->fh_tail[s]) == 0;
 }
-__device__ __forceinline__ bool slot_empty_e(const KArgs &a, int s) {
+__device__ __forceinline__ bool slot_empty_e(const KArgs &a, const Iter &it, int s) {
     Ctl *c = a.ctl;
-    return ld_rlx(&c->eq_tail[s]) + ld_rlx(&c->eh_tail[s]) == 0;
+    return snap_word(it.sn, c, &c->eq_tail[s]) + snap_word(it.sn, c, &c->eh_tail[s]) == 0;
 }
 
 // Step that follows pc (reads the counters pc's step published).
@@ -1882,10 +1904,10 @@ __device__ __forceinline__ PC after_apply(const KArgs &a, const Iter &it) {
         return it.ins ? PC{S_EVICT, 0} : PC{S_PEEL, 0};
     }
     if (it.ins) {
-        if (!slot_empty_f(a, 0)) return PC{S_EXPAND, 0};
-        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
+        if (!slot_empty_f(a, it, 0)) return PC{S_EXPAND, 0};
+        return slot_empty_e(a, it, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
     }
-    return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
+    return slot_empty_e(a, it, 0) ? PC{S_CORE, 0} : PC{S_PEEL, 0};
 }
 
 __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &pc) {
@@ -1898,14 +1920,14 @@ __device__ __forceinline__ PC next_pc(const KArgs &a, const Iter &it, const PC &
     case S_APPLY: return after_apply(a, it);
     case S_EXPAND:
         if (a.t.async_steps) return ld_rlx(&a.ctl->aq_tail[1]) > 0 ? PC{S_EVICT, 0} : PC{S_CORE, 0};
-        if (!slot_empty_f(a, (pc.r + 1) % 3)) return PC{S_EXPAND, pc.r + 1};
-        return slot_empty_e(a, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
+        if (!slot_empty_f(a, it, (pc.r + 1) % 3)) return PC{S_EXPAND, pc.r + 1};
+        return slot_empty_e(a, it, 0) ? PC{S_CORE, 0} : PC{S_EVICT, 0};
     case S_EVICT:
         if (a.t.async_steps) return PC{S_CORE, 0};
-        return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_EVICT, pc.r + 1};
+        return slot_empty_e(a, it, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_EVICT, pc.r + 1};
     case S_PEEL:
         if (a.t.async_steps) return PC{S_CORE, 0};
-        return slot_empty_e(a, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_PEEL, pc.r + 1};
+        return slot_empty_e(a, it, (pc.r + 1) % 3) ? PC{S_CORE, 0} : PC{S_PEEL, pc.r + 1};
     case S_CORE: return PC{S_MCD, 0};
     default: return PC{S_DONE, 0};
     }
@@ -1986,7 +2008,8 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
         Iter it;
         it.ep = ep + 1;
         it.cur = it.ep & 1;
-        it.n_r = qlen(&c->rem_count[it.cur], a.b.cap);
+        it.sn = take_snap(c);
+        it.n_r = sqlen(it.sn, c, &c->rem_count[it.cur], a.b.cap);
         it.ins = ins;
         it.sc = sc;
         if (it.n_r == 0 || bar_aborted(a.bar)) break;
@@ -2000,6 +2023,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                 run_step(a, it, pc, grid_team(), acc);
                 if (gtid() == 0) c->st_grid_steps += 1;
                 gbar(a.bar);
+                it.sn = take_snap(c);
                 ph_stop(c, pc.step, t0);
                 pc = next_pc(a, it, pc);
             } else {
@@ -2014,6 +2038,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                         run_step(a, it, pc, T, acc);
                         if (threadIdx.x == 0) c->st_local_steps += 1;
                         __syncthreads();
+                        it.sn = take_snap(c);
                         pc = next_pc(a, it, pc);
                         if (pc.step == S_DONE) break;
                         work = step_work(a, it, pc);
@@ -2030,6 +2055,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                     }
                 }
                 gbar(a.bar);
+                it.sn = take_snap(c);
                 pc.step = ld_rlx(&c->ipub[slot][0]);
                 pc.r = ld_rlx(&c->ipub[slot][1]);
                 force = ld_rlx(&c->ipub[slot][2]) != 0;

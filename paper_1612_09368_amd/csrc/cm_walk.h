@@ -177,6 +177,34 @@ __device__ __forceinline__ void wave_walk(const DevGraph &g, int32_t v, int32_t 
     }
 }
 
+// Wave walk of chunk [lo, hi) of v through v's up-list (ub = ubl[v] >= 0):
+// the chunk's compacted up-list entries, built from slots [lo, min(hi, ub))
+// and ending at a negative entry when fewer, then the slots appended since
+// (from ub on).  f(w) runs on every lane each step (w < 0: none).  Returns
+// the entries read (uniform).
+template <class F>
+__device__ __forceinline__ int32_t walk_chunk_up(const DevGraph &g, int32_t v, int32_t lo, int32_t hi,
+                                                 int32_t ub, F &&f) {
+    int32_t seen = 0;
+    const int32_t hb = hi < ub ? hi : ub;
+    const int32_t *up = g.upl + g.off[v] + lo;
+    for (int32_t s = 0; lo + s < hb; s += WAVE) {
+        const int32_t i = s + lane();
+        int32_t w = lo + i < hb ? up[i] : -1;
+        const unsigned long long neg = __ballot(w < 0);
+        if (neg && lane() >= __ffsll((long long)neg) - 1) w = -1;
+        seen += neg ? __ffsll((long long)neg) - 1 : WAVE;
+        f(w);
+        if (neg) break;
+    }
+    const int32_t ab = lo > ub ? lo : ub;
+    if (ab < hi) {
+        seen += hi - ab;
+        wave_walk(g, v, ab, hi, [&](int32_t w, int32_t) { f(w); });
+    }
+    return seen;
+}
+
 // Team-stride over a vertex queue in batches of up to 64 entries per wave:
 // a wave takes `per` consecutive entries, per = ceil(n / waves) capped at
 // 64, so a queue shorter than 64 entries per wave is spread over every wave
