@@ -395,14 +395,53 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // Phase clock: global thread 0 reads the device wall clock before a phase
-// and adds the elapsed ticks after the barrier that ends it.
+// and adds the elapsed ticks after the barrier that ends it -- in its
+// workgroup's LDS, since a read-modify-write of the control block there
+// would be a memory round trip right after each barrier on the wave every
+// other one then waits for; ph_flush adds the sums to the control block at
+// the end of a batch or launch.
+// Slots after the phase ticks and counts: the cascade rounds and the grid
+// and local steps of the batch (kept there for the same reason).
+constexpr int PH_ROUNDS = 2 * PH_SLOTS, PH_GSTEPS = 2 * PH_SLOTS + 1, PH_LSTEPS = 2 * PH_SLOTS + 2;
+constexpr int PH_WORDS = 2 * PH_SLOTS + 3;
+__device__ __forceinline__ unsigned long long *ph_lds() {
+    __shared__ unsigned long long acc[PH_WORDS];  // ticks, counts, steps (workgroup 0 only)
+    return acc;
+}
+// At the start of a launch, before its first barrier (which orders the
+// clearing before thread 0's first use).
+__device__ __forceinline__ void ph_init() {
+    if (blockIdx.x == 0 && threadIdx.x < PH_WORDS) ph_lds()[threadIdx.x] = 0ull;
+}
+// Count one event of slot i (PH_ROUNDS .. PH_LSTEPS); global thread 0 only.
+__device__ __forceinline__ void ph_count(int i) {
+    if (gtid() == 0) ph_lds()[i] += 1ull;
+}
 __device__ __forceinline__ unsigned long long ph_start() {
     return gtid() == 0 ? (unsigned long long)wall_clock64() : 0ull;
 }
-__device__ __forceinline__ void ph_stop(Ctl *c, int slot, unsigned long long t0) {
+__device__ __forceinline__ void ph_stop(Ctl *, int slot, unsigned long long t0) {
     if (gtid() == 0) {
-        c->ph_ticks[slot] += (unsigned long long)wall_clock64() - t0;
-        c->ph_count[slot] += 1;
+        unsigned long long *p = ph_lds();
+        p[slot] += (unsigned long long)wall_clock64() - t0;
+        p[PH_SLOTS + slot] += 1;
+    }
+}
+__device__ __forceinline__ void ph_flush(Ctl *c) {
+    if (gtid() == 0) {
+        unsigned long long *p = ph_lds();
+        for (int i = 0; i < PH_SLOTS; ++i) {
+            if (p[PH_SLOTS + i]) {
+                c->ph_ticks[i] += p[i];
+                c->ph_count[i] += p[PH_SLOTS + i];
+                p[i] = 0ull;
+                p[PH_SLOTS + i] = 0ull;
+            }
+        }
+        c->st_rounds += p[PH_ROUNDS];
+        c->st_grid_steps += p[PH_GSTEPS];
+        c->st_local_steps += p[PH_LSTEPS];
+        p[PH_ROUNDS] = p[PH_GSTEPS] = p[PH_LSTEPS] = 0ull;
     }
 }
 
@@ -572,6 +611,7 @@ __device__ __forceinline__ void gbar_any(Bar *b) {
 // gbar_any; afterwards each workgroup knows how many workgroups share its
 // XCC and how many XCCs are in use.
 __device__ __forceinline__ void gbar_setup(Bar *b) {
+    ph_init();
     unsigned *info = bar_info();
     unsigned long long ep = 0;
     unsigned x = 0;

@@ -23,8 +23,10 @@ __device__ __forceinline__ void flush_stat(unsigned long long *dst, long long v)
 
 // Per-thread statistics of a launch, kept in registers and summed into the
 // control block at the end of a batch: adjacency entries read by the
-// traversal phases, and the list entries of the method's sets (insertion
-// candidates, evicted / peeled vertices, vertices whose core moved).
+// traversal phases, the list entries of the method's sets (insertion
+// candidates, evicted / peeled vertices, vertices whose core moved).  Every
+// thread must call flush_acc; it also flushes the phase clock and step
+// counts of global thread 0.
 struct Acc {
     long long scanned, cdeg, edeg, hdeg;
 };
@@ -33,6 +35,7 @@ __device__ __forceinline__ void flush_acc(Ctl *c, Acc &acc) {
     flush_stat(&c->st_cdeg, acc.cdeg);
     flush_stat(&c->st_edeg, acc.edeg);
     flush_stat(&c->st_hdeg, acc.hdeg);
+    ph_flush(c);
     acc = Acc{};
 }
 
@@ -1010,7 +1013,7 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, Acc
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
-    if (gtid() == 0) c->st_rounds += 1;
+    ph_count(PH_ROUNDS);
     auto claim = [&](int32_t w, int32_t k) -> bool {
         if (w < 0) return false;
         if (g.core[w] != k || g.mcd[w] <= k) return false;
@@ -1129,7 +1132,7 @@ __device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, Acc 
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
-    if (gtid() == 0) c->st_rounds += 1;
+    ph_count(PH_ROUNDS);
     auto hit = [&](int32_t w, int32_t k) -> bool {
         if (w < 0 || g.core[w] != k || ld_rlx(&g.stamp[w]) != ep) return false;
         // a counter already at or below k has crossed once: w is evicted
@@ -1177,7 +1180,7 @@ __device__ __forceinline__ void peel_async(const KArgs &a, const Iter &it, Acc &
     Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
-    if (gtid() == 0) c->st_rounds += 1;
+    ph_count(PH_ROUNDS);
     auto body = [&](int32_t w, int32_t k) {
         bool first = false, fire = false;
         if (w >= 0 && g.core[w] == k && ld_rlx(&g.stamp[w]) != ep) {
@@ -1358,7 +1361,7 @@ __device__ __forceinline__ void expand_round(const KArgs &a, const Iter &it, int
     const int32_t nh = sqlen(it.sn, c, &c->fh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->fq_tail[sx] = 0; c->fh_tail[sx] = 0;
-        c->st_rounds += 1;
+        ph_count(PH_ROUNDS);
     }
     const int32_t ep = it.ep;
 
@@ -1550,7 +1553,7 @@ __device__ __forceinline__ void evict_round(const KArgs &a, const Iter &it, int 
     const int32_t nh = sqlen(it.sn, c, &c->eh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
-        c->st_rounds += 1;
+        ph_count(PH_ROUNDS);
     }
     const int32_t ep = it.ep;
     auto hit = [&](int32_t w, int32_t k) -> bool {
@@ -1634,7 +1637,7 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
     const int32_t nh = sqlen(it.sn, c, &c->eh_tail[sc], a.q.hcap);
     if (T.lead()) {
         c->eq_tail[sx] = 0; c->eh_tail[sx] = 0;
-        c->st_rounds += 1;
+        ph_count(PH_ROUNDS);
     }
     const int32_t ep = it.ep;
     WaveBuf bq = wave_buf(0), bt = wave_buf(1), bchg = wave_buf(2);
@@ -2021,7 +2024,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                 force = false;
                 const unsigned long long t0 = ph_start();
                 run_step(a, it, pc, grid_team(), acc);
-                if (gtid() == 0) c->st_grid_steps += 1;
+                ph_count(PH_GSTEPS);
                 gbar(a.bar);
                 it.sn = take_snap(c);
                 ph_stop(c, pc.step, t0);
@@ -2036,7 +2039,7 @@ __device__ __forceinline__ int run_iterations(const KArgs &a, int ins, int max_i
                     for (;;) {
                         if (!block_local_ok(a, it, pc, T)) { fg = true; break; }
                         run_step(a, it, pc, T, acc);
-                        if (threadIdx.x == 0) c->st_local_steps += 1;
+                        ph_count(PH_LSTEPS);
                         __syncthreads();
                         it.sn = take_snap(c);
                         pc = next_pc(a, it, pc);
@@ -2495,6 +2498,7 @@ __device__ __forceinline__ void run_program(const KArgs &a) {
             break;
         }
     }
+    ph_flush(c);  // phases of a last batch that ended before its flush
     if (gtid() == 0) {
         c->epoch = ep;
         pd->stop = j;
@@ -2611,6 +2615,7 @@ __device__ __forceinline__ void run_server(const KArgs &a) {
         if (gtid() == 0) __hip_atomic_store(&h->head, j + gn, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         j += gn;
     }
+    ph_flush(c);
     if (gtid() == 0) {
         c->epoch = ep;
         h->exit_at = j;
