@@ -337,6 +337,55 @@ def test_vertex_ops(cm, dev, oracle_mod, mode):
         check_state(g, ref, "after rejected vertex insert")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_uplists_across_batches(cm, dev, oracle_mod, mode):
+    """Long lists keep up-lists (neighbours at or above their owner's core)
+    across batches; every change that could add a neighbour at or above a
+    vertex's core outside its up-list invalidates it: a neighbour rising to
+    that core, the vertex's own core falling, an edge of it deleted, its list
+    moved, a fresh decomposition.  Many degree-weighted batches on one handle
+    with lists split into 8-slot chunks (so most lists keep up-lists), vertex
+    insertions and hub deletions, and a second decomposition between them:
+    cores and SD equal the oracle's after every step."""
+    rng = graphgen.rng_for("uplists")
+    n = 3000
+    s, d = graphgen.chung_lu_graph(n, 15_000, 2.1, 400.0, rng)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    es = graphgen.EdgeSet(s, d)
+    nid = n
+    with new_graph(cm, n, s, d, dev, mode=mode, small_degree=4, large_degree=8, chunk=8) as g:
+        for step in range(24):
+            if step % 2 == 0:
+                a, b = graphgen.weighted_non_edges(int(rng.integers(20, 400)), es, rng)
+                g.insert_edges(_t(a, dev), _t(b, dev))
+                ref.insert_edges(a, b)
+                es.insert(a, b)
+            else:
+                a, b = graphgen.existing_edges(int(rng.integers(20, 300)), es, rng)
+                g.delete_edges(_t(a, dev), _t(b, dev))
+                ref.delete_edges(a, b)
+                es.delete(a, b)
+            check_state(g, ref, f"step {step}")
+            if step == 7:
+                degs = graphgen.power_law_degrees(30, 1, 40, 2.1, rng)
+                off, nb = graphgen.vertex_insert_payload(nid, 30, degs, es, rng)
+                g.insert_vertices(_t(off, dev), _t(nb, dev))
+                ref.insert_vertices(off, nb)
+                nid += 30
+                es = graphgen.EdgeSet(*ref.edges())
+                check_state(g, ref, f"step {step} vertex insert")
+            if step == 13:
+                deg = np.bincount(np.concatenate(ref.edges()).astype(np.int64), minlength=nid)
+                hubs = np.argsort(-deg)[:12].astype(np.int32)
+                g.delete_vertices(_t(hubs, dev))
+                ref.delete_vertices(hubs)
+                es = graphgen.EdgeSet(*ref.edges())
+                check_state(g, ref, f"step {step} hub delete")
+            if step == 17:
+                g.decompose()
+                check_state(g, ref, f"step {step} decompose again")
+
+
 def test_growth_and_spill(cm, dev, oracle_mod):
     """Lists outgrow their slack many times (spill blocks, pool repack)."""
     rng = graphgen.rng_for("grow")
