@@ -43,14 +43,14 @@ SPACE = {
     "partition_rounds": [1, 2, 3],
     "local_items": [128, 512, 2048],
     "local_work": [1024, 4096, 16384],
-    "local_edges": [2048, 8192, 32768],
+    "local_edges": [512, 2048, 8192],
     "async_steps": [0, 1],
     "expand_mode": [1, 2, 3, 4],
 }
 ORDER = ["async_steps", "expand_mode", "large_degree", "chunk", "small_degree", "blocks_per_cu", "partition_rounds",
          "local_items", "local_work", "local_edges"]
 DEFAULTS = {"blocks_per_cu": 1, "chunk": 256, "large_degree": 256, "small_degree": 4,
-            "partition_rounds": 2, "local_items": 128, "local_work": 16384, "local_edges": 8192,
+            "partition_rounds": 2, "local_items": 128, "local_work": 16384, "local_edges": 2048,
             "async_steps": 0, "expand_mode": 4}
 
 DEFAULT_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")

@@ -1056,7 +1056,7 @@ int cm_create(const cm_config *cfg, cm_graph **out) {
         g->tune.large_deg = g->cfg.large_degree > 0 ? g->cfg.large_degree : 256;
         g->tune.chunk = g->cfg.chunk > 0 ? g->cfg.chunk : 256;
         g->tune.rounds = g->cfg.partition_rounds > 0 ? std::min(g->cfg.partition_rounds, 8) : 2;
-        g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 8192;
+        g->tune.local_edges = g->cfg.local_edges > 0 ? g->cfg.local_edges : 2048;
         g->tune.local_items = g->cfg.local_items > 0 ? g->cfg.local_items : 128;
         g->tune.local_work = g->cfg.local_work > 0 ? g->cfg.local_work : 16384;
         g->tune.async_steps = g->cfg.async_steps ? 1 : 0;
