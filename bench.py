@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # summaries and commands are under profiles/).
 TRAFFIC = {
     "rmat22-stream": {"kernel": "k_program", "bytes_per_launch": 1713.1e9,
-                      "sources_sha256": "ed58cfadccad022f433e14bd9f898f4931d1960d6dbb556e83fdb2055db8e708"},
+                      "sources_sha256": "c07d29e29f74380a43c775c316b93237f0afe07f660d5633858265dc3ecfa856"},
 }
 KERNEL_SOURCES = ["cm_internal.h", "cm_kernels.hip", "cm_phases.h", "cm_walk.h"]
 

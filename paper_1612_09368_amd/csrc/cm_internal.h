@@ -160,15 +160,15 @@ struct DevGraph {
     unsigned long long *claim;  // [n_cap] selection claim key (smaller wins)
     int32_t *bmark;      // [n_cap] batch stamp (validation scans, reservation)
     int32_t *gain;       // [n_cap] edges a batch adds to the list (zero between uses)
-    // Supporter lists of an insertion iteration (null when off): while the
+    // Supporter runs of an insertion iteration (null when off): while the
     // expansion counts a candidate's CSD it also writes the neighbours that
-    // are level-k candidates-to-be (core == k, SD > k), compacted, into the
-    // candidate's own slot range of `sub`; the eviction then walks those
-    // alone instead of the whole list.  A list of up to `large` slots keeps
-    // its count in slen; a longer one is compacted per chunk, each chunk's
-    // entries ending at a negative entry when fewer than the chunk's slots.
+    // are level-k candidates-to-be (core == k, SD > k), compacted from the
+    // start of the candidate's own slot range of `sub`; the eviction then
+    // walks those alone instead of the whole list.  slen = the run's length
+    // (zeroed when the candidate is claimed; the chunks of a long list
+    // reserve their slots in it with atomics).
     int32_t *sub;        // [pool_size] same slot ranges as nbr
-    int32_t *slen;       // [n_cap] supporters written for a list of up to `large` slots
+    int32_t *slen;       // [n_cap] length of the candidate's supporter run
     // Up-lists of long lists (null when off), kept across iterations and
     // batches: per chunk of a list split into chunks, the neighbours whose
     // core was at least the owner's when the list was last scanned whole,
