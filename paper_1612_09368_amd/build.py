@@ -11,6 +11,9 @@ LIB = os.path.join(HERE, "libcoremaint.so")
 SOURCES = ["cm_kernels.hip", "cm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# roctx ranges of the host-side phases (rocprofiler-sdk's marker library)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed fp32 instructions
@@ -43,7 +46,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("\n".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, *LINK]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

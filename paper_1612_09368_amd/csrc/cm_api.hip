@@ -12,12 +12,25 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/coremaint.h"
 #include "cm_launch.h"
 
 using namespace cm;
 
 namespace {
+
+// A named host-side range of the library's work (validation, reservation,
+// maintenance launches, compaction, the public calls), shown by
+// `rocprofv3 --marker-trace`; without a profiler a push / pop is a call
+// into a no-op table.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 struct DevBuf {
     void *p = nullptr;
@@ -460,6 +473,7 @@ double now_ms() {
 // lists keep their order, tombstones are dropped.  extra = slots to add to
 // the pool beyond the packed size.
 void repack(cm_graph *g, int64_t extra) {
+    Range range("coremaint.repack");
     hipStream_t st = g->stream;
     KArgs a = make_args(g);
     int32_t *cnt = g->g.gain;  // gain is zero between batches; used as scratch here
@@ -561,6 +575,7 @@ int64_t alg_bytes(const ProgOut &o) {
 // the number of valid items; in strict mode throws on the first bad item.
 int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *first_bad,
                  int cur, cm_batch_stats *stats, bool packed) {
+    Range range("coremaint.validate");
     hipStream_t st = g->stream;
     g->bstamp += 2;
     HIPCHK(ctl_batch_reset(g->ctl, cur, st));
@@ -591,6 +606,7 @@ int64_t validate(cm_graph *g, int64_t s, bool inserting, bool strict, int64_t *f
 // mutation: lists that cannot take their new edges move to spill blocks;
 // if the pool is full it is repacked into a larger one and the step redone.
 void reserve(cm_graph *g, int cur) {
+    Range range("coremaint.reserve");
     hipStream_t st = g->stream;
     for (int attempt = 0; attempt < 4; ++attempt) {
         KArgs a = make_args(g);
@@ -681,6 +697,7 @@ void run_plain(cm_graph *g, KArgs a, double &kms, int &launches) {
 
 // Run the iterations of a validated batch (list `cur`) to completion.
 void run_maintenance(cm_graph *g, bool inserting, cm_batch_stats *stats) {
+    Range range("coremaint.maintain");
     hipStream_t st = g->stream;
     KArgs a = make_args(g);
     a.inserting = inserting ? 1 : 0;
@@ -751,6 +768,7 @@ int64_t edge_batch(cm_graph *g, int64_t s, bool inserting, cm_batch_stats *stats
     }
     run_maintenance(g, inserting, stats);
     if (!inserting) {
+        Range range("coremaint.compact");
         KArgs c = make_args(g);
         HIPCHK(delete_compact(c, g->grid_reg, st));
     }
@@ -1157,6 +1175,7 @@ void cm_destroy(cm_graph *g) {
 
 int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                   int on_device) {
+    Range range("cm_load_graph");
     if (!g || n < 0 || m < 0 || (m > 0 && (!src || !dst))) return CM_E_ARG;
     if (g->poisoned) return CM_E_DEVICE;
     if (g->serving) return CM_E_STATE;
@@ -1255,6 +1274,7 @@ int cm_load_graph(cm_graph *g, int32_t n, int64_t m, const int32_t *src, const i
 }
 
 int cm_core_decompose(cm_graph *g, cm_batch_stats *stats) {
+    Range range("cm_core_decompose");
     if (!g) return CM_E_ARG;
     double t0 = now_ms();
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -1295,6 +1315,7 @@ int cm_core_decompose(cm_graph *g, cm_batch_stats *stats) {
 
 static int edge_call(cm_graph *g, int64_t s, const int32_t *src, const int32_t *dst, int on_device,
                      cm_batch_stats *stats, bool inserting) {
+    Range range(inserting ? "cm_insert_edges" : "cm_delete_edges");
     if (!g) return CM_E_ARG;
     double t0 = now_ms();
     if (stats) {
@@ -1409,6 +1430,7 @@ int cm_update_edges_noalloc(cm_graph *g, int32_t kind, int64_t s, const int32_t 
 
 int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t *nbrs, int on_device,
                        int32_t *first_new_id, cm_batch_stats *stats) {
+    Range range("cm_insert_vertices");
     if (!g) return CM_E_ARG;
     double t0 = now_ms();
     if (stats) {
@@ -1517,6 +1539,7 @@ int cm_insert_vertices(cm_graph *g, int32_t c, const int64_t *off, const int32_t
 }
 
 int cm_delete_vertices(cm_graph *g, int32_t c, const int32_t *ids, int on_device, cm_batch_stats *stats) {
+    Range range("cm_delete_vertices");
     if (!g) return CM_E_ARG;
     double t0 = now_ms();
     if (stats) {
@@ -1871,6 +1894,7 @@ int64_t serve_bytes(int32_t kind, int64_t items) {
 extern "C" {
 
 int cm_serve_start(cm_graph *g, const cm_serve_config *cfg) {
+    Range range("cm_serve_start");
     if (!g) return CM_E_ARG;
     try {
         require_ready(g, true);
@@ -2065,6 +2089,7 @@ int cm_serve_result(cm_graph *g, int64_t ticket, cm_batch_stats *out) {
 }
 
 int cm_serve_stop(cm_graph *g) {
+    Range range("cm_serve_stop");
     if (!g) return CM_E_ARG;
     if (!g->serving) return CM_OK;
     try {
@@ -2130,6 +2155,7 @@ void fnv_words(uint64_t &h, const int32_t *p, size_t n) {
 extern "C" {
 
 int cm_snapshot(cm_graph *g, const char *path) {
+    Range range("cm_snapshot");
     if (!g || !path) return CM_E_ARG;
     try {
         require_ready(g, true);
@@ -2193,6 +2219,7 @@ int cm_snapshot(cm_graph *g, const char *path) {
 }
 
 int cm_restore(const cm_config *cfg, const char *path, cm_graph **out) {
+    Range range("cm_restore");
     if (!path || !out) return CM_E_ARG;
     *out = nullptr;
     FILE *f = std::fopen(path, "rb");
@@ -2372,6 +2399,7 @@ int cm_export_edges(cm_graph *g, int32_t *src, int32_t *dst, int64_t cap, int64_
 int cm_run_batches(cm_graph *g, int32_t nb, const int32_t *kinds, const int64_t *offsets,
                    const int32_t *src, const int32_t *dst, const int32_t *sub, int32_t nsub,
                    int on_device, cm_batch_stats *results, int32_t *sub_status) {
+    Range range("cm_run_batches");
     if (!g || nb < 0 || nb > (1 << 28) || (nb > 0 && (!kinds || !offsets))) return CM_E_ARG;
     if (nsub < 0 || (sub && nsub == 0)) return CM_E_ARG;
     double t0 = now_ms();

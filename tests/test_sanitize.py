@@ -59,6 +59,7 @@ def test_abi_host_paths_under_sanitizers(tmp_path):
     main = tmp_path / "abi_main.o"
     _run([HIPCC, *common, *SAN, "-c", os.path.join(HERE, "host", "abi_sanitize_main.cpp"), "-o", str(main)])
     exe = tmp_path / "abi_san"
-    _run([HIPCC, "--offload-arch=gfx950", *SAN, str(main), str(api), str(kern), "-o", str(exe)])
+    _run([HIPCC, "--offload-arch=gfx950", *SAN, str(main), str(api), str(kern), "-o", str(exe),
+          "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     out = _run([str(exe), str(tmp_path)], env=ENV, timeout=300)
     assert "abi: ok" in out.stdout
