@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 # summaries and commands are under profiles/).
 TRAFFIC = {
     "rmat22-stream": {"kernel": "k_program", "bytes_per_launch": 1713.1e9,
-                      "sources_sha256": "c07d29e29f74380a43c775c316b93237f0afe07f660d5633858265dc3ecfa856"},
+                      "sources_sha256": "aed7dfe34a332f1461fb7b362f0ee7863f563b3590e1fbdc521900783b80ce17"},
 }
 KERNEL_SOURCES = ["cm_internal.h", "cm_kernels.hip", "cm_phases.h", "cm_walk.h"]
 

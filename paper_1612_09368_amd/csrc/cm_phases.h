@@ -953,7 +953,7 @@ __device__ __forceinline__ void star_apply_delete(const KArgs &a, const Iter &it
     Ctl *c = a.ctl;
     const StarCtx &sc = it.sc;
     const DevGraph &g = a.g;
-    const int32_t mstamp = (int32_t)star_mstamp(it, a);
+    const uint32_t mstamp = star_mstamp(it, a);
     // decide: a pending star that lost no claim leaves in this iteration
     // (always on the whole grid: star steps never run inside one workgroup)
     const int32_t *R = a.b.rem[it.cur];
@@ -997,7 +997,7 @@ __device__ __forceinline__ void star_apply_delete(const KArgs &a, const Iter &it
 }
 
 // Deletion stars of this iteration are dead once their edges are gone.
-__device__ __forceinline__ void star_kill(const KArgs &a, const Iter &it, const Team &T) {
+__device__ __forceinline__ void star_kill(const KArgs &a, const Iter &, const Team &T) {
     const int32_t n = qlen(&a.ctl->sel_count, a.b.cap);
     for (int32_t idx = T.rank; idx < n; idx += T.size) {
         const int32_t x = a.b.sel[idx];
@@ -1129,7 +1129,6 @@ __device__ __forceinline__ void expand_async(const KArgs &a, const Iter &it, Acc
 
 // Asynchronous eviction (Algorithm 4 cascade) of the vertices in queue 1.
 __device__ __forceinline__ void evict_async(const KArgs &a, const Iter &it, Acc &acc) {
-    Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     const int32_t ep = it.ep;
     ph_count(PH_ROUNDS);
@@ -2240,7 +2239,6 @@ __device__ __forceinline__ void prog_refill(const KArgs &a, int32_t ep, int32_t 
 // smallest index wins) and sum the list lengths of the valid ones.
 __device__ __forceinline__ void vdel_check_ids(const KArgs &a, const ProgDesc *pd, const int32_t *ids, int32_t s,
                                                int32_t n_ids, const Team &T) {
-    Ctl *c = a.ctl;
     const DevGraph &g = a.g;
     for (int32_t i = T.rank; i < s; i += T.size) {
         int32_t x = ids[i];
