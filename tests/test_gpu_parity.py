@@ -60,6 +60,7 @@ def check_state(g, ref, tag=""):
 FORMS = {
     "rounds": {},
     "async": {"async_steps": True},
+    "pruned": {"expand_mode": 1},
     "fullscan": {"expand_mode": 2},
     "sublists": {"expand_mode": 3},
 }
@@ -69,9 +70,10 @@ FORM = {}
 @pytest.fixture(autouse=True, params=list(FORMS))
 def _cascade_form(request):
     """Every parity test runs with round-synchronous cascades (default
-    expansion: supporter lists for the eviction and up-lists of long lists),
-    with asynchronous (work-queue) cascades, with the one-pass expansion
-    alone, and with supporter lists but no up-lists."""
+    expansion: supporter runs for the eviction and up-lists of long lists),
+    with asynchronous (work-queue) cascades, with Algorithm 3's pruned
+    two-pass expansion, with the one-pass expansion alone, and with
+    supporter runs but no up-lists."""
     global FORM
     FORM = FORMS[request.param]
     yield
