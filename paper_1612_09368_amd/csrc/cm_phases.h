@@ -153,12 +153,20 @@ __device__ __forceinline__ void mark_scan(const KArgs &a, const BatchCtx &bc, in
 // probing the batch hash.
 constexpr int32_t VAL_SHORT = 32;
 
-// Absolute slot of `target` in x's list, or -1.
+// Absolute slot of `target` in x's list, or -1.  Eight entries are loaded
+// per step before any is compared, so a lane has eight reads in flight.
 __device__ __forceinline__ int64_t find_in_list(const DevGraph &g, int32_t x, int32_t target) {
     const int64_t o = g.off[x];
     const int32_t L = g.len[x];
-    for (int32_t s = 0; s < L; ++s)
-        if (g.nbr[o + s] == target) return o + s;
+    const int32_t *p = g.nbr + o;
+    for (int32_t s = 0; s < L; s += 8) {
+        int32_t e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = s + u < L ? p[s + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e[u] == target) return o + s + u;
+    }
     return -1;
 }
 
@@ -199,35 +207,62 @@ __device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc,
 
 // V3: locate scan.  Each (vertex, chunk) item is read by one wave; every
 // live neighbour probes the batch hash.  Insertion: a hit means the edge
-// exists.  Deletion: a hit records the slot of the entry.
+// exists.  Deletion: a hit records the slot of the entry.  A wave loads
+// SCAN_STEPS steps of its chunk, then sends their first probes, before it
+// resolves any, and fetches its next item while it works on this one: the
+// scan is bound by the latency of these dependent reads.
+constexpr int SCAN_STEPS = 4;
 __device__ __forceinline__ void val_scan(const KArgs &a, const BatchCtx &bc, const Team &T) {
     const uint32_t mask = (uint32_t)bc.hcap - 1u;
     const int32_t n = qlen(&a.ctl->scan_tail, a.b.scap);
-    for_chunks(T, a.b.scanq, n, a.g, a.t.chunk,
-               [&](int32_t x, int32_t lo, int32_t hi, int32_t) {
-                   const int64_t base = a.g.off[x];
-                   wave_walk(a.g, x, lo, hi, [&](int32_t w, int32_t slot) {
-                       if (w < 0) return;
-                       unsigned long long key = edge_key(x, w);
-                       uint32_t h = hash_key(key) & mask;
-                       for (uint32_t probe = 0; probe <= mask; ++probe) {
-                           unsigned long long k2 = a.b.hkey[h];
-                           if (k2 == EMPTY_KEY) break;
-                           if (k2 == key) {
-                               int32_t i = a.b.hval[h];
-                               if (bc.inserting) {
-                                   a.b.err[i] = ST_EXISTS;
-                               } else if (x == a.b.eu[i]) {
-                                   a.b.su[i] = base + slot;
-                               } else {
-                                   a.b.sv[i] = base + slot;
-                               }
-                               break;
-                           }
-                           h = (h + 1u) & mask;
-                       }
-                   });
-               });
+    const int32_t chunk = a.t.chunk;
+    int32_t j = T.wave();
+    int64_t item = j < n ? a.b.scanq[j] : 0;
+    while (j < n) {
+        const int32_t jn = j + T.nwaves();
+        const int64_t next = jn < n ? a.b.scanq[jn] : 0;
+        const int32_t x = item_v(item);
+        const int32_t L = a.g.len[x];
+        const int32_t lo = item_c(item) * chunk;
+        const int32_t hi = lo + chunk < L ? lo + chunk : L;
+        const int64_t base = a.g.off[x];
+        const int32_t *p = a.g.nbr + base;
+        for (int32_t s0 = lo; s0 < hi; s0 += SCAN_STEPS * WAVE) {
+            int32_t w[SCAN_STEPS];
+            unsigned long long k2[SCAN_STEPS];
+            uint32_t h[SCAN_STEPS];
+#pragma unroll
+            for (int u = 0; u < SCAN_STEPS; ++u) {
+                const int32_t i = s0 + u * WAVE + lane();
+                w[u] = i < hi ? p[i] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < SCAN_STEPS; ++u) {
+                h[u] = hash_key(edge_key(x, w[u])) & mask;
+                k2[u] = w[u] >= 0 ? a.b.hkey[h[u]] : EMPTY_KEY;
+            }
+#pragma unroll
+            for (int u = 0; u < SCAN_STEPS; ++u) {
+                const unsigned long long key = edge_key(x, w[u]);
+                uint32_t hh = h[u];
+                unsigned long long kk = k2[u];
+                for (uint32_t probe = 0; probe <= mask && kk != EMPTY_KEY; ++probe) {
+                    if (kk == key) {
+                        const int32_t i = a.b.hval[hh];
+                        const int64_t slot = base + s0 + u * WAVE + lane();
+                        if (bc.inserting) a.b.err[i] = ST_EXISTS;
+                        else if (x == a.b.eu[i]) a.b.su[i] = slot;
+                        else a.b.sv[i] = slot;
+                        break;
+                    }
+                    hh = (hh + 1u) & mask;
+                    kk = a.b.hkey[hh];
+                }
+            }
+        }
+        j = jn;
+        item = next;
+    }
 }
 
 // V4: missing edges, smallest invalid index, emit valid item indices into
@@ -1640,9 +1675,10 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
     }
     const int32_t ep = it.ep;
     WaveBuf bq = wave_buf(0), bt = wave_buf(1), bchg = wave_buf(2);
-    auto body = [&](int32_t w, int32_t k) {
+    // cw = core[w]: cores do not change during a peel round
+    auto body_c = [&](int32_t w, int32_t cw, int32_t k) {
         bool first = false, fire = false;
-        if (w >= 0 && g.core[w] == k && g.stamp[w] != ep) {
+        if (w >= 0 && cw == k && g.stamp[w] != ep) {
             int32_t old = atomicAdd(&g.dec[w], 1);
             first = old == 0;
             fire = g.mcd[w] - old - 1 == k - 1;
@@ -1652,6 +1688,7 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         push_vertex_wb(a, bq, a.q.eq[bn], &c->eq_tail[sn], a.q.eh[bn], &c->eh_tail[sn], w, fire);
         push_vertex_wb(a, bchg, a.q.chg, &c->chg_count, a.q.chh, &c->chh_count, w, fire);
     };
+    auto body = [&](int32_t w, int32_t k) { body_c(w, w >= 0 ? g.core[w] : -1, k); };
     acc.scanned += for_vertex_slots(T, a.q.eq[bc], nq, g, a.t.large_deg, body);
     // a long list with a valid up-list is read through it: the neighbours at
     // the peeled vertex's core are all in its up-set
@@ -1660,7 +1697,8 @@ __device__ __forceinline__ void peel_round(const KArgs &a, const Iter &it, int r
         const int32_t ub = a.t.uplists ? g.ubl[x] : -1;
         int32_t seen = hi - lo;
         if (ub >= 0) seen = walk_chunk_up(g, x, lo, hi, ub, [&](int32_t w) { body(w, k); });
-        else wave_walk(g, x, lo, hi, [&](int32_t w, int32_t) { body(w, k); });
+        else wave_walk_pre(g, x, lo, hi, [&](int32_t w) { return g.core[w]; },
+                           [&](int32_t w, int32_t cw) { body_c(w, cw, k); });
         if (lane() == 0) acc.scanned += seen;
     });
     wb_flush(bq, a.q.eq[bn], a.q.vcap, &c->eq_tail[sn], &c->overflow);
@@ -1755,9 +1793,8 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
     // Only a neighbour at the level the moved vertex crossed (its new core
     // on insertion, its new core + 1 on deletion) may need a delta, so the
     // moved-this-iteration stamp is gathered for those alone.
-    auto nb = [&](int32_t w, int32_t cv) -> int32_t {
+    auto nb_c = [&](int32_t w, int32_t cw, int32_t cv) -> int32_t {
         if (w < 0) return 0;
-        const int32_t cw = g.core[w];
         if (cw == (ins ? cv : cv + 1) && g.chg[w] != ep) {
             if (ins) {
                 atomicAdd(&g.mcd[w], 1);
@@ -1769,6 +1806,7 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
         }
         return cw >= cv ? 1 : 0;
     };
+    auto nb = [&](int32_t w, int32_t cv) -> int32_t { return w < 0 ? 0 : nb_c(w, g.core[w], cv); };
     const int32_t n = sqlen(it.sn, c, &c->chg_count, a.q.vcap);
     for_batches(T, a.q.chg, n, [&](int32_t v) {
         const int32_t L = v >= 0 ? g.len[v] : 0;
@@ -1796,7 +1834,9 @@ __device__ __forceinline__ void mcd_phase(const KArgs &a, const Iter &it, const 
     for_chunks(T, a.q.chh, nh, g, a.t.chunk, [&](int32_t v, int32_t lo, int32_t hi, int32_t) {
         int32_t cv = g.core[v];
         int32_t cnt = 0;
-        wave_walk(g, v, lo, hi, [&](int32_t w, int32_t) { cnt += nb(w, cv); });
+        // cores do not change during this step
+        wave_walk_pre(g, v, lo, hi, [&](int32_t w) { return g.core[w]; },
+                      [&](int32_t w, int32_t cw) { cnt += nb_c(w, cw, cv); });
         cnt = wave_sum(cnt);
         if (lane() == 0) { atomicAdd(&g.mcd[v], cnt); acc.scanned += hi - lo; }
     });

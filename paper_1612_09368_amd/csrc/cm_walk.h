@@ -177,6 +177,32 @@ __device__ __forceinline__ void wave_walk(const DevGraph &g, int32_t v, int32_t 
     }
 }
 
+// Wave walk of slots [lo, hi) of v, up to WALK_STEPS steps at a time: the
+// entries of those steps are loaded, then pre(w) gathers one word per entry
+// (it must read data that f does not change during the walk), before
+// f(w, pre(w)) runs step by step on every lane (w < 0: padding or a
+// tombstone).  The reads of a step then overlap those of the next ones: a
+// walk of a long list is bound by the latency of its dependent reads.
+constexpr int WALK_STEPS = 4;
+template <class P, class F>
+__device__ __forceinline__ void wave_walk_pre(const DevGraph &g, int32_t v, int32_t lo, int32_t hi, P &&pre,
+                                              F &&f) {
+    const int32_t *p = g.nbr + g.off[v];
+    for (int32_t s0 = lo; s0 < hi; s0 += WALK_STEPS * WAVE) {
+        int32_t w[WALK_STEPS], x[WALK_STEPS];
+#pragma unroll
+        for (int u = 0; u < WALK_STEPS; ++u) {
+            const int32_t i = s0 + u * WAVE + lane();
+            w[u] = i < hi ? p[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < WALK_STEPS; ++u) x[u] = w[u] >= 0 ? pre(w[u]) : -1;
+#pragma unroll
+        for (int u = 0; u < WALK_STEPS; ++u)
+            if (s0 + u * WAVE < hi) f(w[u], x[u]);
+    }
+}
+
 // Wave walk of chunk [lo, hi) of v through v's up-list (ub = ubl[v] >= 0):
 // the chunk's compacted up-list entries, built from slots [lo, min(hi, ub))
 // and ending at a negative entry when fewer, then the slots appended since
