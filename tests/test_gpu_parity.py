@@ -234,6 +234,66 @@ def test_skewed_batches(cm, dev, oracle_mod, kind):
     del ref, es
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_locate_scan_long_lists(cm, dev, oracle_mod, mode):
+    """Validation of edges between long lists (the locate scan reads whole
+    lists, several wave steps per item, and a ragged last item): deletions
+    whose partners sit anywhere in a hub's list, a missing edge and an
+    existing edge between two long lists, in strict and in filter mode."""
+    rng = np.random.default_rng(1612)
+    n = 4000
+    h0, h1, h2 = 0, 1, 2
+    # h0: 1037 neighbours besides h1 (four full items of 256 slots and a
+    # ragged one); h1: 600 besides h0; h2: 300, none of them h0
+    p0 = rng.choice(np.arange(3, n), 1037, replace=False)
+    p1 = rng.choice(np.arange(3, n), 600, replace=False)
+    p2 = rng.choice(np.arange(3, n), 300, replace=False)
+    rest = rng.integers(3, n, size=(6000, 2))
+    rest = rest[rest[:, 0] != rest[:, 1]]
+    s = np.concatenate([np.full(1037, h0), np.full(600, h1), [h0], np.full(300, h2), rest[:, 0]])
+    d = np.concatenate([p0, p1, [h1], p2, rest[:, 1]])
+    s, d = graphgen.EdgeSet(s.astype(np.int32), d.astype(np.int32)).edges()
+    s, d = s.astype(np.int32), d.astype(np.int32)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    with new_graph(cm, n, s, d, dev, mode=mode) as g:
+        check_state(g, ref, "load")
+        # an edge missing between two long lists fails the whole batch
+        a = np.array([h0, h2], np.int32)
+        b = np.array([p0[5], h0], np.int32)
+        st, stats = g.delete_edges(_t(a, dev), _t(b, dev), check=False)
+        assert st == cm.E_MISSING and stats.first_bad == 1, (st, stats.first_bad)
+        assert int(ref.validate(a, b, False)[1]) == cm.E_MISSING
+        # an existing edge between two long lists
+        a = np.array([p2[0], h1], np.int32)
+        b = np.array([h2 if p2[0] not in p0 else p1[0], h0], np.int32)
+        err = ref.validate(a, b, True)
+        assert int(err[1]) == cm.E_EXISTS
+        st, stats = g.insert_edges(_t(a, dev), _t(b, dev), check=False)
+        first = int(np.nonzero(err)[0][0])
+        assert st == int(err[first]) and stats.first_bad == first, (st, stats.first_bad, err)
+        check_state(g, ref, "after rejected batches")
+        # deletions spread over every item of h0's list and over h1's
+        a = np.concatenate([np.full(97, h0), np.full(41, h1), [h0]]).astype(np.int32)
+        b = np.concatenate([rng.choice(p0, 97, replace=False), rng.choice(p1, 41, replace=False),
+                            [h1]]).astype(np.int32)
+        g.delete_edges(_t(b, dev), _t(a, dev))
+        ref.delete_edges(b, a)
+        check_state(g, ref, "spread deletions")
+        s2, d2 = ref.edges()
+        s2, d2 = s2.astype(np.int32), d2.astype(np.int32)
+    # filter mode: invalid items between long lists are dropped, the rest applied
+    ref2 = oracle_mod.DynamicGraph(n, s2, d2)
+    with new_graph(cm, n, s2, d2, dev, mode=mode, strict=False) as g:
+        live0 = d2[s2 == h0]
+        a = np.array([h0, h0, h2, h0, h1], np.int32)
+        b = np.array([h1, live0[-1], h0, live0[0], p1[0]], np.int32)
+        st = g.delete_edges(_t(a, dev), _t(b, dev))
+        ref2.delete_edges(a, b, strict=False)
+        ok = int((oracle_mod.DynamicGraph(n, s2, d2).validate(a, b, False) == 0).sum())
+        assert st.applied == ok and st.dropped == a.size - ok, (st.applied, st.dropped, ok)
+        check_state(g, ref2, "filtered deletions")
+
+
 def test_insert_then_delete_restores(cm, dev, oracle_mod):
     rng = graphgen.rng_for("restore")
     n = 5000
