@@ -294,6 +294,57 @@ def test_locate_scan_long_lists(cm, dev, oracle_mod, mode):
         check_state(g, ref2, "filtered deletions")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_hub_lists_cross_levels(cm, dev, oracle_mod, mode):
+    """Vertices with long lists (257, 513, 700 and 1025 entries: several
+    chunks with ragged ends) change core in both directions: a 24-clique
+    holds four hubs padded with leaves, and deleting or re-inserting clique
+    edges moves every member between cores 23 and 22 (and lower), so the
+    peel, the SD recount and the expansion walk the hubs chunk by chunk."""
+    q = 24
+    hubs_len = [257, 513, 700, 1025]
+    clique = np.arange(q)
+    s, d = [], []
+    for i in range(q):
+        for j in range(i + 1, q):
+            s.append(i)
+            d.append(j)
+    nxt = q
+    for h, L in enumerate(hubs_len):
+        for _ in range(L - (q - 1)):
+            s.append(h)
+            d.append(nxt)
+            nxt += 1
+    # a ring through the leaves of hubs 2 and 3 gives them degree 2
+    ring = np.arange(q + hubs_len[0] + hubs_len[1] - 2 * (q - 1), nxt)
+    s.extend(ring[:-1].tolist())
+    d.extend(ring[1:].tolist())
+    n = nxt + 8
+    s = np.array(s, np.int32)
+    d = np.array(d, np.int32)
+    ref = oracle_mod.DynamicGraph(n, s, d)
+    steps = [
+        ("delete", [5], [6]),                      # one clique edge: every member 23 -> 22
+        ("insert", [5], [6]),                      # back to 23
+        ("delete", [0, 7, 9], [1, 8, 10]),         # a hub-hub edge and two more
+        ("delete", [2, 11], [3, 12]),
+        ("insert", [0, 2, 7], [1, 3, 8]),
+        ("insert", [9, 11], [10, 12]),
+        ("delete", [3, 3, 3], [20, 21, 22]),       # the longest hub loses three clique edges
+        ("insert", [3, 3, 3], [20, 21, 22]),
+    ]
+    with new_graph(cm, n, s, d, dev, mode=mode) as g:
+        check_state(g, ref, "load")
+        assert int(g.cores()[clique].min()) == q - 1
+        for i, (kind, a, b) in enumerate(steps):
+            a = np.array(a, np.int32)
+            b = np.array(b, np.int32)
+            (g.insert_edges if kind == "insert" else g.delete_edges)(_t(a, dev), _t(b, dev))
+            (ref.insert_edges if kind == "insert" else ref.delete_edges)(a, b)
+            check_state(g, ref, f"step {i} {kind}")
+        assert int(g.cores()[clique].min()) == q - 1
+
+
 def test_insert_then_delete_restores(cm, dev, oracle_mod):
     rng = graphgen.rng_for("restore")
     n = 5000
