@@ -209,25 +209,32 @@ __device__ __forceinline__ void val_dup_mark(const KArgs &a, const BatchCtx &bc,
 // live neighbour probes the batch hash.  Insertion: a hit means the edge
 // exists.  Deletion: a hit records the slot of the entry.  A wave loads
 // SCAN_STEPS steps of its chunk, then sends their first probes, before it
-// resolves any, and fetches its next item while it works on this one: the
-// scan is bound by the latency of these dependent reads.
+// resolves any, and loads its next item with this one's length and offset.
 constexpr int SCAN_STEPS = 4;
 __device__ __forceinline__ void val_scan(const KArgs &a, const BatchCtx &bc, const Team &T) {
     const uint32_t mask = (uint32_t)bc.hcap - 1u;
     const int32_t n = qlen(&a.ctl->scan_tail, a.b.scap);
     const int32_t chunk = a.t.chunk;
     int32_t j = T.wave();
-    int64_t item = j < n ? a.b.scanq[j] : 0;
+    if (j >= n) return;  // uniform over the wave
+    int64_t item = a.b.scanq[j];
     while (j < n) {
         const int32_t jn = j + T.nwaves();
-        const int64_t next = jn < n ? a.b.scanq[jn] : 0;
+        // the next item, the length and the offset are loaded together: the
+        // next item's load is unconditional (its index stays in range) and
+        // the item's walk is a do-while, so that no branch puts a wait
+        // between them
+        const int64_t next = a.b.scanq[jn < n ? jn : j];
         const int32_t x = item_v(item);
         const int32_t L = a.g.len[x];
+        const int64_t base = a.g.off[x];
         const int32_t lo = item_c(item) * chunk;
         const int32_t hi = lo + chunk < L ? lo + chunk : L;
-        const int64_t base = a.g.off[x];
         const int32_t *p = a.g.nbr + base;
-        for (int32_t s0 = lo; s0 < hi; s0 += SCAN_STEPS * WAVE) {
+        // every item holds slots (lo < hi); were one empty, its loads would
+        // all be masked off
+        int32_t s0 = lo;
+        do {
             int32_t w[SCAN_STEPS];
             unsigned long long k2[SCAN_STEPS];
             uint32_t h[SCAN_STEPS];
@@ -259,7 +266,8 @@ __device__ __forceinline__ void val_scan(const KArgs &a, const BatchCtx &bc, con
                     kk = a.b.hkey[hh];
                 }
             }
-        }
+            s0 += SCAN_STEPS * WAVE;
+        } while (s0 < hi);
         j = jn;
         item = next;
     }
